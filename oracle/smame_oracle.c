@@ -1,0 +1,503 @@
+/*
+ * Plain FP64 CPU oracle for the SMAME step of arXiv 2012.03525.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the library.  Single thread,
+ * built with -O2 -ffp-contract=off so every product and sum is rounded as
+ * written.
+ *
+ * What is computed, in the paper's order (Sec. 2):
+ *   1. ghost values of the level-n fields (boundary rules below);
+ *   2. rho^{n+1} everywhere from the simplified continuity update, Eq. (2.10),
+ *      with the centred gradient (2.12) and the 5/7-point Laplacian (2.13);
+ *   3. ghost values of rho^{n+1};
+ *   4. (rho u)^{n+1} everywhere from the simplified momentum update, Eq. (2.11),
+ *      plus the body force delta_t rho^{n+1} g (Sec. 2, after Table-1 text)
+ *      and, for two-phase flow, the surface-tension force -delta_t phi d mu;
+ *   5. u^{n+1} = (rho u)^{n+1} / rho^{n+1};
+ *   6. two-phase flow: Cahn-Hilliard equation (2.14) advanced by Heun's
+ *      second-order Runge-Kutta method with isotropic stencils, using u^n.
+ *
+ * Readings where the paper is silent (each listed with its reason in the
+ * design notes of the repository):
+ *   - the flux d_b(rho u_a u_b) is the centred difference of the per-node
+ *     product (conservative form);
+ *   - the pressure term d_a(rho c_s^2) is c_s^2 times the centred difference
+ *     of drho (the constant rho0 c_s^2 drops out of a difference);
+ *   - walls sit halfway between nodes: ghost drho = mirror value, ghost
+ *     velocity = 2 u_wall - mirror value; a symmetry plane mirrors every
+ *     field and flips the normal velocity; phi and mu are mirrored
+ *     (contact angle 90 degrees); the rules are applied to the level-n fields,
+ *     to rho^{n+1} and to every intermediate phase-field quantity;
+ *   - isotropic stencils are the D2Q9-weighted 9-point ones;
+ *   - Heun's method; both stages use u^n.
+ */
+#include "smame_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* padded grid: one ghost layer on every side of every active axis      */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int dim, nx, ny, nz;
+    int px, py, pz;   /* padded extents */
+    int oz;           /* 1 in 3D, 0 in 2D */
+} pgrid;
+
+static pgrid make_grid(const orc_params* p)
+{
+    pgrid g;
+    g.dim = p->dim;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nz = (p->dim == 3) ? p->nz : 1;
+    g.px = g.nx + 2;
+    g.py = g.ny + 2;
+    g.pz = (p->dim == 3) ? g.nz + 2 : 1;
+    g.oz = (p->dim == 3) ? 1 : 0;
+    return g;
+}
+
+/* padded index of node (i,j,k); i in [-1,nx], j in [-1,ny], k in [-1,nz] (3D) */
+static long P(const pgrid* g, int i, int j, int k)
+{
+    return ((long)(k + g->oz) * g->py + (j + 1)) * g->px + (i + 1);
+}
+
+/* dense index of interior node */
+static long D(const pgrid* g, int i, int j, int k)
+{
+    return ((long)k * g->ny + j) * g->nx + i;
+}
+
+/* Map a coordinate that may lie one layer outside [0,n) to its source node.
+ * *face is set to the face crossed (lo/hi) or -1. */
+static int map_axis(int i, int n, int bc_lo, int bc_hi, int face_lo, int* face)
+{
+    *face = -1;
+    if (i < 0) {
+        *face = face_lo;
+        return (bc_lo == ORC_PERIODIC) ? i + n : -1 - i;
+    }
+    if (i >= n) {
+        *face = face_lo + 1;
+        return (bc_hi == ORC_PERIODIC) ? i - n : 2 * n - 1 - i;
+    }
+    return i;
+}
+
+static int is_ghost(const pgrid* g, int i, int j, int k)
+{
+    if (i < 0 || i >= g->nx || j < 0 || j >= g->ny) return 1;
+    if (g->dim == 3 && (k < 0 || k >= g->nz)) return 1;
+    return 0;
+}
+
+/* Fill the ghost layer of a scalar field: periodic wrap or mirror. */
+static void fill_scalar(const orc_params* p, const pgrid* g, double* f)
+{
+    int kl = (g->dim == 3) ? -1 : 0, kh = (g->dim == 3) ? g->nz : 0;
+    for (int k = kl; k <= kh; ++k)
+        for (int j = -1; j <= g->ny; ++j)
+            for (int i = -1; i <= g->nx; ++i) {
+                if (!is_ghost(g, i, j, k)) continue;
+                int fx, fy, fz;
+                int si = map_axis(i, g->nx, p->bc[0], p->bc[1], 0, &fx);
+                int sj = map_axis(j, g->ny, p->bc[2], p->bc[3], 2, &fy);
+                int sk = (g->dim == 3) ? map_axis(k, g->nz, p->bc[4], p->bc[5], 4, &fz) : 0;
+                f[P(g, i, j, k)] = f[P(g, si, sj, sk)];
+            }
+}
+
+/* Velocity rule when a face is crossed: wall -> 2 u_w - u (every component),
+ * symmetry -> normal component negated. */
+static void apply_face(const orc_params* p, int face, double* uvw)
+{
+    if (face < 0) return;
+    int t = p->bc[face];
+    if (t == ORC_WALL) {
+        for (int c = 0; c < 3; ++c) uvw[c] = 2.0 * p->wall_u[face][c] - uvw[c];
+    } else if (t == ORC_SYMMETRY) {
+        int axis = face / 2;
+        uvw[axis] = -uvw[axis];
+    }
+}
+
+/* Fill ghost velocity (faces applied in the order x, y, z). */
+static void fill_velocity(const orc_params* p, const pgrid* g, double* u, double* v, double* w)
+{
+    int kl = (g->dim == 3) ? -1 : 0, kh = (g->dim == 3) ? g->nz : 0;
+    for (int k = kl; k <= kh; ++k)
+        for (int j = -1; j <= g->ny; ++j)
+            for (int i = -1; i <= g->nx; ++i) {
+                if (!is_ghost(g, i, j, k)) continue;
+                int fx, fy, fz = -1;
+                int si = map_axis(i, g->nx, p->bc[0], p->bc[1], 0, &fx);
+                int sj = map_axis(j, g->ny, p->bc[2], p->bc[3], 2, &fy);
+                int sk = (g->dim == 3) ? map_axis(k, g->nz, p->bc[4], p->bc[5], 4, &fz) : 0;
+                long s = P(g, si, sj, sk);
+                double q[3];
+                q[0] = u[s];
+                q[1] = v[s];
+                q[2] = (g->dim == 3) ? w[s] : 0.0;
+                apply_face(p, fx, q);
+                apply_face(p, fy, q);
+                if (g->dim == 3) apply_face(p, fz, q);
+                long d = P(g, i, j, k);
+                u[d] = q[0];
+                v[d] = q[1];
+                if (g->dim == 3) w[d] = q[2];
+            }
+}
+
+static void to_padded(const pgrid* g, const double* src, double* dst)
+{
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) dst[P(g, i, j, k)] = src[D(g, i, j, k)];
+}
+
+static int check_params(const orc_params* p)
+{
+    if (!p) return -1;
+    if (p->dim != 2 && p->dim != 3) return -1;
+    if (p->nx < 2 || p->ny < 2) return -1;
+    if (p->dim == 3 && p->nz < 2) return -1;
+    if (p->two_phase && p->dim != 2) return -1;
+    int nf = (p->dim == 3) ? 6 : 4;
+    for (int a = 0; a < nf; a += 2) {
+        int lo = p->bc[a], hi = p->bc[a + 1];
+        if ((lo == ORC_PERIODIC) != (hi == ORC_PERIODIC)) return -1;
+        if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return -1;
+    }
+    return 0;
+}
+
+/* offsets of the axis neighbours in the padded array */
+static void axis_strides(const pgrid* g, long s[3])
+{
+    s[0] = 1;
+    s[1] = g->px;
+    s[2] = (long)g->px * g->py;
+}
+
+/* ------------------------------------------------------------------ */
+/* isotropic 2D stencils (D2Q9 weights)                                 */
+/* ------------------------------------------------------------------ */
+/* gradient: [4 (f_E - f_W) + (f_NE + f_SE - f_NW - f_SW)] / (12 dx) for x */
+static double giso_x(const double* f, long c, long sy, double dx)
+{
+    double e = f[c + 1], wv = f[c - 1];
+    double ne = f[c + 1 + sy], se = f[c + 1 - sy], nw = f[c - 1 + sy], sw = f[c - 1 - sy];
+    return (4.0 * (e - wv) + (ne + se - nw - sw)) / (12.0 * dx);
+}
+static double giso_y(const double* f, long c, long sy, double dx)
+{
+    double n = f[c + sy], s = f[c - sy];
+    double ne = f[c + 1 + sy], nw = f[c - 1 + sy], se = f[c + 1 - sy], sw = f[c - 1 - sy];
+    return (4.0 * (n - s) + (ne + nw - se - sw)) / (12.0 * dx);
+}
+/* Laplacian: [4 (E + W + N + S) + (NE + NW + SE + SW) - 20 C] / (6 dx^2) */
+static double liso(const double* f, long c, long sy, double dx)
+{
+    double ax = f[c + 1] + f[c - 1] + f[c + sy] + f[c - sy];
+    double dg = f[c + 1 + sy] + f[c - 1 + sy] + f[c + 1 - sy] + f[c - 1 - sy];
+    return (4.0 * ax + dg - 20.0 * f[c]) / (6.0 * dx * dx);
+}
+
+/* mu = 4 a phi (phi^2 - 1) - kappa L_iso phi on interior nodes of padded arrays */
+static void chem_pot(const orc_params* p, const pgrid* g, const double* phi, double* mu)
+{
+    double a = 3.0 * p->sigma / (4.0 * p->width);
+    double kappa = 3.0 * p->sigma * p->width / 8.0;
+    long sy = g->px;
+    for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+            long c = P(g, i, j, 0);
+            double f = phi[c];
+            mu[c] = 4.0 * a * f * (f * f - 1.0) - kappa * liso(phi, c, sy, p->dx);
+        }
+}
+
+/* CHE right-hand side R = M L_iso mu - (u G_iso,x phi + v G_iso,y phi) */
+static double che_rhs(const orc_params* p, const pgrid* g, const double* phi, const double* mu,
+                      const double* u, const double* v, long c)
+{
+    long sy = g->px;
+    double diff = p->mobility * liso(mu, c, sy, p->dx);
+    double adv = u[c] * giso_x(phi, c, sy, p->dx) + v[c] * giso_y(phi, c, sy, p->dx);
+    return diff - adv;
+}
+
+/* ------------------------------------------------------------------ */
+/* one step                                                             */
+/* ------------------------------------------------------------------ */
+int orc_step(const orc_params* p, const double* force_x_row,
+             const double* drho, const double* u, const double* v,
+             const double* w, const double* phi,
+             double* out_drho, double* out_u, double* out_v,
+             double* out_w, double* out_phi)
+{
+    if (check_params(p)) return -1;
+    if (p->dim == 3 && (!w || !out_w)) return -1;
+    if (p->two_phase && (!phi || !out_phi)) return -1;
+    pgrid g = make_grid(p);
+    long np = (long)g.px * g.py * g.pz;
+    int nv = p->dim;
+    /* padded arrays: drho, u, v, w, m0, m1, m2, drho_new, phi, mu, phis, mus */
+    double* buf = (double*)calloc((size_t)np * 12, sizeof(double));
+    if (!buf) return -2;
+    double* r = buf;
+    double* uu[3] = {buf + np, buf + 2 * np, buf + 3 * np};
+    double* m[3] = {buf + 4 * np, buf + 5 * np, buf + 6 * np};
+    double* rn = buf + 7 * np;
+    double* ph = buf + 8 * np;
+    double* mu = buf + 9 * np;
+    double* phs = buf + 10 * np;
+    double* mus = buf + 11 * np;
+
+    /* 1. level-n fields with ghosts */
+    to_padded(&g, drho, r);
+    to_padded(&g, u, uu[0]);
+    to_padded(&g, v, uu[1]);
+    if (nv == 3) to_padded(&g, w, uu[2]);
+    fill_scalar(p, &g, r);
+    fill_velocity(p, &g, uu[0], uu[1], uu[2]);
+    for (long q = 0; q < np; ++q) {
+        double rho = p->rho0 + r[q];
+        for (int a = 0; a < nv; ++a) m[a][q] = rho * uu[a][q];
+    }
+    if (p->two_phase) {
+        to_padded(&g, phi, ph);
+        fill_scalar(p, &g, ph);
+        chem_pot(p, &g, ph, mu);
+        fill_scalar(p, &g, mu);
+    }
+
+    long st[3];
+    axis_strides(&g, st);
+    const double dx = p->dx, dt = p->dt, cs2 = p->cs * p->cs, nu = p->nu;
+
+    /* 2. continuity, Eq. (2.10):
+     *    rho' = rho - dt d_a(rho u_a) + 1/2 cs^2 dt^2 d_aa rho                */
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) {
+                long c = P(&g, i, j, k);
+                double div = 0.0, lap = 0.0;
+                for (int a = 0; a < nv; ++a) {
+                    div += (m[a][c + st[a]] - m[a][c - st[a]]) / (2.0 * dx);
+                    lap += (r[c + st[a]] + r[c - st[a]] - 2.0 * r[c]) / (dx * dx);
+                }
+                rn[c] = r[c] - dt * div + p->sat_rho * 0.5 * cs2 * dt * dt * lap;
+            }
+    /* 3. ghosts of rho^{n+1} */
+    fill_scalar(p, &g, rn);
+
+    /* 4-5. momentum, Eq. (2.11), then u = m / rho */
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) {
+                long c = P(&g, i, j, k);
+                long d = D(&g, i, j, k);
+                double rho_new = p->rho0 + rn[c];
+                double mn[3];
+                for (int a = 0; a < nv; ++a) {
+                    double flux = 0.0, visc = 0.0;
+                    for (int b = 0; b < nv; ++b) {
+                        long cp = c + st[b], cm = c - st[b];
+                        /* Pi_ab = rho u_a u_b + cs^2 drho delta_ab */
+                        double pip = m[a][cp] * uu[b][cp];
+                        double pim = m[a][cm] * uu[b][cm];
+                        if (a == b) {
+                            pip += cs2 * r[cp];
+                            pim += cs2 * r[cm];
+                        }
+                        flux += (pip - pim) / (2.0 * dx);
+                        visc += (m[a][cp] + m[a][cm] - 2.0 * m[a][c]) / (dx * dx);
+                    }
+                    long ap = c + st[a], am = c - st[a];
+                    double grad_new = (rn[ap] - rn[am]) / (2.0 * dx);
+                    double grad_old = (r[ap] - r[am]) / (2.0 * dx);
+                    double sat = (nu + 0.5 * cs2 * dt) * (grad_new - grad_old);
+                    double ga = p->g[a];
+                    if (a == 0 && force_x_row) ga += force_x_row[j];
+                    mn[a] = m[a][c] - dt * flux + nu * dt * visc - p->sat_mom * sat + dt * rho_new * ga;
+                }
+                if (p->two_phase) {
+                    long sy = g.px;
+                    mn[0] -= dt * ph[c] * giso_x(mu, c, sy, dx);
+                    mn[1] -= dt * ph[c] * giso_y(mu, c, sy, dx);
+                }
+                out_drho[d] = rn[c];
+                out_u[d] = mn[0] / rho_new;
+                out_v[d] = mn[1] / rho_new;
+                if (nv == 3) out_w[d] = mn[2] / rho_new;
+            }
+
+    /* 6. Cahn-Hilliard (2.14) by Heun's method with u^n */
+    if (p->two_phase) {
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) {
+                long c = P(&g, i, j, 0);
+                phs[c] = ph[c] + dt * che_rhs(p, &g, ph, mu, uu[0], uu[1], c);
+            }
+        fill_scalar(p, &g, phs);
+        chem_pot(p, &g, phs, mus);
+        fill_scalar(p, &g, mus);
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) {
+                long c = P(&g, i, j, 0);
+                double r2 = che_rhs(p, &g, phs, mus, uu[0], uu[1], c);
+                out_phi[D(&g, i, j, 0)] = 0.5 * (ph[c] + phs[c] + dt * r2);
+            }
+    }
+    free(buf);
+    return 0;
+}
+
+int orc_run(const orc_params* p, const double* force_x_row, long nsteps,
+            double* drho, double* u, double* v, double* w, double* phi)
+{
+    if (check_params(p)) return -1;
+    pgrid g = make_grid(p);
+    long n = (long)g.nx * g.ny * g.nz;
+    double* t = (double*)malloc((size_t)n * 5 * sizeof(double));
+    if (!t) return -2;
+    double *a[5] = {drho, u, v, w, phi};
+    double *b[5] = {t, t + n, t + 2 * n, t + 3 * n, t + 4 * n};
+    for (long s = 0; s < nsteps; ++s) {
+        int rc = orc_step(p, force_x_row, a[0], a[1], a[2], a[3], a[4],
+                          b[0], b[1], b[2], (p->dim == 3) ? b[3] : NULL,
+                          p->two_phase ? b[4] : NULL);
+        if (rc) {
+            free(t);
+            return rc;
+        }
+        for (int f = 0; f < 5; ++f) {
+            double* x = a[f];
+            a[f] = b[f];
+            b[f] = x;
+        }
+    }
+    /* the newest state is in a[]; copy it back into the caller arrays */
+    if (nsteps % 2 == 1) {
+        memcpy(drho, a[0], (size_t)n * sizeof(double));
+        memcpy(u, a[1], (size_t)n * sizeof(double));
+        memcpy(v, a[2], (size_t)n * sizeof(double));
+        if (p->dim == 3) memcpy(w, a[3], (size_t)n * sizeof(double));
+        if (p->two_phase) memcpy(phi, a[4], (size_t)n * sizeof(double));
+    }
+    free(t);
+    return 0;
+}
+
+int orc_chemical_potential(const orc_params* p, const double* phi, double* out)
+{
+    if (check_params(p) || p->dim != 2) return -1;
+    pgrid g = make_grid(p);
+    long np = (long)g.px * g.py;
+    double* ph = (double*)calloc((size_t)np * 2, sizeof(double));
+    if (!ph) return -2;
+    double* mu = ph + np;
+    to_padded(&g, phi, ph);
+    fill_scalar(p, &g, ph);
+    chem_pot(p, &g, ph, mu);
+    for (int j = 0; j < g.ny; ++j)
+        for (int i = 0; i < g.nx; ++i) out[D(&g, i, j, 0)] = mu[P(&g, i, j, 0)];
+    free(ph);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* diagnostics                                                          */
+/* ------------------------------------------------------------------ */
+int orc_diag(const orc_params* p, const double* drho, const double* u,
+             const double* v, const double* w, const double* phi,
+             const double* prev_u, const double* prev_v, const double* prev_w,
+             double* out)
+{
+    if (check_params(p)) return -1;
+    pgrid g = make_grid(p);
+    long np = (long)g.px * g.py * g.pz;
+    int nv = p->dim;
+    double* buf = (double*)calloc((size_t)np * 3, sizeof(double));
+    if (!buf) return -2;
+    double* uu[3] = {buf, buf + np, buf + 2 * np};
+    to_padded(&g, u, uu[0]);
+    to_padded(&g, v, uu[1]);
+    if (nv == 3) to_padded(&g, w, uu[2]);
+    fill_velocity(p, &g, uu[0], uu[1], uu[2]);
+    long st[3];
+    axis_strides(&g, st);
+    double dxd = (nv == 3) ? p->dx * p->dx * p->dx : p->dx * p->dx;
+    long n = (long)g.nx * g.ny * g.nz;
+    double mass = 0, mom[3] = {0, 0, 0}, ke = 0, dumax = 0, umax = 0, ens = 0;
+    double div2 = 0, divmax = 0, phisum = 0;
+    int bad = 0;
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) {
+                long c = P(&g, i, j, k);
+                long d = D(&g, i, j, k);
+                double rho = p->rho0 + drho[d];
+                double q2 = 0;
+                for (int a = 0; a < nv; ++a) {
+                    mom[a] += rho * uu[a][c];
+                    q2 += uu[a][c] * uu[a][c];
+                }
+                mass += drho[d];
+                ke += q2;
+                double mag = sqrt(q2);
+                if (mag > umax) umax = mag;
+                if (prev_u) {
+                    double pq = prev_u[d] * prev_u[d] + prev_v[d] * prev_v[d];
+                    if (nv == 3) pq += prev_w[d] * prev_w[d];
+                    double dm = fabs(mag - sqrt(pq));
+                    if (dm > dumax) dumax = dm;
+                }
+                /* centred derivatives d_b u_a */
+                double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+                for (int a = 0; a < nv; ++a)
+                    for (int b = 0; b < nv; ++b)
+                        du[a][b] = (uu[a][c + st[b]] - uu[a][c - st[b]]) / (2.0 * p->dx);
+                double om2;
+                if (nv == 2) {
+                    double oz = du[1][0] - du[0][1];
+                    om2 = oz * oz;
+                } else {
+                    double ox = du[2][1] - du[1][2];
+                    double oy = du[0][2] - du[2][0];
+                    double oz = du[1][0] - du[0][1];
+                    om2 = ox * ox + oy * oy + oz * oz;
+                }
+                ens += om2;
+                double dv = 0;
+                for (int a = 0; a < nv; ++a) dv += du[a][a];
+                div2 += dv * dv;
+                if (fabs(dv) > divmax) divmax = fabs(dv);
+                if (p->two_phase && phi) phisum += phi[d];
+                double vals[5] = {drho[d], u[d], v[d], (nv == 3) ? w[d] : 0.0,
+                                  (p->two_phase && phi) ? phi[d] : 0.0};
+                for (int f = 0; f < 5; ++f)
+                    if (!isfinite(vals[f])) bad = 1;
+            }
+    out[0] = mass * dxd;
+    out[1] = mom[0] * dxd;
+    out[2] = mom[1] * dxd;
+    out[3] = mom[2] * dxd;
+    out[4] = 0.5 * ke * dxd;
+    out[5] = dumax;
+    out[6] = umax;
+    out[7] = ens / (2.0 * (double)n);
+    out[8] = ke / (2.0 * (double)n);
+    out[9] = sqrt(div2 / (double)n);
+    out[10] = divmax;
+    out[11] = phisum;
+    out[12] = bad ? 1.0 : 0.0;
+    free(buf);
+    return 0;
+}
