@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark of the SMAME step on one MI355X.
+
+Default workload: 3D periodic Taylor-Green vortex, 256^3 nodes, FP32 with
+drho storage, u0 = 0.05, Re = 1600 on a 2 pi box, one SMAME step per
+"step" (the fused 2.5D z-march kernel).  Prints ONE JSON line with MLUPS,
+HBM GB/s against the 8 TB/s peak, the roofline record of the step kernel
+and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="tgv3d_256",
+                    choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024"])
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def workload(name, tile):
+    from paper_2012_03525_amd import acm, inputs
+    if name == "tgv3d_256":
+        n, u0 = 256, 0.05
+        nu = u0 * (n / (2 * math.pi)) / 1600.0
+        cfg = acm.make_config(3, n, n, n, nu=nu, precision="f32", tile=tile, graph_chunk=100)
+        st = inputs.tgv3d(n, u0)
+        meta = {"workload": "3D periodic Taylor-Green vortex 256^3, FP32 drho storage",
+                "grid": [n, n, n], "u0": u0, "Re": 1600, "nu_lattice": nu, "steps_of_case": 2000}
+        bytes_per_lup = 32  # read drho,u,v,w + write drho,u,v,w (FP32)
+        kernel = "step3d_kernel"
+    elif name == "tgv2d_64":
+        n = 64
+        cfg = acm.make_config(2, n, n, nu=0.01, precision="f64", tile=tile, graph_chunk=100)
+        st = inputs.tgv2d(n, 0.01, noise=1e-6)
+        meta = {"workload": "2D periodic Taylor-Green vortex 64^2, FP64", "grid": [n, n], "u0": 0.01, "nu": 0.01}
+        bytes_per_lup = 48
+        kernel = "step2d_kernel"
+    else:
+        n = 1024
+        wu = [[0.0] * 3 for _ in range(6)]
+        wu[2] = [-0.02, 0, 0]
+        wu[3] = [0.02, 0, 0]
+        cfg = acm.make_config(2, n, n, nu=0.1, precision="f32", bc=(0, 0, 1, 1, 0, 0), wall_u=wu,
+                              two_phase=True, sigma=0.01, width=4.0, mobility=0.02, tile=tile, graph_chunk=100)
+        st = inputs.drop_in_shear(n, n, 128.0, 4.0, 0.02)
+        meta = {"workload": "2D two-phase drop in simple shear 1024^2, FP32", "grid": [n, n], "R": 128, "W": 4,
+                "mobility": 0.02, "u_wall": 0.02, "nu": 0.1, "sigma": 0.01, "steps_of_case": 20000}
+        bytes_per_lup = 32
+        kernel = "twophase2d_kernel"
+    return cfg, st, meta, bytes_per_lup, kernel
+
+
+def cpu_baseline(name, cfg, st, budget_s):
+    """Time the FP64 CPU oracle (single thread) on a bounded sample of the
+    same workload: whole-grid steps until about budget_s seconds pass."""
+    import oracle
+    oracle.build(force=False)
+    p = oracle.Params(dim=cfg.dim, nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, dx=cfg.dx, dt=cfg.dt, nu=cfg.nu,
+                      cs=(cfg.cs if cfg.cs > 0 else cfg.dx / (cfg.dt * math.sqrt(3))),
+                      bc=list(cfg.bc), wall_u=[[cfg.wall_u[f][a] for a in range(3)] for f in range(6)],
+                      two_phase=bool(cfg.two_phase), sigma=cfg.sigma, width=cfg.width, mobility=cfg.mobility)
+    nodes = cfg.nx * cfg.ny * (cfg.nz if cfg.dim == 3 else 1)
+    t0 = time.perf_counter()
+    steps = 0
+    s = st
+    while True:
+        s = oracle.step(p, s)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 1000:
+            break
+    return {"value": nodes * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} whole-grid FP64 steps of the same workload ({nodes} nodes) in {el:.1f} s, "
+                      f"single thread, host has {os.cpu_count()} logical CPUs"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2012_03525_amd import acm
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    acm.lib()
+    cfg, st, meta, bpl, kname = workload(a.workload, a.tile)
+    solver = acm.Solver(cfg, st)
+    nodes = cfg.nx * cfg.ny * (cfg.nz if cfg.dim == 3 else 1)
+    print(f"[bench] {meta['workload']}: warmup {a.warmup}", file=sys.stderr, flush=True)
+    solver.run(a.warmup)
+    torch.cuda.synchronize()
+    stream = solver.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    solver.run(a.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / a.steps
+    mlups = nodes / (ms_per_step * 1e-3) / 1e6
+    gbs = bpl * nodes / (ms_per_step * 1e-3) / 1e9
+    d = solver.diagnostics()
+    print(f"[bench] {a.steps} steps: {gpu_ms:.2f} ms GPU, {wall*1e3:.2f} ms wall, {mlups:.0f} MLUPS, "
+          f"{gbs:.0f} GB/s, nonfinite={d['nonfinite']}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "MLUPS + HBM GB/s vs peak; learned-coarse vs plain-fine time at <=2% L2 err",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if cfg.precision == acm.F32 else "f64",
+        "data": "synthetic",
+        "config": dict(meta, parallelism="single GPU"),
+        "hbm_gbs_algorithmic": round(gbs, 1),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kname,
+            "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_lup": bpl,
+            "lups_per_launch": nodes,
+            "avg_launch_us": round(ms_per_step * 1e3, 3),
+        },
+        "state_check": {"nonfinite": d["nonfinite"], "ke": d["ke"], "step": d["step"]},
+    }
+    solver.close()
+    if not a.no_cpu:
+        print("[bench] CPU oracle baseline...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(a.workload, cfg, st, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

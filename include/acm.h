@@ -1,0 +1,165 @@
+/*
+ * acm.h - C ABI of the MI355X SMAME library (libacm.so).
+ *
+ * The library advances the simplified artificial-compressibility equations
+ * of Huang, arXiv 2012.03525 ("SMAME"):
+ *   continuity  (Eq. 2.10)  rho^{n+1} = rho^n - dt d_a(rho u_a)^n
+ *                                       + 1/2 cs^2 dt^2 d_aa rho^n
+ *   momentum    (Eq. 2.11)  (rho u_a)^{n+1} = (rho u_a)^n
+ *                             - dt d_b(rho u_a u_b + rho cs^2 delta_ab)^n
+ *                             + nu dt d_bb (rho u_a)^n
+ *                             - (nu + 1/2 cs^2 dt)(d_a rho^{n+1} - d_a rho^n)
+ *                             + dt rho^{n+1} g_a            (body force, Sec. 2)
+ *                             - dt phi d_a mu               (two-phase, Sec. 2)
+ * with centred second-order differences (Eqs. 2.12-2.13) on a collocated
+ * grid, and, for two-phase flow, the Cahn-Hilliard equation (Eq. 2.14)
+ * with mu = 4 a phi (phi^2 - 1) - kappa d_aa phi, a = 3 sigma/(4W),
+ * kappa = 3 sigma W/8, isotropic stencils and Heun's second-order
+ * Runge-Kutta step.
+ *
+ * Conventions shared by every entry point
+ * - Fields are caller-owned DEVICE arrays, structure of arrays, x fastest:
+ *   element (i, j, k) of an nx*ny*nz grid lives at (k*ny + j)*nx + i.
+ *   Density is stored as the deviation drho = rho - rho0 (rho0 = 1 in the
+ *   paper, Sec. 2 last paragraph), so FP32 storage keeps its O(Ma^2) signal.
+ * - Element type is double for ACM_F64 and float for ACM_F32.
+ * - Every call that launches work is asynchronous on the stream given at
+ *   initialisation (a hipStream_t passed as void*; NULL = the null stream),
+ *   except the calls documented as synchronising.
+ * - Errors are returned as acm_status; no exception crosses the ABI.
+ *   acm_last_error() returns a thread-local message for the last failure.
+ * - A handle is not thread-safe; use one handle per stream.
+ */
+#ifndef ACM_H
+#define ACM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ACM_OK = 0,
+    ACM_EINVAL = -1,      /* bad size, pointer, boundary pairing or parameter   */
+    ACM_EUNSTABLE = -2,   /* linear stability check failed (see acm_stability)  */
+    ACM_EHIP = -3,        /* a HIP runtime call failed                          */
+    ACM_ENONFINITE = -4,  /* diagnostics found a NaN/Inf (fields still returned)*/
+    ACM_ESTATE = -5       /* call not valid in the handle's current state       */
+} acm_status;
+
+/* Boundary type of a face.  Faces are ordered -x, +x, -y, +y, -z, +z.
+ * PERIODIC must be paired with PERIODIC on the opposite face.
+ * WALL is a no-slip (optionally moving) wall halfway between the last node
+ * and its ghost: ghost drho = mirror drho, ghost u = 2 u_wall - mirror u.
+ * SYMMETRY is a mirror plane halfway between nodes: every field mirrored,
+ * normal velocity negated.  For two-phase runs phi and mu are mirrored at
+ * both (contact angle 90 degrees, Sec. 2 wetting condition with cos = 0).
+ * The paper states the physical conditions (Sec. 3.2-3.6) but not their
+ * discretisation; the halfway placement is this library's reading. */
+typedef enum { ACM_BC_PERIODIC = 0, ACM_BC_WALL = 1, ACM_BC_SYMMETRY = 2 } acm_bc;
+
+typedef enum { ACM_F64 = 0, ACM_F32 = 1 } acm_precision;
+
+/* Problem statement (Sec. 2; Sec. 3 opening: dx = L/N_L, dt = T_c/N_t). */
+typedef struct acm_config {
+    int32_t dim;            /* 2 or 3                                         */
+    int32_t nx, ny, nz;     /* nodes per axis (nz ignored in 2D); each >= 4   */
+    double dx, dt;          /* grid spacing and time step                     */
+    double nu;              /* kinematic viscosity                            */
+    double cs;              /* sound speed; <= 0 selects dx/(dt sqrt 3)       */
+    double rho0;            /* reference density (1 in the paper)             */
+    double sat_rho;         /* multiplier of the continuity SAT (paper: 1)    */
+    double sat_mom;         /* multiplier of the momentum SAT (paper: 1)      */
+    double g[3];            /* uniform body force per unit mass               */
+    int32_t bc[6];          /* acm_bc per face                                */
+    double wall_u[6][3];    /* wall velocity per face (normal part must be 0) */
+    int32_t two_phase;      /* 1: Cahn-Hilliard coupling (2D only)            */
+    double sigma;           /* surface tension                                */
+    double width;           /* interface width W                              */
+    double mobility;        /* mobility M                                     */
+    int32_t precision;      /* acm_precision                                  */
+    int32_t allow_unstable; /* 1: skip the stability check                    */
+    int32_t graph_chunk;    /* steps per captured HIP graph (even); 0 = 64    */
+    int32_t tile;           /* kernel tile variant; 0 = default               */
+} acm_config;
+
+/* Device pointers of one complete state.  w is used in 3D only, phi in
+ * two-phase runs only; unused members may be NULL. */
+typedef struct acm_fields {
+    void* drho;
+    void* u;
+    void* v;
+    void* w;
+    void* phi;
+} acm_fields;
+
+/* Diagnostics of the newest state (all FP64, deterministic reductions).
+ * Sums over nodes use the cell volume dx^D where stated. */
+typedef struct acm_diag {
+    double mass;        /* sum(drho) dx^D                                      */
+    double mom[3];      /* sum(rho u_a) dx^D                                   */
+    double ke;          /* E_k = 1/2 sum |u|^2 dx^D (Sec. 3.1, not rho-weighted)*/
+    double dumax;       /* max | |u|^{n+1} - |u|^n | (steady test, Sec. 3.2)   */
+    double umax;        /* max |u|                                             */
+    double enstrophy;   /* (1/2S) sum |omega|^2 dS, centred vorticity (Eq. 3.4)*/
+    double energy;      /* (1/2S) sum |u|^2 dS (Eq. 3.4)                       */
+    double div_rms;     /* rms of the centred divergence of u                  */
+    double div_max;     /* max |centred divergence of u|                       */
+    double phi_sum;     /* sum(phi) (two-phase)                                */
+    int64_t step;       /* steps taken since init                              */
+    int32_t nonfinite;  /* 1 if any stored value is NaN or Inf                 */
+    int32_t which;      /* 0: set a holds the newest state, 1: set b           */
+} acm_diag;
+
+typedef struct acm_handle acm_handle;
+
+/* Largest modulus of the amplification factor of the step linearised about
+ * rest (Eqs. 2.10-2.13 in Fourier space, over all wavenumbers), and for
+ * two-phase runs the Heun stability number dt M lambda (8a + kappa lambda)
+ * of the bulk Cahn-Hilliard mode (stable when <= 2).  Pure host call. */
+acm_status acm_stability(const acm_config* cfg, double* max_amplification, double* che_number);
+
+/* Validate cfg, check stability (unless allow_unstable), and bind the two
+ * caller-owned state sets a and b (each sized for the grid and precision).
+ * The initial state must already be in a.  force_x: NULL or a device array
+ * of ny elements (precision type) added to g[0] on row j (e.g. Kolmogorov
+ * forcing).  stream: hipStream_t or NULL.  The handle owns only host data,
+ * graph executables and a small reduction buffer it allocates here. */
+acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b,
+                    const void* force_x, void* stream, acm_handle** out);
+
+/* One step: the newest state moves from one set to the other.  Async. */
+acm_status acm_step(acm_handle* h);
+
+/* nsteps steps, launched as captured HIP graphs of graph_chunk steps plus
+ * single launches for the remainder.  Async. */
+acm_status acm_run(acm_handle* h, int64_t nsteps);
+
+/* Diagnostics of the newest state (dumax compares with the other set, so it
+ * is meaningful once at least one step has run).  SYNCHRONISES the stream.
+ * Returns ACM_ENONFINITE (with *out filled) if a stored value is not finite. */
+acm_status acm_diagnostics(acm_handle* h, acm_diag* out);
+
+/* Which set holds the newest state (0 = a, 1 = b) and the step counter. */
+acm_status acm_current(const acm_handle* h, int32_t* which, int64_t* step);
+
+/* Resume bookkeeping after the caller restored a checkpoint into set
+ * `which`: the scheme is one-step, so a state plus its step count is a
+ * complete checkpoint. */
+acm_status acm_set_current(acm_handle* h, int32_t which, int64_t step);
+
+/* Release the handle (not the caller's fields).  Synchronises the stream. */
+void acm_destroy(acm_handle* h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* acm_last_error(void);
+
+/* Library version string. */
+const char* acm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

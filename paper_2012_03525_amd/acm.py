@@ -1,0 +1,216 @@
+"""ctypes binding of libacm.so (include/acm.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; PyTorch provides device
+memory (tensor.data_ptr()) and the stream (torch.cuda.current_stream()).
+Importing this module fails loudly if libacm.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libacm.so")
+
+OK, EINVAL, EUNSTABLE, EHIP, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
+PERIODIC, WALL, SYMMETRY = 0, 1, 2
+F64, F32 = 0, 1
+
+
+class AcmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"acm status {status}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("nu", ctypes.c_double), ("cs", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("sat_rho", ctypes.c_double), ("sat_mom", ctypes.c_double),
+        ("g", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 6), ("wall_u", (ctypes.c_double * 3) * 6),
+        ("two_phase", ctypes.c_int32), ("sigma", ctypes.c_double), ("width", ctypes.c_double),
+        ("mobility", ctypes.c_double), ("precision", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
+        ("graph_chunk", ctypes.c_int32), ("tile", ctypes.c_int32),
+    ]
+
+
+class Fields(ctypes.Structure):
+    _fields_ = [("drho", ctypes.c_void_p), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("phi", ctypes.c_void_p)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("mom", ctypes.c_double * 3), ("ke", ctypes.c_double),
+        ("dumax", ctypes.c_double), ("umax", ctypes.c_double), ("enstrophy", ctypes.c_double),
+        ("energy", ctypes.c_double), ("div_rms", ctypes.c_double), ("div_max", ctypes.c_double),
+        ("phi_sum", ctypes.c_double), ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int32),
+        ("which", ctypes.c_int32),
+    ]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+# exported symbols and their ctypes signatures (also checked by the CPU tests)
+SIGNATURES = {
+    "acm_stability": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "acm_init": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(Fields), ctypes.POINTER(Fields),
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "acm_step": (ctypes.c_int, [ctypes.c_void_p]),
+    "acm_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "acm_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diag)]),
+    "acm_current": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int64)]),
+    "acm_set_current": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
+    "acm_destroy": (None, [ctypes.c_void_p]),
+    "acm_last_error": (ctypes.c_char_p, []),
+    "acm_version": (ctypes.c_char_p, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2012_03525_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> int:
+    if status != OK:
+        raise AcmError(status, lib().acm_last_error().decode())
+    return status
+
+
+def make_config(dim: int, nx: int, ny: int, nz: int = 1, *, dx: float = 1.0, dt: float = 1.0,
+                nu: float = 0.0, cs: float = 0.0, rho0: float = 1.0, sat_rho: float = 1.0,
+                sat_mom: float = 1.0, g: Sequence[float] = (0.0, 0.0, 0.0),
+                bc: Sequence[int] = (0, 0, 0, 0, 0, 0), wall_u=None, two_phase: bool = False,
+                sigma: float = 0.0, width: float = 4.0, mobility: float = 0.0, precision: str = "f32",
+                allow_unstable: bool = False, graph_chunk: int = 0, tile: int = 0) -> Config:
+    c = Config()
+    c.dim, c.nx, c.ny, c.nz = dim, nx, ny, (nz if dim == 3 else 1)
+    c.dx, c.dt, c.nu, c.cs, c.rho0 = dx, dt, nu, cs, rho0
+    c.sat_rho, c.sat_mom = sat_rho, sat_mom
+    for a in range(3):
+        c.g[a] = float(g[a])
+    for f in range(6):
+        c.bc[f] = int(bc[f])
+        for a in range(3):
+            c.wall_u[f][a] = float(wall_u[f][a]) if wall_u is not None else 0.0
+    c.two_phase = 1 if two_phase else 0
+    c.sigma, c.width, c.mobility = sigma, width, mobility
+    c.precision = {"f64": F64, "f32": F32}[precision]
+    c.allow_unstable = 1 if allow_unstable else 0
+    c.graph_chunk = graph_chunk
+    c.tile = tile
+    return c
+
+
+def stability(cfg: Config):
+    amp, che = ctypes.c_double(), ctypes.c_double()
+    check(lib().acm_stability(ctypes.byref(cfg), ctypes.byref(amp), ctypes.byref(che)))
+    return amp.value, che.value
+
+
+def _names(cfg: Config):
+    names = ["drho", "u", "v"]
+    if cfg.dim == 3:
+        names.append("w")
+    if cfg.two_phase:
+        names.append("phi")
+    return names
+
+
+class Solver:
+    """Owns two device state sets (torch tensors) and a libacm handle."""
+
+    def __init__(self, cfg: Config, state: Dict[str, np.ndarray], device: str = "cuda:0",
+                 force_x: Optional[np.ndarray] = None, tensors=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if cfg.precision == F64 else torch.float32
+        self.shape = (cfg.nz, cfg.ny, cfg.nx) if cfg.dim == 3 else (cfg.ny, cfg.nx)
+        self.names = _names(cfg)
+        if tensors is not None:
+            self.sets = tensors
+        else:
+            self.sets = [{k: torch.empty(self.shape, dtype=self.dtype, device=self.device) for k in self.names}
+                         for _ in range(2)]
+            for k in self.names:
+                a = np.ascontiguousarray(np.asarray(state[k], dtype=np.float64).reshape(self.shape))
+                self.sets[0][k].copy_(torch.from_numpy(a).to(self.dtype))
+        self.force = None
+        if force_x is not None:
+            self.force = torch.from_numpy(np.ascontiguousarray(force_x, dtype=np.float64)).to(
+                device=self.device, dtype=self.dtype)
+        self._f = [self._fields(s) for s in self.sets]
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib().acm_init(ctypes.byref(cfg), ctypes.byref(self._f[0]), ctypes.byref(self._f[1]),
+                             ctypes.c_void_p(self.force.data_ptr() if self.force is not None else None),
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def _fields(self, s):
+        f = Fields()
+        for k in self.names:
+            setattr(f, k, s[k].data_ptr())
+        return f
+
+    def step(self):
+        check(lib().acm_step(self.h))
+
+    def run(self, nsteps: int):
+        check(lib().acm_run(self.h, int(nsteps)))
+
+    def current(self):
+        w, s = ctypes.c_int32(), ctypes.c_int64()
+        check(lib().acm_current(self.h, ctypes.byref(w), ctypes.byref(s)))
+        return w.value, s.value
+
+    def set_current(self, which: int, step: int):
+        check(lib().acm_set_current(self.h, int(which), int(step)))
+
+    def diagnostics(self, raise_nonfinite: bool = False) -> dict:
+        d = Diag()
+        st = lib().acm_diagnostics(self.h, ctypes.byref(d))
+        if st not in (OK, ENONFINITE) or (st == ENONFINITE and raise_nonfinite):
+            check(st)
+        return {"mass": d.mass, "mom_x": d.mom[0], "mom_y": d.mom[1], "mom_z": d.mom[2], "ke": d.ke,
+                "dumax": d.dumax, "umax": d.umax, "enstrophy": d.enstrophy, "energy": d.energy,
+                "div_rms": d.div_rms, "div_max": d.div_max, "phi_sum": d.phi_sum, "step": d.step,
+                "nonfinite": d.nonfinite, "which": d.which}
+
+    def tensors(self) -> Dict[str, "object"]:
+        """Device tensors of the newest state (no copy)."""
+        return self.sets[self.current()[0]]
+
+    def state(self) -> Dict[str, np.ndarray]:
+        """Newest state copied to host as FP64 numpy arrays (synchronises)."""
+        self.torch.cuda.synchronize(self.device)
+        return {k: t.detach().to("cpu", dtype=self.torch.float64).numpy() for k, t in self.tensors().items()}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().acm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,118 @@
+// Internal declarations of libacm: device-side coefficient block, boundary
+// mapping helpers and kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace acm {
+
+enum : int { BC_PERIODIC = 0, BC_WALL = 1, BC_SYMMETRY = 2 };
+
+// Coefficients of one SMAME step, folded on the host from the problem
+// statement so that the kernels only multiply and add.
+template <typename T>
+struct Coef {
+    int nx, ny, nz;
+    int bc[6];
+    int nonperiodic;   // any face is a wall or symmetry plane
+    T rho0;
+    T cg;              // dt / (2 dx): centred difference times dt
+    T cs2;             // cs^2
+    T kr;              // sat_rho * cs^2 dt^2 / (2 dx^2)      (Eq. 2.10 SAT)
+    T kv;              // nu dt / dx^2                         (viscous term)
+    T ks;              // sat_mom (nu + cs^2 dt / 2) / (2 dx)  (Eq. 2.11 SAT)
+    T gdt[3];          // dt g
+    T dt;
+    T fs[6][3];        // ghost velocity = fs * mirror + fo, per crossed face
+    T fo[6][3];
+    const T* fx;       // per-row x force (ny values) or null
+    // two-phase (2D)
+    T a4;              // 4 a, a = 3 sigma / (4 W)
+    T kap6;            // kappa / (6 dx^2)
+    T mob;             // M
+    T gi;              // 1 / (12 dx)   isotropic gradient
+    T li;              // 1 / (6 dx^2)  isotropic Laplacian
+};
+
+template <typename T>
+struct State {
+    T* r;
+    T* u;
+    T* v;
+    T* w;
+    T* phi;
+};
+
+// Map a possibly out-of-range coordinate onto its source node.  face is set
+// to the crossed face index (lo = 2*axis, hi = 2*axis+1) for a wall or a
+// symmetry plane, -1 otherwise.  Points more than one reflection away (only
+// reached by ragged tiles, never used by an output) are clamped in range.
+__device__ __forceinline__ int map_coord(int g, int n, int bc_lo, int face_lo, int& face)
+{
+    face = -1;
+    if (g < 0) {
+        if (bc_lo == BC_PERIODIC) {
+            g += n;
+            if (g < 0) g = ((g % n) + n) % n;
+        } else {
+            face = face_lo;
+            g = -1 - g;
+            if (g >= n) g = n - 1;
+        }
+    } else if (g >= n) {
+        if (bc_lo == BC_PERIODIC) {
+            g -= n;
+            if (g >= n) g %= n;
+        } else {
+            face = face_lo + 1;
+            g = 2 * n - 1 - g;
+            if (g < 0) g = 0;
+        }
+    }
+    return g;
+}
+
+// Position whose rho^{n+1} stands in for a ghost position: the mirror node
+// for a wall / symmetry face, the position itself otherwise (a periodic
+// ghost is computed from wrapped data and equals its image bit for bit).
+__device__ __forceinline__ int mirror_coord(int g, int n, int bc_lo)
+{
+    if (bc_lo == BC_PERIODIC) return g;
+    if (g < 0) return -1 - g;
+    if (g >= n) return 2 * n - 1 - g;
+    return g;
+}
+
+template <typename T>
+__device__ __forceinline__ T fmaT(T a, T b, T c) { return fma(a, b, c); }
+
+// 1 / rho for the velocity update.  FP32 uses the hardware reciprocal: it
+// only scales the (small) increment u^{n+1} - u^n, so its 1-ulp error is
+// far below the storage rounding of u.
+__device__ __forceinline__ float recipT(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recipT(double x) { return 1.0 / x; }
+
+// ---------------------------------------------------------------------------
+// launchers (kern_step.hip, kern_twophase.hip, kern_diag.hip)
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_step2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_step3d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_twophase2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
+                             hipStream_t s);
+
+// number of FP64 quantities reduced by the diagnostics kernel
+constexpr int NDIAG = 14;
+template <typename T>
+hipError_t launch_diag(const Coef<T>& c, int dim, int two_phase, const State<T>& cur,
+                       const State<T>& prev, int have_prev, double* partials, int nblocks,
+                       double* result, hipStream_t s);
+
+}  // namespace acm

@@ -1,0 +1,412 @@
+// C ABI of libacm (declared in include/acm.h): validation, the linear
+// stability guard, HIP-graph run loop and diagnostics.
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/acm.h"
+#include "acm_internal.h"
+
+using namespace acm;
+
+namespace {
+
+thread_local std::string g_err;
+
+acm_status fail(acm_status st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+acm_status hip_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return ACM_EHIP;
+}
+
+double sound_speed(const acm_config& c) { return c.cs > 0 ? c.cs : c.dx / (c.dt * std::sqrt(3.0)); }
+
+// Spectral radius of the step linearised about rest (Eqs. 2.10-2.13 in
+// Fourier space).  With s_a = sin(k_a dx)/dx, |s|^2 = sum s_a^2 and
+// lambda = sum (2 - 2 cos k_a dx)/dx^2, the density and the momentum
+// component along s evolve by
+//   [ 1 - A lambda              , -i dt |s|                      ]
+//   [ i |s| (A B lambda - dt cs^2), 1 - nu dt lambda - B dt |s|^2 ]
+// (A = sat_rho cs^2 dt^2 / 2, B = sat_mom (nu + cs^2 dt / 2)); the other
+// momentum components decay by 1 - nu dt lambda.
+double max_amplification(const acm_config& c)
+{
+    const double cs = sound_speed(c), cs2 = cs * cs, dt = c.dt, dx = c.dx, nu = c.nu;
+    const double A = c.sat_rho * 0.5 * cs2 * dt * dt;
+    const double B = c.sat_mom * (nu + 0.5 * cs2 * dt);
+    const int D = c.dim;
+    const int nk = (D == 3) ? 33 : 129;
+    const double pi = 3.14159265358979323846;
+    double worst = 0.0;
+    const int nz = (D == 3) ? nk : 1;
+    for (int iz = 0; iz < nz; ++iz)
+        for (int iy = 0; iy < nk; ++iy)
+            for (int ix = 0; ix < nk; ++ix) {
+                const double k[3] = {pi * ix / (nk - 1), pi * iy / (nk - 1), D == 3 ? pi * iz / (nk - 1) : 0.0};
+                double lam = 0.0, s2 = 0.0;
+                for (int a = 0; a < D; ++a) {
+                    lam += (2.0 - 2.0 * std::cos(k[a])) / (dx * dx);
+                    const double sa = std::sin(k[a]) / dx;
+                    s2 += sa * sa;
+                }
+                const double s = std::sqrt(s2);
+                using cd = std::complex<double>;
+                const cd a11 = 1.0 - A * lam, a12 = cd(0, -dt * s);
+                const cd a21 = cd(0, s * (A * B * lam - dt * cs2)), a22 = 1.0 - nu * dt * lam - B * dt * s2;
+                const cd tr = a11 + a22, det = a11 * a22 - a12 * a21;
+                const cd disc = std::sqrt(tr * tr / 4.0 - det);
+                const double l1 = std::abs(tr / 2.0 + disc), l2 = std::abs(tr / 2.0 - disc);
+                const double lt = std::abs(1.0 - nu * dt * lam);
+                worst = std::fmax(worst, std::fmax(std::fmax(l1, l2), lt));
+            }
+    return worst;
+}
+
+// Heun stability number of the bulk Cahn-Hilliard mode: linearised about
+// phi = +-1, mu = 8 a phi' - kappa L phi', so the growth symbol is
+// -dt M lambda (8 a + kappa lambda); the isotropic Laplacian reaches
+// lambda = 16 / (3 dx^2) at the checkerboard mode.  Heun is stable for <= 2.
+double che_number(const acm_config& c)
+{
+    if (!c.two_phase) return 0.0;
+    const double a = 3.0 * c.sigma / (4.0 * c.width), kappa = 3.0 * c.sigma * c.width / 8.0;
+    const double lam = 16.0 / (3.0 * c.dx * c.dx);
+    return c.dt * c.mobility * lam * (8.0 * a + kappa * lam);
+}
+
+acm_status validate(const acm_config* c)
+{
+    if (!c) return fail(ACM_EINVAL, "config is NULL");
+    if (c->dim != 2 && c->dim != 3) return fail(ACM_EINVAL, "dim must be 2 or 3");
+    const int minn = c->two_phase ? 8 : 4;
+    if (c->nx < minn || c->ny < minn || (c->dim == 3 && c->nz < minn))
+        return fail(ACM_EINVAL, "every axis needs at least " + std::to_string(minn) + " nodes");
+    if ((double)c->nx * c->ny * (c->dim == 3 ? c->nz : 1) > 4.0e9)
+        return fail(ACM_EINVAL, "grid larger than 4e9 nodes");
+    if (!(c->dx > 0) || !(c->dt > 0)) return fail(ACM_EINVAL, "dx and dt must be positive");
+    if (!(c->nu >= 0)) return fail(ACM_EINVAL, "nu must be non-negative");
+    if (!(c->rho0 > 0)) return fail(ACM_EINVAL, "rho0 must be positive");
+    if (c->two_phase && c->dim != 2) return fail(ACM_EINVAL, "two-phase runs are 2D");
+    if (c->two_phase && (!(c->width > 0) || !(c->sigma >= 0) || !(c->mobility >= 0)))
+        return fail(ACM_EINVAL, "two-phase needs width > 0, sigma >= 0, mobility >= 0");
+    if (c->precision != ACM_F64 && c->precision != ACM_F32) return fail(ACM_EINVAL, "unknown precision");
+    const int nf = c->dim == 3 ? 6 : 4;
+    for (int f = 0; f < nf; ++f) {
+        if (c->bc[f] < 0 || c->bc[f] > 2) return fail(ACM_EINVAL, "unknown boundary type");
+        if (c->bc[f] == ACM_BC_WALL && c->wall_u[f][f / 2] != 0.0)
+            return fail(ACM_EINVAL, "wall velocity must be tangential");
+    }
+    for (int a = 0; a < nf; a += 2)
+        if ((c->bc[a] == ACM_BC_PERIODIC) != (c->bc[a + 1] == ACM_BC_PERIODIC))
+            return fail(ACM_EINVAL, "a periodic face needs a periodic opposite face");
+    if (c->graph_chunk < 0 || (c->graph_chunk % 2) != 0) return fail(ACM_EINVAL, "graph_chunk must be even");
+    return ACM_OK;
+}
+
+template <typename T>
+Coef<T> make_coef(const acm_config& c, const void* force_x)
+{
+    Coef<T> k{};
+    k.nx = c.nx;
+    k.ny = c.ny;
+    k.nz = c.dim == 3 ? c.nz : 1;
+    const int nf = c.dim == 3 ? 6 : 4;
+    k.nonperiodic = 0;
+    for (int f = 0; f < 6; ++f) {
+        k.bc[f] = (f < nf) ? c.bc[f] : ACM_BC_PERIODIC;
+        if (k.bc[f] != ACM_BC_PERIODIC) k.nonperiodic = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (k.bc[f] == ACM_BC_WALL) {
+                k.fs[f][a] = T(-1);
+                k.fo[f][a] = T(2.0 * c.wall_u[f][a]);
+            } else if (k.bc[f] == ACM_BC_SYMMETRY) {
+                k.fs[f][a] = (a == f / 2) ? T(-1) : T(1);
+                k.fo[f][a] = T(0);
+            } else {
+                k.fs[f][a] = T(1);
+                k.fo[f][a] = T(0);
+            }
+        }
+    }
+    const double cs = sound_speed(c), cs2 = cs * cs, dt = c.dt, dx = c.dx;
+    k.rho0 = T(c.rho0);
+    k.cg = T(dt / (2.0 * dx));
+    k.cs2 = T(cs2);
+    k.kr = T(c.sat_rho * 0.5 * cs2 * dt * dt / (dx * dx));
+    k.kv = T(c.nu * dt / (dx * dx));
+    k.ks = T(c.sat_mom * (c.nu + 0.5 * cs2 * dt) / (2.0 * dx));
+    for (int a = 0; a < 3; ++a) k.gdt[a] = T(dt * c.g[a]);
+    k.dt = T(dt);
+    k.fx = static_cast<const T*>(force_x);
+    if (c.two_phase) {
+        const double a = 3.0 * c.sigma / (4.0 * c.width), kappa = 3.0 * c.sigma * c.width / 8.0;
+        k.a4 = T(4.0 * a);
+        k.kap6 = T(kappa / (6.0 * dx * dx));
+        k.mob = T(c.mobility);
+        k.gi = T(1.0 / (12.0 * dx));
+        k.li = T(1.0 / (6.0 * dx * dx));
+    }
+    return k;
+}
+
+}  // namespace
+
+struct acm_handle {
+    acm_config cfg;
+    acm_fields set[2];
+    const void* force_x = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    int which = 0;
+    int64_t step = 0;
+    int chunk = 64;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    double* partials = nullptr;
+    double* result = nullptr;
+    double* host = nullptr;
+    int diag_blocks = 0;
+    Coef<float> cf;
+    Coef<double> cd;
+};
+
+namespace {
+
+template <typename T>
+State<T> state_of(const acm_fields& f)
+{
+    return State<T>{static_cast<T*>(f.drho), static_cast<T*>(f.u), static_cast<T*>(f.v), static_cast<T*>(f.w),
+                    static_cast<T*>(f.phi)};
+}
+
+template <typename T>
+hipError_t launch_typed(const acm_handle* h, const Coef<T>& c, int from, hipStream_t s)
+{
+    const State<T> in = state_of<T>(h->set[from]);
+    const State<T> out = state_of<T>(h->set[1 - from]);
+    if (h->cfg.two_phase) return launch_twophase2d<T>(c, in, out, h->cfg.tile, s);
+    if (h->cfg.dim == 3) return launch_step3d<T>(c, in, out, h->cfg.tile, s);
+    return launch_step2d<T>(c, in, out, h->cfg.tile, s);
+}
+
+hipError_t launch_one(const acm_handle* h, int from, hipStream_t s)
+{
+    if (h->cfg.precision == ACM_F64) return launch_typed<double>(h, h->cd, from, s);
+    return launch_typed<float>(h, h->cf, from, s);
+}
+
+acm_status build_graph(acm_handle* h, int parity)
+{
+    hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    for (int i = 0; i < h->chunk; ++i) {
+        e = launch_one(h, (parity + i) & 1, h->cap);
+        if (e != hipSuccess) {
+            hipGraph_t g = nullptr;
+            hipStreamEndCapture(h->cap, &g);
+            if (g) hipGraphDestroy(g);
+            return hip_fail(e, "kernel launch during capture");
+        }
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->cap, &g);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&h->exec[parity], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->exec[parity] = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return ACM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* acm_last_error(void) { return g_err.c_str(); }
+
+const char* acm_version(void) { return "acm 0.1 (gfx950)"; }
+
+acm_status acm_stability(const acm_config* cfg, double* max_amp, double* che)
+{
+    acm_status st = validate(cfg);
+    if (st != ACM_OK) return st;
+    if (max_amp) *max_amp = max_amplification(*cfg);
+    if (che) *che = che_number(*cfg);
+    return ACM_OK;
+}
+
+acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b, const void* force_x,
+                    void* stream, acm_handle** out)
+{
+    g_err.clear();
+    if (!out) return fail(ACM_EINVAL, "out is NULL");
+    *out = nullptr;
+    acm_status st = validate(cfg);
+    if (st != ACM_OK) return st;
+    if (!a || !b) return fail(ACM_EINVAL, "field sets are NULL");
+    const acm_fields* sets[2] = {a, b};
+    for (int s = 0; s < 2; ++s) {
+        const acm_fields* f = sets[s];
+        if (!f->drho || !f->u || !f->v) return fail(ACM_EINVAL, "drho, u and v are required");
+        if (cfg->dim == 3 && !f->w) return fail(ACM_EINVAL, "w is required in 3D");
+        if (cfg->two_phase && !f->phi) return fail(ACM_EINVAL, "phi is required for two-phase runs");
+    }
+    if (!cfg->allow_unstable) {
+        const double amp = max_amplification(*cfg);
+        if (amp > 1.0 + 1e-12) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "linearised step amplifies by %.6f > 1 (set allow_unstable to run anyway)",
+                          amp);
+            return fail(ACM_EUNSTABLE, buf);
+        }
+        const double z = che_number(*cfg);
+        if (z > 2.0) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "Cahn-Hilliard stability number %.4f > 2", z);
+            return fail(ACM_EUNSTABLE, buf);
+        }
+    }
+    acm_handle* h = new (std::nothrow) acm_handle();
+    if (!h) return fail(ACM_EINVAL, "out of host memory");
+    h->cfg = *cfg;
+    h->set[0] = *a;
+    h->set[1] = *b;
+    h->force_x = force_x;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->chunk = cfg->graph_chunk > 0 ? cfg->graph_chunk : 64;
+    h->cf = make_coef<float>(*cfg, force_x);
+    h->cd = make_coef<double>(*cfg, force_x);
+    hipError_t e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    const double n = (double)cfg->nx * cfg->ny * (cfg->dim == 3 ? cfg->nz : 1);
+    h->diag_blocks = (int)std::fmin(2048.0, std::fmax(1.0, std::ceil(n / 256.0)));
+    e = hipMalloc(&h->partials, sizeof(double) * NDIAG * (size_t)h->diag_blocks);
+    if (e == hipSuccess) e = hipMalloc(&h->result, sizeof(double) * NDIAG);
+    if (e == hipSuccess) e = hipHostMalloc(&h->host, sizeof(double) * NDIAG, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        acm_destroy(h);
+        return hip_fail(e, "allocating reduction buffers");
+    }
+    *out = h;
+    return ACM_OK;
+}
+
+acm_status acm_step(acm_handle* h)
+{
+    if (!h) return fail(ACM_EINVAL, "handle is NULL");
+    hipError_t e = launch_one(h, h->which, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    h->which ^= 1;
+    h->step += 1;
+    return ACM_OK;
+}
+
+acm_status acm_run(acm_handle* h, int64_t nsteps)
+{
+    if (!h) return fail(ACM_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(ACM_EINVAL, "nsteps must be >= 0");
+    while (nsteps >= h->chunk) {
+        const int p = h->which;
+        if (!h->exec[p]) {
+            acm_status st = build_graph(h, p);
+            if (st != ACM_OK) return st;
+        }
+        hipError_t e = hipGraphLaunch(h->exec[p], h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        h->step += h->chunk;  // chunk is even: the parity is unchanged
+        nsteps -= h->chunk;
+    }
+    for (int64_t i = 0; i < nsteps; ++i) {
+        acm_status st = acm_step(h);
+        if (st != ACM_OK) return st;
+    }
+    return ACM_OK;
+}
+
+acm_status acm_diagnostics(acm_handle* h, acm_diag* out)
+{
+    if (!h || !out) return fail(ACM_EINVAL, "NULL argument");
+    const acm_config& c = h->cfg;
+    hipError_t e;
+    const int have_prev = h->step > 0 ? 1 : 0;
+    if (c.precision == ACM_F64)
+        e = launch_diag<double>(h->cd, c.dim, c.two_phase, state_of<double>(h->set[h->which]),
+                                state_of<double>(h->set[1 - h->which]), have_prev, h->partials, h->diag_blocks,
+                                h->result, h->stream);
+    else
+        e = launch_diag<float>(h->cf, c.dim, c.two_phase, state_of<float>(h->set[h->which]),
+                               state_of<float>(h->set[1 - h->which]), have_prev, h->partials, h->diag_blocks,
+                               h->result, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
+    e = hipMemcpyAsync(h->host, h->result, sizeof(double) * NDIAG, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const double* r = h->host;
+    const double dxd = c.dim == 3 ? c.dx * c.dx * c.dx : c.dx * c.dx;
+    const double n = (double)c.nx * c.ny * (c.dim == 3 ? c.nz : 1);
+    const double inv2dx = 1.0 / (2.0 * c.dx);
+    out->mass = r[0] * dxd;
+    out->mom[0] = r[1] * dxd;
+    out->mom[1] = r[2] * dxd;
+    out->mom[2] = r[3] * dxd;
+    out->ke = 0.5 * r[4] * dxd;
+    out->dumax = r[5];
+    out->umax = r[6];
+    out->enstrophy = r[7] * inv2dx * inv2dx / (2.0 * n);
+    out->energy = r[4] / (2.0 * n);
+    out->div_rms = std::sqrt(r[8] / n) * inv2dx;
+    out->div_max = r[9] * inv2dx;
+    out->phi_sum = r[10];
+    out->nonfinite = r[11] != 0.0 ? 1 : 0;
+    out->step = h->step;
+    out->which = h->which;
+    if (out->nonfinite) return fail(ACM_ENONFINITE, "state holds a NaN or Inf");
+    return ACM_OK;
+}
+
+acm_status acm_current(const acm_handle* h, int32_t* which, int64_t* step)
+{
+    if (!h) return fail(ACM_EINVAL, "handle is NULL");
+    if (which) *which = h->which;
+    if (step) *step = h->step;
+    return ACM_OK;
+}
+
+acm_status acm_set_current(acm_handle* h, int32_t which, int64_t step)
+{
+    if (!h) return fail(ACM_EINVAL, "handle is NULL");
+    if (which != 0 && which != 1) return fail(ACM_EINVAL, "which must be 0 or 1");
+    if (step < 0) return fail(ACM_EINVAL, "step must be >= 0");
+    h->which = which;
+    h->step = step;
+    return ACM_OK;
+}
+
+void acm_destroy(acm_handle* h)
+{
+    if (!h) return;
+    if (h->stream || h->cap) hipStreamSynchronize(h->stream);
+    for (int p = 0; p < 2; ++p)
+        if (h->exec[p]) hipGraphExecDestroy(h->exec[p]);
+    if (h->partials) hipFree(h->partials);
+    if (h->result) hipFree(h->result);
+    if (h->host) hipHostFree(h->host);
+    if (h->cap) hipStreamDestroy(h->cap);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,254 @@
+// Fused two-phase SMAME step (2D) for gfx950: flow update with the
+// surface-tension force, and the Cahn-Hilliard equation (Eq. 2.14) advanced
+// by Heun's second-order Runge-Kutta method, all in one launch.
+//
+// Per step and node (Sec. 2, two-phase paragraphs):
+//   mu     = 4 a phi (phi^2 - 1) - kappa L_iso phi
+//   flow   = single-phase update (Eqs. 2.10-2.11) + force -dt phi G_iso mu
+//   R(f,m) = M L_iso m - (u G_iso,x f + v G_iso,y f)        (u = u^n)
+//   phi*   = phi + dt R(phi, mu)
+//   phi^{n+1} = (phi + phi* + dt R(phi*, mu*)) / 2,   mu* = mu(phi*)
+// with the D2Q9-weighted isotropic stencils
+//   G_iso,x f = [4 (f_E - f_W) + (f_NE + f_SE - f_NW - f_SW)] / (12 dx)
+//   L_iso f   = [4 (f_E + f_W + f_N + f_S) + (f_NE + f_NW + f_SE + f_SW) - 20 f] / (6 dx^2).
+// Dependency radii: phi needs a 4-node halo (mu on tile+3, phi* on tile+2,
+// mu* on tile+1), the flow fields a 2-node halo.  Ghost positions of every
+// intermediate take the value at their mirror node for walls and symmetry
+// planes (contact angle 90 degrees), so they are computed there.
+#include "acm_internal.h"
+
+namespace acm {
+
+template <typename T>
+__device__ __forceinline__ T momc2(T r, T u, T rho0) { return fmaT(r, u, rho0 * u); }
+
+template <int TX, int TY>
+struct Shape2P {
+    static constexpr int PX = TX + 8, PY = TY + 8, PXY = PX * PY;   // phi, halo 4
+    static constexpr int MX = TX + 6, MY = TY + 6, MXY = MX * MY;   // mu, halo 3
+    static constexpr int RX = TX + 4, RY = TY + 4, RXY = RX * RY;   // flow fields / phi*, halo 2
+    static constexpr int DX = TX + 2, DY = TY + 2, DXY = DX * DY;   // mu*, drho', halo 1
+};
+
+// isotropic Laplacian numerator: 4 (E+W+N+S) + (NE+NW+SE+SW) - 20 C
+template <typename T, int W>
+__device__ __forceinline__ T liso_num(const T* f, int e)
+{
+    const T ax = (f[e + 1] + f[e - 1]) + (f[e + W] + f[e - W]);
+    const T dg = (f[e + 1 + W] + f[e - 1 + W]) + (f[e + 1 - W] + f[e - 1 - W]);
+    return fmaT(T(4), ax, dg) - T(20) * f[e];
+}
+template <typename T, int W>
+__device__ __forceinline__ T gisox_num(const T* f, int e)
+{
+    return fmaT(T(4), f[e + 1] - f[e - 1], (f[e + 1 + W] + f[e + 1 - W]) - (f[e - 1 + W] + f[e - 1 - W]));
+}
+template <typename T, int W>
+__device__ __forceinline__ T gisoy_num(const T* f, int e)
+{
+    return fmaT(T(4), f[e + W] - f[e - W], (f[e + 1 + W] + f[e - 1 + W]) - (f[e + 1 - W] + f[e - 1 - W]));
+}
+
+// chemical potential from a phi array of row width W at index e
+template <typename T, int W>
+__device__ __forceinline__ T chem(const Coef<T>& c, const T* f, int e)
+{
+    const T p = f[e];
+    return fmaT(c.a4 * p, fmaT(p, p, T(-1)), -c.kap6 * liso_num<T, W>(f, e));
+}
+
+// local coordinate (in a region with halo h) whose value stands in for the
+// position l: the mirror node for wall / symmetry ghosts, else l itself
+__device__ __forceinline__ int ghost_src(int l, int h, int o0, int n, int bc_lo, int lo, int hi)
+{
+    const int g = mirror_coord(o0 + l - h, n, bc_lo);
+    return min(max(g - o0 + h, lo), hi);
+}
+
+template <typename T, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, State<T> out, int nbx)
+{
+    using S = Shape2P<TX, TY>;
+    constexpr int PX = S::PX, MX = S::MX, RX = S::RX, DX = S::DX;
+    __shared__ T sp[S::PXY];                          // phi^n
+    __shared__ T smu[S::MXY];                         // mu^n
+    __shared__ T sr[S::RXY], su[S::RXY], sv[S::RXY];  // drho, u, v
+    __shared__ T sps[S::RXY];                         // phi*
+    __shared__ T sms[S::DXY];                         // mu*
+    __shared__ T srn[S::DXY];                         // drho'
+
+    const int lb = [&] {
+        constexpr int NX = 8;
+        const int nb = gridDim.x, b = blockIdx.x;
+        const int per = nb / NX, rem = nb % NX;
+        const int x = b % NX, i = b / NX;
+        return x * per + min(x, rem) + i;
+    }();
+    const int by = lb / nbx, bx = lb - by * nbx;
+    const int x0 = bx * TX, y0 = by * TY;
+    const int nx = c.nx, ny = c.ny;
+    const bool interior = (x0 >= 4) && (x0 + TX + 4 <= nx) && (y0 >= 4) && (y0 + TY + 4 <= ny);
+    const bool mirror = !interior && c.nonperiodic;
+    const int tid = threadIdx.x;
+
+    // ---- stage phi (halo 4) and drho, u, v (halo 2)
+    for (int q = tid; q < S::PXY; q += NT) {
+        const int ly = q / PX, lx = q - ly * PX;
+        int fx, fy;
+        const int sx = map_coord(x0 + lx - 4, nx, c.bc[0], 0, fx);
+        const int sy = map_coord(y0 + ly - 4, ny, c.bc[2], 2, fy);
+        sp[q] = in.phi[(size_t)sy * nx + sx];
+    }
+    for (int q = tid; q < S::RXY; q += NT) {
+        const int ly = q / RX, lx = q - ly * RX;
+        int fx, fy;
+        const int sx = map_coord(x0 + lx - 2, nx, c.bc[0], 0, fx);
+        const int sy = map_coord(y0 + ly - 2, ny, c.bc[2], 2, fy);
+        const size_t s = (size_t)sy * nx + sx;
+        T r = in.r[s], u = in.u[s], v = in.v[s];
+        if (fx >= 0) {
+            u = fmaT(c.fs[fx][0], u, c.fo[fx][0]);
+            v = fmaT(c.fs[fx][1], v, c.fo[fx][1]);
+        }
+        if (fy >= 0) {
+            u = fmaT(c.fs[fy][0], u, c.fo[fy][0]);
+            v = fmaT(c.fs[fy][1], v, c.fo[fy][1]);
+        }
+        sr[q] = r;
+        su[q] = u;
+        sv[q] = v;
+    }
+    __syncthreads();
+
+    // ---- mu^n on tile+3, drho' on tile+1
+    for (int q = tid; q < S::MXY; q += NT) {
+        const int ly = q / MX, lx = q - ly * MX;
+        int ex = lx + 1, ey = ly + 1;  // phi-region coordinates
+        if (mirror) {
+            ex = ghost_src(lx, 3, x0, nx, c.bc[0], 0, MX - 1) + 1;
+            ey = ghost_src(ly, 3, y0, ny, c.bc[2], 0, S::MY - 1) + 1;
+        }
+        smu[q] = chem<T, PX>(c, sp, ey * PX + ex);
+    }
+    for (int q = tid; q < S::DXY; q += NT) {
+        const int ly = q / DX, lx = q - ly * DX;
+        int ex = lx + 1, ey = ly + 1;  // flow-region coordinates
+        if (mirror) {
+            ex = ghost_src(lx, 1, x0, nx, c.bc[0], 0, DX - 1) + 1;
+            ey = ghost_src(ly, 1, y0, ny, c.bc[2], 0, S::DY - 1) + 1;
+        }
+        const int e = ey * RX + ex;
+        const T rc = sr[e];
+        const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
+        const T mE = momc2(rE, su[e + 1], c.rho0), mW = momc2(rW, su[e - 1], c.rho0);
+        const T mN = momc2(rN, sv[e + RX], c.rho0), mS = momc2(rS, sv[e - RX], c.rho0);
+        const T div = (mE - mW) + (mN - mS);
+        const T lap = ((rE + rW) + (rN + rS)) - T(4) * rc;
+        srn[q] = fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
+    }
+    __syncthreads();
+
+    // ---- phi* on tile+2
+    for (int q = tid; q < S::RXY; q += NT) {
+        const int ly = q / RX, lx = q - ly * RX;
+        int ex = lx, ey = ly;  // flow-region coordinates of the evaluation node
+        if (mirror) {
+            ex = ghost_src(lx, 2, x0, nx, c.bc[0], 0, RX - 1);
+            ey = ghost_src(ly, 2, y0, ny, c.bc[2], 0, S::RY - 1);
+        }
+        const int ep = (ey + 2) * PX + (ex + 2);  // phi region
+        const int em = (ey + 1) * MX + (ex + 1);  // mu region
+        const int ef = ey * RX + ex;
+        const T gxp = gisox_num<T, PX>(sp, ep), gyp = gisoy_num<T, PX>(sp, ep);
+        const T adv = fmaT(su[ef], gxp, sv[ef] * gyp) * c.gi;
+        const T rhs = fmaT(c.mob * c.li, liso_num<T, MX>(smu, em), -adv);
+        sps[q] = fmaT(c.dt, rhs, sp[ep]);
+    }
+    __syncthreads();
+
+    // ---- mu* on tile+1
+    for (int q = tid; q < S::DXY; q += NT) {
+        const int ly = q / DX, lx = q - ly * DX;
+        int ex = lx + 1, ey = ly + 1;  // phi*-region coordinates
+        if (mirror) {
+            ex = ghost_src(lx, 1, x0, nx, c.bc[0], 0, DX - 1) + 1;
+            ey = ghost_src(ly, 1, y0, ny, c.bc[2], 0, S::DY - 1) + 1;
+        }
+        sms[q] = chem<T, RX>(c, sps, ey * RX + ex);
+    }
+    __syncthreads();
+
+    // ---- outputs on the tile
+    const T rho0 = c.rho0, cs2 = c.cs2;
+    for (int q = tid; q < TX * TY; q += NT) {
+        const int ly = q / TX, lx = q - ly * TX;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= nx || gy >= ny) continue;
+        const int e = (ly + 2) * RX + (lx + 2);   // flow / phi* region
+        const int d = (ly + 1) * DX + (lx + 1);   // drho' / mu* region
+        const int ep = (ly + 4) * PX + (lx + 4);  // phi region
+        const int em = (ly + 3) * MX + (lx + 3);  // mu region
+        // flow
+        const T rc = sr[e], uc = su[e], vc = sv[e];
+        const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
+        const T uE = su[e + 1], uW = su[e - 1], uN = su[e + RX], uS = su[e - RX];
+        const T vE = sv[e + 1], vW = sv[e - 1], vN = sv[e + RX], vS = sv[e - RX];
+        const T mxC = momc2(rc, uc, rho0), myC = momc2(rc, vc, rho0);
+        const T mxE = momc2(rE, uE, rho0), mxW = momc2(rW, uW, rho0);
+        const T mxN = momc2(rN, uN, rho0), mxS = momc2(rS, uS, rho0);
+        const T myE = momc2(rE, vE, rho0), myW = momc2(rW, vW, rho0);
+        const T myN = momc2(rN, vN, rho0), myS = momc2(rS, vS, rho0);
+        const T rnC = srn[d];
+        const T fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + (mxN * vN - mxS * vS);
+        const T fyy = (myE * uE - myW * uW) + (fmaT(myN, vN, cs2 * rN) - fmaT(myS, vS, cs2 * rS));
+        const T lpx = ((mxE + mxW) + (mxN + mxS)) - T(4) * mxC;
+        const T lpy = ((myE + myW) + (myN + myS)) - T(4) * myC;
+        const T sx = (srn[d + 1] - srn[d - 1]) - (rE - rW);
+        const T sy = (srn[d + DX] - srn[d - DX]) - (rN - rS);
+        const T rho_n = rho0 + rnC;
+        // surface tension -dt phi G_iso mu
+        const T pc = sp[ep];
+        const T fstx = -c.dt * pc * (gisox_num<T, MX>(smu, em) * c.gi);
+        const T fsty = -c.dt * pc * (gisoy_num<T, MX>(smu, em) * c.gi);
+        T gx_ = c.gdt[0];
+        if (c.fx) gx_ = fmaT(c.dt, c.fx[gy], gx_);
+        const T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lpx, fmaT(-c.cg, fxx, fstx))));
+        const T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, lpy, fmaT(-c.cg, fyy, fsty))));
+        const T drn = rnC - rc;
+        const T inv = recipT(rho_n);
+        // Cahn-Hilliard second stage
+        const T gxs = gisox_num<T, RX>(sps, e), gys = gisoy_num<T, RX>(sps, e);
+        const T adv = fmaT(uc, gxs, vc * gys) * c.gi;
+        const T rhs = fmaT(c.mob * c.li, liso_num<T, DX>(sms, d), -adv);
+        const T phin = T(0.5) * fmaT(c.dt, rhs, pc + sps[e]);
+        const size_t o = (size_t)gy * nx + gx;
+        out.r[o] = rnC;
+        out.u[o] = fmaT(fmaT(-uc, drn, dmx), inv, uc);
+        out.v[o] = fmaT(fmaT(-vc, drn, dmy), inv, vc);
+        out.phi[o] = phin;
+    }
+}
+
+template <typename T, int TX, int TY, int NT>
+static hipError_t launch2p_variant(const Coef<T>& c, const State<T>& in, const State<T>& out, hipStream_t s)
+{
+    const int nbx = (c.nx + TX - 1) / TX, nby = (c.ny + TY - 1) / TY;
+    hipLaunchKernelGGL((twophase2d_kernel<T, TX, TY, NT>), dim3(nbx * nby), dim3(NT), 0, s, c, in, out, nbx);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_twophase2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile, hipStream_t s)
+{
+    switch (tile) {
+        case 1: return launch2p_variant<T, 32, 8, 256>(c, in, out, s);
+        case 2: return launch2p_variant<T, 64, 8, 256>(c, in, out, s);
+        case 3: return launch2p_variant<T, 16, 16, 256>(c, in, out, s);
+        default: return launch2p_variant<T, 32, 16, 256>(c, in, out, s);
+    }
+}
+
+template hipError_t launch_twophase2d<float>(const Coef<float>&, const State<float>&, const State<float>&, int, hipStream_t);
+template hipError_t launch_twophase2d<double>(const Coef<double>&, const State<double>&, const State<double>&, int, hipStream_t);
+
+}  // namespace acm

@@ -1,0 +1,133 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/acm.h declares, validates its arguments before any
+HIP call, and its linear-stability guard reproduces the paper's SAT ablation."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2012_03525_amd import acm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(inc, fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(acm_[a-z0-9_]+)\s*\(", src, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = acm.lib()
+    names = declared_functions()
+    assert "acm_init" in names and "acm_run" in names and "acm_diagnostics" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_string():
+    assert b"gfx950" in acm.lib().acm_version()
+
+
+def _init(cfg, a=None, b=None):
+    h = ctypes.c_void_p()
+    fa = a if a is not None else acm.Fields(1, 2, 3, 4, 5)
+    fb = b if b is not None else acm.Fields(6, 7, 8, 9, 10)
+    return acm.lib().acm_init(ctypes.byref(cfg), ctypes.byref(fa), ctypes.byref(fb), None, None, ctypes.byref(h))
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (lambda c: setattr(c, "dim", 4), acm.EINVAL),
+    (lambda c: setattr(c, "nx", 3), acm.EINVAL),
+    (lambda c: setattr(c, "dx", 0.0), acm.EINVAL),
+    (lambda c: setattr(c, "nu", -1.0), acm.EINVAL),
+    (lambda c: c.bc.__setitem__(0, 1), acm.EINVAL),          # wall paired with periodic
+    (lambda c: setattr(c, "precision", 7), acm.EINVAL),
+    (lambda c: setattr(c, "graph_chunk", 3), acm.EINVAL),
+    (lambda c: setattr(c, "nu", 0.3), acm.EUNSTABLE),         # above the 2D viscous bound
+    (lambda c: setattr(c, "sat_mom", 0.0), acm.EUNSTABLE),    # continuity-only SAT
+])
+def test_init_rejects_bad_arguments_without_touching_the_gpu(mutate, expect):
+    cfg = acm.make_config(2, 16, 16, nu=0.05)
+    mutate(cfg)
+    assert _init(cfg) == expect
+    assert acm.lib().acm_last_error()
+
+
+def test_init_rejects_missing_fields():
+    cfg = acm.make_config(3, 8, 8, 8, nu=0.02)
+    assert _init(cfg, a=acm.Fields(1, 2, 3, 0, 0)) == acm.EINVAL      # no w in 3D
+    cfg2 = acm.make_config(2, 16, 16, nu=0.05, two_phase=True, sigma=1e-3, width=4, mobility=0.1)
+    assert _init(cfg2, a=acm.Fields(1, 2, 3, 0, 0)) == acm.EINVAL     # no phi
+    cfg3 = acm.make_config(2, 16, 16, nu=0.05, bc=(1, 1, 0, 0, 0, 0),
+                           wall_u=[[0.1, 0, 0]] + [[0, 0, 0]] * 5)
+    assert _init(cfg3) == acm.EINVAL                                  # wall moving through itself
+
+
+def _numpy_radius(nu, sat_rho, sat_mom, dim=2):
+    """Spectral radius of the linearised step computed with numpy.eigvals
+    from the same Fourier symbols (checked against the oracle in the pins)."""
+    cs2 = 1.0 / 3.0
+    A = sat_rho * 0.5 * cs2
+    B = sat_mom * (nu + 0.5 * cs2)
+    ks = np.linspace(0, math.pi, 97 if dim == 2 else 25)
+    grids = np.meshgrid(*([ks] * dim), indexing="ij")
+    lam = sum(2 - 2 * np.cos(k) for k in grids).ravel()
+    s2 = sum(np.sin(k) ** 2 for k in grids).ravel()
+    worst = 0.0
+    for l, q in zip(lam, s2):
+        s = math.sqrt(q)
+        M = np.array([[1 - A * l, -1j * s], [1j * s * (A * B * l - cs2), 1 - nu * l - B * q]])
+        worst = max(worst, np.abs(np.linalg.eigvals(M)).max(), abs(1 - nu * l))
+    return worst
+
+
+@pytest.mark.parametrize("sat_rho,sat_mom,expected", [
+    (1, 1, 1.000), (0, 1, 1.000), (1, 0, 1.010), (0, 0, 1.123)])
+def test_stability_guard_reproduces_fig3_ablation(sat_rho, sat_mom, expected):
+    """Fig. 3 setting (N_L = 50, c = 20, Re = 20 -> nu_lat = 0.125): the
+    linearised step is neutral with both SATs or the momentum SAT only, and
+    amplifies with the continuity SAT only (slow blow-up) or none (fast)."""
+    cfg = acm.make_config(2, 100, 100, nu=0.125, sat_rho=sat_rho, sat_mom=sat_mom)
+    amp, _ = acm.stability(cfg)
+    assert amp == pytest.approx(expected, abs=1.5e-3)
+    assert amp == pytest.approx(_numpy_radius(0.125, sat_rho, sat_mom), abs=5e-5)  # k-grids differ
+
+
+@pytest.mark.parametrize("dim,bound", [(2, 0.218), (3, 0.0836)])
+def test_viscous_stability_bound(dim, bound):
+    """Largest stable lattice viscosity with both SATs at cs^2 = 1/3."""
+    lo, hi = 0.0, 1.0
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        amp, _ = acm.stability(acm.make_config(dim, 8, 8, 8, nu=mid))
+        if amp <= 1.0 + 1e-12:
+            lo = mid
+        else:
+            hi = mid
+    assert lo == pytest.approx(bound, abs=2e-3)
+
+
+def test_che_stability_number_matches_capillary_wave_statement():
+    """Sec. 3.4: c = 5 unstable, c = 6 stable (N_L = 64, Cn = 0.0625, Pe = 2e4)."""
+    for c, expect in ((5, 2.075), (6, 1.729)):
+        NL, Re = 64, 1000
+        nu = NL / (c * Re)
+        sigma = NL / (c * c * Re)
+        cfg = acm.make_config(2, 64, 64, nu=nu, two_phase=True, sigma=sigma, width=4.0,
+                              mobility=NL * NL / (2e4 * nu), bc=(0, 0, 1, 1, 0, 0))
+        _, z = acm.stability(cfg)
+        assert z == pytest.approx(expect, abs=2e-3)
+    bad = acm.make_config(2, 64, 64, nu=64 / 5000, two_phase=True, sigma=64 / 25000, width=4.0,
+                          mobility=16.0, bc=(0, 0, 1, 1, 0, 0))
+    assert _init(bad) == acm.EUNSTABLE

@@ -1,0 +1,345 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  FP64 builds must agree to relative L2 <= 1e-12; the
+FP32 build (drho storage) to <= 2e-5 on u and <= 1e-4 on drho after 1000
+steps of the 2D Taylor-Green case.  FP32 inputs are rounded to FP32 first
+and the oracle starts from exactly those values."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2012_03525_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def acm_mod():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2012_03525_amd import acm
+    acm.lib()
+    return acm
+
+
+def rel_l2(a, b):
+    den = np.linalg.norm(b.ravel())
+    return float(np.linalg.norm((a - b).ravel()) / max(den, 1e-300))
+
+
+def rel_l2_vec(g, o, keys):
+    """Relative L2 of a vector field (components stacked): the FP32 error of
+    a component that is nearly zero is measured against the velocity scale."""
+    num = sum(float(np.sum((g[k] - o[k]) ** 2)) for k in keys)
+    den = sum(float(np.sum(o[k] ** 2)) for k in keys)
+    return math.sqrt(num / max(den, 1e-300))
+
+
+def to_f32(st):
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in st.items()}
+
+
+def oparams(orc, cfg):
+    bc = list(cfg.bc)
+    wu = [[cfg.wall_u[f][a] for a in range(3)] for f in range(6)]
+    cs = cfg.cs if cfg.cs > 0 else cfg.dx / (cfg.dt * math.sqrt(3))
+    return orc.Params(dim=cfg.dim, nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, dx=cfg.dx, dt=cfg.dt, nu=cfg.nu, cs=cs,
+                      rho0=cfg.rho0, sat_rho=cfg.sat_rho, sat_mom=cfg.sat_mom, g=list(cfg.g), bc=bc, wall_u=wu,
+                      two_phase=bool(cfg.two_phase), sigma=cfg.sigma, width=cfg.width, mobility=cfg.mobility)
+
+
+def run_both(acm, orc, cfg, st, nsteps, force_x=None, use_run=True):
+    s = acm.Solver(cfg, st, force_x=force_x)
+    if use_run:
+        s.run(nsteps)
+    else:
+        for _ in range(nsteps):
+            s.step()
+    g = s.state()
+    s.close()
+    o = orc.run(oparams(orc, cfg), st, nsteps, force_x_row=force_x)
+    return g, o
+
+
+# --- the 2D Taylor-Green case: 64^2, u0 = 0.01, nu = 0.01, 1000 steps -------
+def tgv64():
+    return inputs.tgv2d(64, 0.01, seed=20201206, noise=1e-6)
+
+
+def test_tgv2d_fp64_parity(acm_mod, orc):
+    cfg = acm_mod.make_config(2, 64, 64, nu=0.01, precision="f64")
+    g, o = run_both(acm_mod, orc, cfg, tgv64(), 1000)
+    for k in ("drho", "u", "v"):
+        assert rel_l2(g[k], o[k]) <= 1e-12, k
+
+
+def test_tgv2d_fp32_parity(acm_mod, orc):
+    cfg = acm_mod.make_config(2, 64, 64, nu=0.01, precision="f32")
+    st = to_f32(tgv64())
+    g, o = run_both(acm_mod, orc, cfg, st, 1000)
+    eu, ev, er = rel_l2(g["u"], o["u"]), rel_l2(g["v"], o["v"]), rel_l2(g["drho"], o["drho"])
+    print(f"fp32 rel L2 after 1000 steps: u {eu:.3e} v {ev:.3e} drho {er:.3e}")
+    assert eu <= 2e-5 and ev <= 2e-5
+    assert er <= 1e-4
+
+
+def test_graph_run_equals_single_steps(acm_mod):
+    """acm_run (captured graphs of graph_chunk steps) is bitwise equal to
+    the same number of acm_step calls."""
+    st = to_f32(tgv64())
+    cfg = acm_mod.make_config(2, 64, 64, nu=0.01, precision="f32", graph_chunk=8)
+    a = acm_mod.Solver(cfg, st)
+    a.run(37)
+    b = acm_mod.Solver(cfg, st)
+    for _ in range(37):
+        b.step()
+    sa, sb = a.state(), b.state()
+    assert a.current() == b.current() == (1, 37)
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k])
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5])
+def test_tiles_bitwise_identical(acm_mod, tile):
+    """The per-node arithmetic does not depend on the tile shape."""
+    st = to_f32(inputs.seeded_state((45, 70), seed=2, scale_u=0.03, scale_r=1e-3))
+    wu = [[0.0] * 3 for _ in range(6)]
+    wu[3] = [0.05, 0.0, 0.0]
+    base = acm_mod.make_config(2, 70, 45, nu=0.05, precision="f32", bc=(0, 0, 1, 1, 0, 0), wall_u=wu)
+    ref = acm_mod.Solver(base, st)
+    ref.run(20)
+    r = ref.state()
+    cfg = acm_mod.make_config(2, 70, 45, nu=0.05, precision="f32", bc=(0, 0, 1, 1, 0, 0), wall_u=wu, tile=tile)
+    s = acm_mod.Solver(cfg, st)
+    s.run(20)
+    o = s.state()
+    for k in r:
+        assert np.array_equal(r[k], o[k]), k
+
+
+BC2D = {
+    "periodic": ((0, 0, 0, 0, 0, 0), {}),
+    "cavity": ((1, 1, 1, 1, 0, 0), {3: [0.05, 0, 0]}),
+    "walls_moving": ((1, 1, 1, 1, 0, 0), {0: [0, -0.02, 0], 1: [0, 0.03, 0], 2: [0.01, 0, 0], 3: [-0.04, 0, 0]}),
+    "symmetry": ((2, 2, 2, 2, 0, 0), {}),
+    "mixed": ((0, 0, 1, 2, 0, 0), {2: [0.03, 0, 0]}),
+    "sym_wall": ((2, 1, 1, 2, 0, 0), {1: [0, 0.02, 0], 2: [0.01, 0, 0]}),
+}
+
+
+@pytest.mark.parametrize("name", list(BC2D))
+@pytest.mark.parametrize("shape", [(45, 70), (16, 16), (4, 9)])
+@pytest.mark.parametrize("tile", [0, 3])
+def test_bc2d_fp64_parity(acm_mod, orc, name, shape, tile):
+    faces, walls = BC2D[name]
+    wu = [[0.0] * 3 for _ in range(6)]
+    for f, v in walls.items():
+        wu[f] = v
+    ny, nx = shape
+    st = inputs.seeded_state(shape, seed=5, scale_u=0.03, scale_r=1e-3)
+    cfg = acm_mod.make_config(2, nx, ny, nu=0.04, precision="f64", bc=faces, wall_u=wu, tile=tile,
+                              g=(1e-5, -2e-5, 0.0))
+    g, o = run_both(acm_mod, orc, cfg, st, 30)
+    for k in ("drho", "u", "v"):
+        assert rel_l2(g[k], o[k]) <= 1e-12, (k, rel_l2(g[k], o[k]))
+
+
+def test_body_force_row_profile_parity(acm_mod, orc):
+    n = 64
+    st = inputs.random_spectrum_field(n, seed=3, u_rms=0.02, kmax=8)
+    fx = 1e-5 * np.sin(2 * math.pi * 4 * np.arange(n) / n)
+    cfg = acm_mod.make_config(2, n, n, nu=0.02, precision="f64")
+    g, o = run_both(acm_mod, orc, cfg, st, 100, force_x=fx)
+    for k in ("drho", "u", "v"):
+        assert rel_l2(g[k], o[k]) <= 1e-12
+
+
+# --- 3D ----------------------------------------------------------------------
+def test_tgv3d_fp64_parity_64(acm_mod, orc):
+    """3D Taylor-Green, FP64 GPU build at 64^3 against the oracle."""
+    n, u0 = 64, 0.05
+    nu = u0 * (n / (2 * math.pi)) / 1600.0
+    cfg = acm_mod.make_config(3, n, n, n, nu=nu, precision="f64")
+    g, o = run_both(acm_mod, orc, cfg, inputs.tgv3d(n, u0), 60)
+    for k in ("drho", "u", "v", "w"):
+        assert rel_l2(g[k], o[k]) <= 1e-12, k
+
+
+def test_tgv3d_fp32_parity_64(acm_mod, orc):
+    n, u0 = 64, 0.05
+    nu = u0 * (n / (2 * math.pi)) / 1600.0
+    cfg = acm_mod.make_config(3, n, n, n, nu=nu, precision="f32")
+    g, o = run_both(acm_mod, orc, cfg, to_f32(inputs.tgv3d(n, u0)), 60)
+    assert rel_l2_vec(g, o, ("u", "v", "w")) <= 2e-5
+    assert rel_l2(g["drho"], o["drho"]) <= 1e-4
+
+
+BC3D = {
+    "periodic": ((0, 0, 0, 0, 0, 0), {}),
+    "cavity": ((1, 1, 1, 1, 1, 1), {5: [0.05, 0, 0]}),
+    "mixed": ((2, 2, 0, 0, 1, 1), {4: [0.01, 0.02, 0], 5: [-0.02, 0, 0]}),
+    "zsym": ((0, 0, 1, 2, 2, 1), {2: [0, 0, 0.03], 5: [0, 0.01, 0]}),
+}
+
+
+@pytest.mark.parametrize("name", list(BC3D))
+@pytest.mark.parametrize("tile", [0, 1, 3 | (1 << 8)])
+def test_bc3d_fp64_parity(acm_mod, orc, name, tile):
+    faces, walls = BC3D[name]
+    wu = [[0.0] * 3 for _ in range(6)]
+    for f, v in walls.items():
+        wu[f] = v
+    shape = (19, 21, 70)
+    st = inputs.seeded_state(shape, seed=9, scale_u=0.03, scale_r=1e-3)
+    cfg = acm_mod.make_config(3, 70, 21, 19, nu=0.03, precision="f64", bc=faces, wall_u=wu, tile=tile,
+                              g=(1e-5, 0.0, -1e-5))
+    g, o = run_both(acm_mod, orc, cfg, st, 12)
+    for k in ("drho", "u", "v", "w"):
+        assert rel_l2(g[k], o[k]) <= 1e-12, (k, rel_l2(g[k], o[k]))
+
+
+def test_tgv3d_full_size_one_step_and_invariants(acm_mod, orc):
+    """256^3 FP32 in the benchmark's launch configuration: one step compared
+    node by node with the oracle, then 200 more steps checked for exact-mass
+    and momentum invariants and monotone kinetic-energy decay."""
+    n, u0 = 256, 0.05
+    nu = u0 * (n / (2 * math.pi)) / 1600.0
+    st = to_f32(inputs.tgv3d(n, u0))
+    cfg = acm_mod.make_config(3, n, n, n, nu=nu, precision="f32")
+    s = acm_mod.Solver(cfg, st)
+    d0 = s.diagnostics()
+    s.step()
+    g = s.state()
+    o = orc.step(oparams(orc, cfg), st)
+    umax = max(np.abs(o[k]).max() for k in ("u", "v", "w"))
+    for k in ("u", "v", "w"):
+        err = np.abs(g[k] - o[k]).max() / umax
+        assert err < 1e-6, (k, err)
+    assert np.abs(g["drho"] - o["drho"]).max() / np.abs(o["drho"]).max() < 1e-6
+    del o
+    kes = [s.diagnostics()["ke"]]
+    for _ in range(4):
+        s.run(50)
+        d = s.diagnostics(raise_nonfinite=True)
+        kes.append(d["ke"])
+        assert abs(d["mass"] - d0["mass"]) < 1e-6 * n ** 3 * 1e-3
+        for a in ("mom_x", "mom_y", "mom_z"):
+            assert abs(d[a]) < 1e-8 * n ** 3
+    assert all(kes[i + 1] < kes[i] for i in range(len(kes) - 1))
+    s.close()
+
+
+# --- two-phase -----------------------------------------------------------------
+def drop128(u_wall=0.02):
+    return inputs.drop_in_shear(128, 128, 16.0, 4.0, u_wall)
+
+
+def drop_cfg(acm, n, precision, tile=0):
+    wu = [[0.0] * 3 for _ in range(6)]
+    wu[2] = [-0.02, 0, 0]
+    wu[3] = [0.02, 0, 0]
+    return acm.make_config(2, n, n, nu=0.1, precision=precision, bc=(0, 0, 1, 1, 0, 0), wall_u=wu,
+                           two_phase=True, sigma=0.01, width=4.0, mobility=0.02, tile=tile)
+
+
+@pytest.mark.parametrize("tile", [0, 1, 3])
+def test_twophase_fp64_parity(acm_mod, orc, tile):
+    cfg = drop_cfg(acm_mod, 128, "f64", tile)
+    g, o = run_both(acm_mod, orc, cfg, drop128(), 300)
+    for k in ("drho", "u", "v", "phi"):
+        assert rel_l2(g[k], o[k]) <= 1e-12, (k, rel_l2(g[k], o[k]))
+
+
+def test_twophase_fp32_parity(acm_mod, orc):
+    cfg = drop_cfg(acm_mod, 128, "f32")
+    g, o = run_both(acm_mod, orc, cfg, to_f32(drop128()), 1000)
+    assert rel_l2(g["phi"], o["phi"]) <= 1e-5
+    assert rel_l2_vec(g, o, ("u", "v")) <= 2e-5
+    assert rel_l2(g["drho"], o["drho"]) <= 1e-4
+
+
+@pytest.mark.parametrize("faces", [(0, 0, 0, 0, 0, 0), (2, 2, 1, 1, 0, 0), (1, 1, 2, 2, 0, 0)])
+def test_twophase_bc_ragged_fp64(acm_mod, orc, faces):
+    ny, nx = 37, 53
+    st = inputs.seeded_state((ny, nx), seed=4, scale_u=0.02, scale_r=1e-3, two_phase=True)
+    wu = [[0.0] * 3 for _ in range(6)]
+    if faces[2] == 1:
+        wu[2] = [0.01, 0, 0]
+    if faces[0] == 1:
+        wu[1] = [0, -0.02, 0]
+    cfg = acm_mod.make_config(2, nx, ny, nu=0.08, precision="f64", bc=faces, wall_u=wu, two_phase=True,
+                              sigma=0.005, width=4.0, mobility=0.05)
+    g, o = run_both(acm_mod, orc, cfg, st, 20)
+    for k in ("drho", "u", "v", "phi"):
+        assert rel_l2(g[k], o[k]) <= 1e-12, (k, rel_l2(g[k], o[k]))
+
+
+def test_twophase_full_size_one_step(acm_mod, orc):
+    """1024^2 drop in shear (FP32, the full two-phase workload): one step node
+    by node against the oracle."""
+    st = to_f32(inputs.drop_in_shear(1024, 1024, 128.0, 4.0, 0.02))
+    cfg = drop_cfg(acm_mod, 1024, "f32")
+    s = acm_mod.Solver(cfg, st)
+    s.step()
+    g = s.state()
+    o = orc.step(oparams(orc, cfg), st)
+    umax = max(np.abs(o[k]).max() for k in ("u", "v"))
+    for k in ("u", "v"):
+        assert np.abs(g[k] - o[k]).max() / umax < 1e-6, k
+    assert np.abs(g["phi"] - o["phi"]).max() < 1e-6
+    assert np.abs(g["drho"] - o["drho"]).max() < 1e-9
+    s.close()
+
+
+# --- diagnostics ----------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_diagnostics_match_oracle(acm_mod, orc, dim):
+    shape = (20, 24, 28) if dim == 3 else (40, 56)
+    st = inputs.seeded_state(shape, seed=8, scale_u=0.03, scale_r=1e-3, two_phase=(dim == 2))
+    wu = [[0.0] * 3 for _ in range(6)]
+    wu[3] = [0.04, 0, 0]
+    faces = (0, 0, 1, 1, 2, 2) if dim == 3 else (0, 0, 1, 1, 0, 0)
+    kw = dict(two_phase=True, sigma=0.01, width=4.0, mobility=0.02) if dim == 2 else {}
+    cfg = acm_mod.make_config(dim, shape[-1], shape[-2], shape[0] if dim == 3 else 1, nu=0.05,
+                              precision="f64", bc=faces, wall_u=wu, dx=0.5, dt=0.25, **kw)
+    s = acm_mod.Solver(cfg, st)
+    s.run(3)
+    prev = None
+    d = s.diagnostics()
+    cur = s.state()
+    w = s.current()[0]
+    prev = {k: t.cpu().double().numpy() for k, t in s.sets[1 - w].items()}
+    od = orc.diag(oparams(orc, cfg), cur, prev)
+    for k in ("mass", "mom_x", "mom_y", "mom_z", "ke", "dumax", "umax", "enstrophy", "energy", "div_rms",
+              "div_max", "phi_sum"):
+        assert d[k] == pytest.approx(od[k], rel=1e-11, abs=1e-15), k
+    assert d["nonfinite"] == 0 and d["step"] == 3
+
+
+def test_diagnostics_flag_nonfinite(acm_mod):
+    st = inputs.seeded_state((16, 16), seed=1)
+    st["u"][3, 4] = np.nan
+    s = acm_mod.Solver(acm_mod.make_config(2, 16, 16, nu=0.05, precision="f32"), st)
+    d = s.diagnostics()
+    assert d["nonfinite"] == 1
+    with pytest.raises(acm_mod.AcmError):
+        s.diagnostics(raise_nonfinite=True)
+
+
+def test_checkpoint_resume_bitwise(acm_mod):
+    """One-step scheme: a state plus its step count is a full checkpoint;
+    N steps equal k steps, save, restore into a fresh handle, N-k steps."""
+    st = to_f32(tgv64())
+    cfg = acm_mod.make_config(2, 64, 64, nu=0.01, precision="f32", graph_chunk=16)
+    a = acm_mod.Solver(cfg, st)
+    a.run(100)
+    full = a.state()
+    b = acm_mod.Solver(cfg, st)
+    b.run(37)
+    ck = b.state()
+    c = acm_mod.Solver(cfg, ck)
+    c.set_current(0, 37)
+    c.run(63)
+    out = c.state()
+    for k in full:
+        assert np.array_equal(full[k], out[k])
