@@ -34,7 +34,33 @@ def parse():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-only", action="store_true",
+                    help="time only the plain copy kernel (bandwidth / counter calibration)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     return ap.parse_args()
+
+
+def copy_bandwidth(mib: int, reps: int = 20):
+    """Achieved rate of the library's plain copy kernel: bytes read + written
+    per second for a `mib` MiB buffer (read mib, write mib per launch)."""
+    import torch
+    from paper_2012_03525_amd import acm
+    n = mib * (1 << 20)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        acm.stream_copy(dst, src, n, s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        acm.stream_copy(dst, src, n, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes_per_launch": 2 * n, "avg_launch_us": round(ms * 1e3, 2), "gbs": round(2 * n / (ms * 1e-3) / 1e9, 1)}
 
 
 def workload(name, tile):
@@ -103,6 +129,11 @@ def main():
     from paper_2012_03525_amd import acm
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     acm.lib()
+    if a.copy_only:
+        print(json.dumps({"copy": copy_bandwidth(a.copy_mib)}), flush=True)
+        return
+    copy = copy_bandwidth(1024)
+    print(f"[bench] plain copy kernel: {copy['gbs']} GB/s", file=sys.stderr, flush=True)
     cfg, st, meta, bpl, kname = workload(a.workload, a.tile)
     solver = acm.Solver(cfg, st)
     nodes = cfg.nx * cfg.ny * (cfg.nz if cfg.dim == 3 else 1)
@@ -152,6 +183,8 @@ def main():
             "bytes_per_lup": bpl,
             "lups_per_launch": nodes,
             "avg_launch_us": round(ms_per_step * 1e3, 3),
+            "copy_kernel_gbs": copy["gbs"],
+            "frac_of_copy": round(gbs / copy["gbs"], 4),
         },
         "state_check": {"nonfinite": d["nonfinite"], "ke": d["ke"], "step": d["step"]},
     }

@@ -156,6 +156,13 @@ void acm_destroy(acm_handle* h);
 /* Message of the last failing call on this thread ("" if none). */
 const char* acm_last_error(void);
 
+/* Plain device-to-device copy of `bytes` bytes (both pointers 16-byte
+ * aligned), asynchronous on `stream`.  Used to measure the practical copy
+ * bandwidth that the stencil kernels are compared with, and to calibrate
+ * hardware byte counters.  Returns ACM_EINVAL for NULL or misaligned
+ * pointers. */
+acm_status acm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
 /* Library version string. */
 const char* acm_version(void);
 

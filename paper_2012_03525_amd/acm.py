@@ -70,6 +70,7 @@ SIGNATURES = {
     "acm_destroy": (None, [ctypes.c_void_p]),
     "acm_last_error": (ctypes.c_char_p, []),
     "acm_version": (ctypes.c_char_p, []),
+    "acm_stream_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
 }
 
 
@@ -122,6 +123,14 @@ def stability(cfg: Config):
     amp, che = ctypes.c_double(), ctypes.c_double()
     check(lib().acm_stability(ctypes.byref(cfg), ctypes.byref(amp), ctypes.byref(che)))
     return amp.value, che.value
+
+
+def stream_copy(dst, src, nbytes: int, stream=None):
+    """Device copy through the library's plain copy kernel (torch tensors)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    check(lib().acm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                ctypes.c_size_t(nbytes), ctypes.c_void_p(s.cuda_stream)))
 
 
 def _names(cfg: Config):

@@ -1,0 +1,43 @@
+// Plain device copy used to calibrate bandwidth measurements: the achieved
+// copy rate is the practical ceiling the stencil kernels are compared with,
+// and its hardware byte counters give the scale factor for FETCH_SIZE /
+// WRITE_SIZE readings.
+#include "../../include/acm.h"
+#include "acm_internal.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void copy16_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                     size_t n16)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void copy1_kernel(const unsigned char* __restrict__ src,
+                                                    unsigned char* __restrict__ dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+}  // namespace
+
+extern "C" acm_status acm_stream_copy(void* dst, const void* src, size_t bytes, void* stream)
+{
+    if (bytes == 0) return ACM_OK;
+    if (!dst || !src) return ACM_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t n16 = bytes / 16;
+    if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16 != 0) return ACM_EINVAL;
+    if (n16) {
+        const int blocks = (int)std::min<size_t>((n16 + 255) / 256, 256 * 64);
+        hipLaunchKernelGGL(copy16_kernel, dim3(blocks), dim3(256), 0, s, static_cast<const uint4*>(src),
+                           static_cast<uint4*>(dst), n16);
+    }
+    const size_t tail = bytes - n16 * 16;
+    if (tail)
+        hipLaunchKernelGGL(copy1_kernel, dim3(1), dim3(256), 0, s, static_cast<const unsigned char*>(src) + n16 * 16,
+                           static_cast<unsigned char*>(dst) + n16 * 16, tail);
+    return hipGetLastError() == hipSuccess ? ACM_OK : ACM_EHIP;
+}

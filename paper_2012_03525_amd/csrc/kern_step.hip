@@ -16,6 +16,8 @@
 // The code is compiled with -ffp-contract=off; every fma is explicit, so the
 // per-node result does not depend on the tile shape or on the kernel that
 // calls the tile function (the batched kernel relies on this).
+#include <type_traits>
+
 #include "acm_internal.h"
 
 namespace acm {
@@ -224,37 +226,78 @@ template hipError_t launch_step2d<double>(const Coef<double>&, const State<doubl
 // resident in LDS as a ring; drho' is computed one plane ahead on the tile
 // plus a one-node ring, so every node's drho' is formed exactly once per
 // workgroup.  Plane k+3 is fetched into registers while plane k is computed.
+//
+// GEN = false is the fast path for fully periodic boxes with rho0 = 1: no
+// ghost transforms, m = u + drho u.  GEN = true handles every boundary type
+// and any rho0.  Both evaluate the same expressions, so a periodic rho0 = 1
+// case gives identical bits on either path.
 // ===========================================================================
-template <int TX, int TY>
+template <int TX, int TY, int RPT>
 struct Shape3 {
     static constexpr int RX = TX + 4, RY = TY + 4, RXY = RX * RY;
     static constexpr int DX = TX + 2, DY = TY + 2, DXY = DX * DY;
-    static constexpr int NT = TX * TY;
+    static constexpr int NT = TX * TY / RPT;        // threads; each owns RPT rows of one column
+    static constexpr int YS = TY / RPT;             // row stride between a thread's rows
     static constexpr int NL = (RXY + NT - 1) / NT;  // plane points staged per thread
+    static constexpr int ND = (DXY + NT - 1) / NT;  // drho' points per thread
 };
 
+template <bool GEN, typename T>
+__device__ __forceinline__ T mom3(T r, T u, T rho0)
+{
+    if constexpr (GEN) return fmaT(r, u, rho0 * u);
+    else return fmaT(r, u, u);
+}
+
 // drho' at R-index e of plane slot (cur), with the planes below / above.
-template <typename T, int RX>
+template <bool GEN, typename T, int RX>
 __device__ __forceinline__ T rho_new_3d(const Coef<T>& c, const T* r0, const T* u0, const T* v0,
                                         const T* rD, const T* wD, const T* rU, const T* wU, int e)
 {
     const T rc = r0[e];
     const T rE = r0[e + 1], rW = r0[e - 1], rN = r0[e + RX], rS = r0[e - RX];
     const T rUp = rU[e], rDn = rD[e];
-    const T mE = momc(rE, u0[e + 1], c.rho0), mW = momc(rW, u0[e - 1], c.rho0);
-    const T mN = momc(rN, v0[e + RX], c.rho0), mS = momc(rS, v0[e - RX], c.rho0);
-    const T mU = momc(rUp, wU[e], c.rho0), mD = momc(rDn, wD[e], c.rho0);
+    const T mE = mom3<GEN>(rE, u0[e + 1], c.rho0), mW = mom3<GEN>(rW, u0[e - 1], c.rho0);
+    const T mN = mom3<GEN>(rN, v0[e + RX], c.rho0), mS = mom3<GEN>(rS, v0[e - RX], c.rho0);
+    const T mU = mom3<GEN>(rUp, wU[e], c.rho0), mD = mom3<GEN>(rDn, wD[e], c.rho0);
     const T div = ((mE - mW) + (mN - mS)) + (mU - mD);
     const T lap = (((rE + rW) + (rN + rS)) + (rUp + rDn)) - T(6) * rc;
     return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
 }
 
-template <typename T, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void step3d_kernel(Coef<T> c, State<T> in, State<T> out, int zc,
-                                                          int nbx, int nby)
+// Buffer-resource access for the z-march: one descriptor per field and plane
+// (scalar registers), 32-bit lane byte offsets fixed for the whole march.
+// The hardware range-checks every access against the plane size.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes)
 {
-    using S = Shape3<TX, TY>;
-    constexpr int RX = S::RX, RXY = S::RXY, DX = S::DX, DXY = S::DXY, NT = S::NT, NL = S::NL;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+// streaming (non-temporal) store: the new state is not re-read in this step
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 2);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 2);
+}
+
+template <typename T, int TX, int TY, int RPT, bool GEN>
+__global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<T> in, State<T> out, int zc,
+                                                                int nbx, int nby)
+{
+    using S = Shape3<TX, TY, RPT>;
+    constexpr int RX = S::RX, RXY = S::RXY, DX = S::DX, DXY = S::DXY, NT = S::NT, NL = S::NL, ND = S::ND;
+    constexpr int YS = S::YS;
     __shared__ T sr[4][RXY], su[4][RXY], sv[4][RXY], sw[4][RXY];
     __shared__ T sd[2][DXY];
 
@@ -263,43 +306,42 @@ __global__ __launch_bounds__(TX * TY) void step3d_kernel(Coef<T> c, State<T> in,
     const int t1 = lb / nbx;
     const int by = t1 % nby, bz = t1 / nby;
     const int x0 = bx * TX, y0 = by * TY;
-    const int z0 = bz * zc;
+    const int z0 = bz * zc;  // zc is a multiple of 16, so z0 % 4 == 0
     const int z1 = min(z0 + zc, c.nz);
     const int nx = c.nx, ny = c.ny, nz = c.nz;
-    const size_t plane = (size_t)nx * ny;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const unsigned pbytes = plane * (unsigned)sizeof(T);
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
-    const int gx = x0 + tx, gy = y0 + ty;
-    const bool active = (gx < nx) && (gy < ny);
-    const int eo = (ty + 2) * RX + (tx + 2);  // own node in R coordinates
-    const int dO = (ty + 1) * DX + (tx + 1);  // own node in D coordinates
+    const int tx = tid % TX, tyb = tid / TX;
+    const int gx = x0 + tx;
     const bool inplane_interior = (x0 >= 2) && (x0 + TX + 2 <= nx) && (y0 >= 2) && (y0 + TY + 2 <= ny);
-    const bool zperiodic = (c.bc[4] == BC_PERIODIC);
+    const bool zperiodic = GEN ? (c.bc[4] == BC_PERIODIC) : true;
 
-    // per-thread staging map: in-plane source offset and crossed faces
-    int soff[NL];
+    // per-thread staging map: in-plane byte offset and crossed faces.
+    // Padding lanes (q >= RXY) load a valid duplicate and skip the LDS store.
+    unsigned voff[NL];
     signed char sfx[NL], sfy[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
         const int q = tid + i * NT;
-        const int qq = q < RXY ? q : 0;
+        const int qq = q < RXY ? q : tid;
         const int ly = qq / RX, lx = qq - ly * RX;
         int fx, fy;
         const int sx = map_coord(x0 + lx - 2, nx, c.bc[0], 0, fx);
         const int sy = map_coord(y0 + ly - 2, ny, c.bc[2], 2, fy);
-        soff[i] = sy * nx + sx;
+        voff[i] = ((unsigned)sy * (unsigned)nx + (unsigned)sx) * (unsigned)sizeof(T);
         sfx[i] = (signed char)fx;
         sfy[i] = (signed char)fy;
     }
     // drho' ring positions (mirror substitution for wall / symmetry ghosts)
-    int dsrc[(DXY + NT - 1) / NT];
+    int dsrc[ND];
 #pragma unroll
-    for (int i = 0; i < (DXY + NT - 1) / NT; ++i) {
+    for (int i = 0; i < ND; ++i) {
         const int q = tid + i * NT;
         const int qq = q < DXY ? q : 0;
         const int ly = qq / DX, lx = qq - ly * DX;
         int ex = lx + 1, ey = ly + 1;
-        if (!inplane_interior && c.nonperiodic) {
+        if (GEN && !inplane_interior && c.nonperiodic) {
             const int mx = mirror_coord(x0 + lx - 1, nx, c.bc[0]);
             const int my = mirror_coord(y0 + ly - 1, ny, c.bc[2]);
             ex = min(max(mx - x0 + 2, 1), DX);
@@ -307,164 +349,214 @@ __global__ __launch_bounds__(TX * TY) void step3d_kernel(Coef<T> c, State<T> in,
         }
         dsrc[i] = ey * RX + ex;
     }
+    // output byte offsets of the thread's nodes (same in every plane)
+    unsigned ooff[RPT];
+    bool oact[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int gy = y0 + tyb + r * YS;
+        oact[r] = (gx < nx) && (gy < ny);
+        ooff[r] = oact[r] ? ((unsigned)gy * (unsigned)nx + (unsigned)gx) * (unsigned)sizeof(T) : 0u;
+    }
 
-    T pr[NL], pu[NL], pv[NL], pw[NL];
-    // fetch plane gz into registers (ghost planes mapped, velocity rules applied)
-    auto fetch = [&](int gz) {
+    T pr[2][NL], pu[2][NL], pv[2][NL], pw[2][NL];
+    // fetch plane gz into register set b (ghost planes mapped, velocity rules applied)
+    auto fetch = [&](int gz, auto bset) {
+        constexpr int b = decltype(bset)::value;
         int fz;
         const int sz = map_coord(gz, nz, c.bc[4], 4, fz);
         const size_t base = (size_t)sz * plane;
+        const auto rr = plane_rsrc(in.r + base, pbytes), ru = plane_rsrc(in.u + base, pbytes);
+        const auto rv = plane_rsrc(in.v + base, pbytes), rw = plane_rsrc(in.w + base, pbytes);
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
-            if (tid + i * NT < RXY) {
-                const size_t s = base + soff[i];
-                pr[i] = in.r[s];
-                pu[i] = in.u[s];
-                pv[i] = in.v[s];
-                pw[i] = in.w[s];
-                if (c.nonperiodic) {
-                    const int f0 = sfx[i], f1 = sfy[i];
-                    if (f0 >= 0) {
-                        pu[i] = fmaT(c.fs[f0][0], pu[i], c.fo[f0][0]);
-                        pv[i] = fmaT(c.fs[f0][1], pv[i], c.fo[f0][1]);
-                        pw[i] = fmaT(c.fs[f0][2], pw[i], c.fo[f0][2]);
-                    }
-                    if (f1 >= 0) {
-                        pu[i] = fmaT(c.fs[f1][0], pu[i], c.fo[f1][0]);
-                        pv[i] = fmaT(c.fs[f1][1], pv[i], c.fo[f1][1]);
-                        pw[i] = fmaT(c.fs[f1][2], pw[i], c.fo[f1][2]);
-                    }
-                    if (fz >= 0) {
-                        pu[i] = fmaT(c.fs[fz][0], pu[i], c.fo[fz][0]);
-                        pv[i] = fmaT(c.fs[fz][1], pv[i], c.fo[fz][1]);
-                        pw[i] = fmaT(c.fs[fz][2], pw[i], c.fo[fz][2]);
+            pr[b][i] = bload((T*)nullptr, rr, voff[i]);
+            pu[b][i] = bload((T*)nullptr, ru, voff[i]);
+            pv[b][i] = bload((T*)nullptr, rv, voff[i]);
+            pw[b][i] = bload((T*)nullptr, rw, voff[i]);
+        }
+        if constexpr (GEN) {
+            if (c.nonperiodic) {
+#pragma unroll
+                for (int i = 0; i < NL; ++i) {
+                    const int fc[3] = {sfx[i], sfy[i], fz};
+                    for (int a = 0; a < 3; ++a) {
+                        const int f = fc[a];
+                        if (f >= 0) {
+                            pu[b][i] = fmaT(c.fs[f][0], pu[b][i], c.fo[f][0]);
+                            pv[b][i] = fmaT(c.fs[f][1], pv[b][i], c.fo[f][1]);
+                            pw[b][i] = fmaT(c.fs[f][2], pw[b][i], c.fo[f][2]);
+                        }
                     }
                 }
             }
         }
     };
-    auto store = [&](int slot) {
+    auto store = [&](auto slotc, auto bset) {
+        constexpr int slot = decltype(slotc)::value;
+        constexpr int b = decltype(bset)::value;
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
             const int q = tid + i * NT;
-            if (q < RXY) {
-                sr[slot][q] = pr[i];
-                su[slot][q] = pu[i];
-                sv[slot][q] = pv[i];
-                sw[slot][q] = pw[i];
+            if ((i + 1) * NT <= RXY || q < RXY) {
+                sr[slot][q] = pr[b][i];
+                su[slot][q] = pu[b][i];
+                sv[slot][q] = pv[b][i];
+                sw[slot][q] = pw[b][i];
             }
         }
     };
-    // drho' of plane p (slot sp) on the tile + ring into sd[dslot]
-    auto ring = [&](int p, int dslot) {
-        const int s0 = p & 3, sD = (p - 1) & 3, sU = (p + 1) & 3;
+    // drho' of the plane in slot S0 (below SD, above SU) on the tile + ring into sd[DS]
+    auto ring = [&](auto s0c, auto dsc) {
+        constexpr int s0 = decltype(s0c)::value, sD = (s0 + 3) & 3, sU = (s0 + 1) & 3;
+        constexpr int ds = decltype(dsc)::value;
 #pragma unroll
-        for (int i = 0; i < (DXY + NT - 1) / NT; ++i) {
+        for (int i = 0; i < ND; ++i) {
             const int q = tid + i * NT;
-            if (q < DXY)
-                sd[dslot][q] = rho_new_3d<T, RX>(c, sr[s0], su[s0], sv[s0], sr[sD], sw[sD], sr[sU], sw[sU],
-                                                 dsrc[i]);
+            if ((i + 1) * NT <= DXY || q < DXY)
+                sd[ds][q] = rho_new_3d<GEN, T, RX>(c, sr[s0], su[s0], sv[s0], sr[sD], sw[sD], sr[sU], sw[sU],
+                                                   dsrc[i]);
         }
     };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
 
-    // ---- prologue: planes z0-2 .. z0+1, drho'(z0-1) own node, drho'(z0) ring
-    for (int p = z0 - 2; p <= z0 + 1; ++p) {
-        fetch(p);
-        store(p & 3);
-    }
-    fetch(z0 + 2);  // in flight during the prologue compute
+    // ---- prologue (z0 % 4 == 0): planes z0-2 .. z0+1 resident, z0+2 and z0+3 in flight
+    fetch(z0 - 2, I0{});
+    fetch(z0 - 1, I1{});
+    store(I2{}, I0{});
+    store(I3{}, I1{});
+    fetch(z0, I0{});
+    fetch(z0 + 1, I1{});
+    store(I0{}, I0{});
+    store(I1{}, I1{});
+    fetch(z0 + 2, I0{});
+    fetch(z0 + 3, I1{});
     __syncthreads();
-    ring(z0, z0 & 1);
-    T rn_prev = T(0);
-    if (zperiodic || z0 > 0) {
-        // drho'(z0-1) at the own node (planes z0-2, z0-1, z0 are resident)
-        const int p = z0 - 1;
-        rn_prev = rho_new_3d<T, RX>(c, sr[p & 3], su[p & 3], sv[p & 3], sr[(p - 1) & 3], sw[(p - 1) & 3],
-                                    sr[(p + 1) & 3], sw[(p + 1) & 3], eo);
+    ring(I0{}, I0{});
+    T rn_prev[RPT], r_prev[RPT], u_prev[RPT], v_prev[RPT], w_prev[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int eo = (tyb + r * YS + 2) * RX + (tx + 2);
+        rn_prev[r] = T(0);
+        if (zperiodic || z0 > 0)  // drho'(z0-1) at the own node: planes z0-2, z0-1, z0 are resident
+            rn_prev[r] = rho_new_3d<GEN, T, RX>(c, sr[3], su[3], sv[3], sr[2], sw[2], sr[0], sw[0], eo);
     }
     __syncthreads();
-    if (!(zperiodic || z0 > 0)) rn_prev = sd[z0 & 1][dO];  // wall / symmetry at z = 0: mirror
-    // own-node values of plane z0-1
-    T r_prev = sr[(z0 - 1) & 3][eo], u_prev = su[(z0 - 1) & 3][eo];
-    T v_prev = sv[(z0 - 1) & 3][eo], w_prev = sw[(z0 - 1) & 3][eo];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int eo = (tyb + r * YS + 2) * RX + (tx + 2);
+        const int dO = (tyb + r * YS + 1) * DX + (tx + 1);
+        if (!(zperiodic || z0 > 0)) rn_prev[r] = sd[0][dO];  // wall / symmetry at z = 0: mirror
+        r_prev[r] = sr[3][eo];
+        u_prev[r] = su[3][eo];
+        v_prev[r] = sv[3][eo];
+        w_prev[r] = sw[3][eo];
+    }
 
     const T rho0 = c.rho0, cs2 = c.cs2;
-    for (int k = z0; k < z1; ++k) {
-        store((k + 2) & 3);  // plane k+2 (its slot held plane k-2)
-        if (k + 3 <= z1 + 1) fetch(k + 3);
+    // one plane; J = k mod 4 fixes every LDS slot and register set at compile time
+    auto iterate = [&](int k, auto jc) {
+        constexpr int J = decltype(jc)::value;
+        constexpr int s0 = J, sU = (J + 1) & 3, s2 = (J + 2) & 3;
+        using BS = std::integral_constant<int, J & 1>;
+        store(std::integral_constant<int, s2>{}, BS{});  // plane k+2 (its slot held plane k-2)
+        if (k + 4 <= z1 + 1) fetch(k + 4, BS{});
         __syncthreads();
         const bool upper_ghost = (!zperiodic) && (k + 1 >= nz);
-        if (!upper_ghost) ring(k + 1, (k + 1) & 1);
+        if (!upper_ghost) ring(std::integral_constant<int, sU>{}, std::integral_constant<int, (J + 1) & 1>{});
         __syncthreads();
 
-        const int s0 = k & 3, sU = (k + 1) & 3;
         const T* r0 = sr[s0];
         const T* u0 = su[s0];
         const T* v0 = sv[s0];
         const T* w0 = sw[s0];
-        const T* dc = sd[k & 1];
-        const T rc = r0[eo], uc = u0[eo], vc = v0[eo], wc = w0[eo];
-        const T rnC = dc[dO];
-        const T rn_next = upper_ghost ? rnC : sd[(k + 1) & 1][dO];
-        if (active) {
-            const int e = eo;
-            const T rE = r0[e + 1], rW = r0[e - 1], rN = r0[e + RX], rS = r0[e - RX];
-            const T rU = sr[sU][e], rD = r_prev;
-            const T uE = u0[e + 1], uW = u0[e - 1], uN = u0[e + RX], uS = u0[e - RX];
-            const T vE = v0[e + 1], vW = v0[e - 1], vN = v0[e + RX], vS = v0[e - RX];
-            const T wE = w0[e + 1], wW = w0[e - 1], wN = w0[e + RX], wS = w0[e - RX];
-            const T uU = su[sU][e], vU = sv[sU][e], wU = sw[sU][e];
-            const T uD = u_prev, vD = v_prev, wD = w_prev;
+        const T* dc = sd[J & 1];
+        const T* dn = sd[(J + 1) & 1];
+        const size_t ob = (size_t)k * plane;
+        const auto orr = plane_rsrc(out.r + ob, pbytes), ou = plane_rsrc(out.u + ob, pbytes);
+        const auto ov = plane_rsrc(out.v + ob, pbytes), ow = plane_rsrc(out.w + ob, pbytes);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int ty = tyb + r * YS;
+            const int e = (ty + 2) * RX + (tx + 2);
+            const int dO = (ty + 1) * DX + (tx + 1);
+            const T rc = r0[e], uc = u0[e], vc = v0[e], wc = w0[e];
+            const T rnC = dc[dO];
+            const T rn_next = upper_ghost ? rnC : dn[dO];
+            if (oact[r]) {
+                const T rE = r0[e + 1], rW = r0[e - 1], rN = r0[e + RX], rS = r0[e - RX];
+                const T rU = sr[sU][e], rD = r_prev[r];
+                const T uE = u0[e + 1], uW = u0[e - 1], uN = u0[e + RX], uS = u0[e - RX];
+                const T vE = v0[e + 1], vW = v0[e - 1], vN = v0[e + RX], vS = v0[e - RX];
+                const T wE = w0[e + 1], wW = w0[e - 1], wN = w0[e + RX], wS = w0[e - RX];
+                const T uU = su[sU][e], vU = sv[sU][e], wU = sw[sU][e];
+                const T uD = u_prev[r], vD = v_prev[r], wD = w_prev[r];
 
-            const T mxC = momc(rc, uc, rho0), myC = momc(rc, vc, rho0), mzC = momc(rc, wc, rho0);
-            const T mxE = momc(rE, uE, rho0), myE = momc(rE, vE, rho0), mzE = momc(rE, wE, rho0);
-            const T mxW = momc(rW, uW, rho0), myW = momc(rW, vW, rho0), mzW = momc(rW, wW, rho0);
-            const T mxN = momc(rN, uN, rho0), myN = momc(rN, vN, rho0), mzN = momc(rN, wN, rho0);
-            const T mxS = momc(rS, uS, rho0), myS = momc(rS, vS, rho0), mzS = momc(rS, wS, rho0);
-            const T mxU = momc(rU, uU, rho0), myU = momc(rU, vU, rho0), mzU = momc(rU, wU, rho0);
-            const T mxD = momc(rD, uD, rho0), myD = momc(rD, vD, rho0), mzD = momc(rD, wD, rho0);
+                const T mxC = mom3<GEN>(rc, uc, rho0), myC = mom3<GEN>(rc, vc, rho0), mzC = mom3<GEN>(rc, wc, rho0);
+                const T mxE = mom3<GEN>(rE, uE, rho0), myE = mom3<GEN>(rE, vE, rho0), mzE = mom3<GEN>(rE, wE, rho0);
+                const T mxW = mom3<GEN>(rW, uW, rho0), myW = mom3<GEN>(rW, vW, rho0), mzW = mom3<GEN>(rW, wW, rho0);
+                const T mxN = mom3<GEN>(rN, uN, rho0), myN = mom3<GEN>(rN, vN, rho0), mzN = mom3<GEN>(rN, wN, rho0);
+                const T mxS = mom3<GEN>(rS, uS, rho0), myS = mom3<GEN>(rS, vS, rho0), mzS = mom3<GEN>(rS, wS, rho0);
+                const T mxU = mom3<GEN>(rU, uU, rho0), myU = mom3<GEN>(rU, vU, rho0), mzU = mom3<GEN>(rU, wU, rho0);
+                const T mxD = mom3<GEN>(rD, uD, rho0), myD = mom3<GEN>(rD, vD, rho0), mzD = mom3<GEN>(rD, wD, rho0);
 
-            const T fxx = ((fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + (mxN * vN - mxS * vS)) +
-                          (mxU * wU - mxD * wD);
-            const T fyy = ((myE * uE - myW * uW) + (fmaT(myN, vN, cs2 * rN) - fmaT(myS, vS, cs2 * rS))) +
-                          (myU * wU - myD * wD);
-            const T fzz = ((mzE * uE - mzW * uW) + (mzN * vN - mzS * vS)) +
-                          (fmaT(mzU, wU, cs2 * rU) - fmaT(mzD, wD, cs2 * rD));
-            const T lpx = (((mxE + mxW) + (mxN + mxS)) + (mxU + mxD)) - T(6) * mxC;
-            const T lpy = (((myE + myW) + (myN + myS)) + (myU + myD)) - T(6) * myC;
-            const T lpz = (((mzE + mzW) + (mzN + mzS)) + (mzU + mzD)) - T(6) * mzC;
-            const T sx = (dc[dO + 1] - dc[dO - 1]) - (rE - rW);
-            const T sy = (dc[dO + DX] - dc[dO - DX]) - (rN - rS);
-            const T sz = (rn_next - rn_prev) - (rU - rD);
-            const T rho_n = rho0 + rnC;
-            T gx_ = c.gdt[0];
-            if (c.fx) gx_ = fmaT(c.dt, c.fx[gy], gx_);
-            const T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lpx, -c.cg * fxx)));
-            const T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, lpy, -c.cg * fyy)));
-            const T dmz = fmaT(rho_n, c.gdt[2], fmaT(-c.ks, sz, fmaT(c.kv, lpz, -c.cg * fzz)));
-            const T drn = rnC - rc;
-            const T inv = recipT(rho_n);
-            const size_t o = (size_t)k * plane + (size_t)gy * nx + gx;
-            out.r[o] = rnC;
-            out.u[o] = fmaT(fmaT(-uc, drn, dmx), inv, uc);
-            out.v[o] = fmaT(fmaT(-vc, drn, dmy), inv, vc);
-            out.w[o] = fmaT(fmaT(-wc, drn, dmz), inv, wc);
+                // centred differences of drho (pressure term and density SAT share them)
+                const T gxr = rE - rW, gyr = rN - rS, gzr = rU - rD;
+                const T fxx = fmaT(cs2, gxr, ((mxE * uE - mxW * uW) + (mxN * vN - mxS * vS)) + (mxU * wU - mxD * wD));
+                const T fyy = fmaT(cs2, gyr, ((myE * uE - myW * uW) + (myN * vN - myS * vS)) + (myU * wU - myD * wD));
+                const T fzz = fmaT(cs2, gzr, ((mzE * uE - mzW * uW) + (mzN * vN - mzS * vS)) + (mzU * wU - mzD * wD));
+                const T lpx = fmaT(T(-6), mxC, ((mxE + mxW) + (mxN + mxS)) + (mxU + mxD));
+                const T lpy = fmaT(T(-6), myC, ((myE + myW) + (myN + myS)) + (myU + myD));
+                const T lpz = fmaT(T(-6), mzC, ((mzE + mzW) + (mzN + mzS)) + (mzU + mzD));
+                const T sx = (dc[dO + 1] - dc[dO - 1]) - gxr;
+                const T sy = (dc[dO + DX] - dc[dO - DX]) - gyr;
+                const T sz = (rn_next - rn_prev[r]) - gzr;
+                const T rho_n = rho0 + rnC;
+                T gx_ = c.gdt[0];
+                if (c.fx) gx_ = fmaT(c.dt, c.fx[y0 + ty], gx_);
+                const T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lpx, -c.cg * fxx)));
+                const T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, lpy, -c.cg * fyy)));
+                const T dmz = fmaT(rho_n, c.gdt[2], fmaT(-c.ks, sz, fmaT(c.kv, lpz, -c.cg * fzz)));
+                const T drn = rnC - rc;
+                const T inv = recipT(rho_n);
+                bstore(rnC, orr, ooff[r]);
+                bstore(fmaT(fmaT(-uc, drn, dmx), inv, uc), ou, ooff[r]);
+                bstore(fmaT(fmaT(-vc, drn, dmy), inv, vc), ov, ooff[r]);
+                bstore(fmaT(fmaT(-wc, drn, dmz), inv, wc), ow, ooff[r]);
+            }
+            r_prev[r] = rc;
+            u_prev[r] = uc;
+            v_prev[r] = vc;
+            w_prev[r] = wc;
+            rn_prev[r] = rnC;
         }
-        r_prev = rc;
-        u_prev = uc;
-        v_prev = vc;
-        w_prev = wc;
-        rn_prev = rnC;
+    };
+    int k = z0;
+    for (; k + 3 < z1; k += 4) {
+        iterate(k, I0{});
+        iterate(k + 1, I1{});
+        iterate(k + 2, I2{});
+        iterate(k + 3, I3{});
     }
+    if (k < z1) iterate(k, I0{});
+    if (k + 1 < z1) iterate(k + 1, I1{});
+    if (k + 2 < z1) iterate(k + 2, I2{});
 }
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, int RPT>
 static hipError_t launch3d_variant(const Coef<T>& c, const State<T>& in, const State<T>& out, int zc,
                                    hipStream_t s)
 {
     const int nbx = (c.nx + TX - 1) / TX, nby = (c.ny + TY - 1) / TY, nbz = (c.nz + zc - 1) / zc;
-    hipLaunchKernelGGL((step3d_kernel<T, TX, TY>), dim3(nbx * nby * nbz), dim3(TX * TY), 0, s, c, in, out, zc,
-                       nbx, nby);
+    const bool fast = !c.nonperiodic && c.rho0 == T(1);
+    const dim3 grid(nbx * nby * nbz), block(TX * TY / RPT);
+    if (fast)
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+    else
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true>), grid, block, 0, s, c, in, out, zc, nbx, nby);
     return hipGetLastError();
 }
 
@@ -475,12 +567,30 @@ hipError_t launch_step3d(const Coef<T>& c, const State<T>& in, const State<T>& o
     int zc = (tile >> 8) * 16;
     if (zc <= 0) zc = 64;
     if (zc > c.nz) zc = c.nz;
-    switch (tile & 0xff) {
-        case 1: return launch3d_variant<T, 32, 8>(c, in, out, zc, s);
-        case 2: return launch3d_variant<T, 64, 8>(c, in, out, zc, s);
-        case 3: return launch3d_variant<T, 32, 4>(c, in, out, zc, s);
-        case 4: return launch3d_variant<T, 64, 2>(c, in, out, zc, s);
-        default: return launch3d_variant<T, 64, 4>(c, in, out, zc, s);
+    int shape = tile & 0xff;
+    if constexpr (sizeof(T) == 8) {
+        // FP64 keeps one row per thread and moderate tiles (LDS and registers)
+        switch (shape) {
+            case 3: return launch3d_variant<T, 32, 4, 1>(c, in, out, zc, s);
+            case 4: return launch3d_variant<T, 64, 4, 1>(c, in, out, zc, s);
+            default: return launch3d_variant<T, 32, 8, 1>(c, in, out, zc, s);
+        }
+    } else {
+        switch (shape) {
+            case 1: return launch3d_variant<T, 32, 8, 1>(c, in, out, zc, s);
+            case 2: return launch3d_variant<T, 64, 8, 1>(c, in, out, zc, s);
+            case 3: return launch3d_variant<T, 32, 4, 1>(c, in, out, zc, s);
+            case 4: return launch3d_variant<T, 64, 4, 1>(c, in, out, zc, s);
+            case 5: return launch3d_variant<T, 64, 16, 2>(c, in, out, zc, s);
+            case 7: return launch3d_variant<T, 32, 16, 2>(c, in, out, zc, s);
+            case 8: return launch3d_variant<T, 128, 8, 2>(c, in, out, zc, s);
+            case 9: return launch3d_variant<T, 128, 4, 1>(c, in, out, zc, s);
+            case 10: return launch3d_variant<T, 256, 4, 2>(c, in, out, zc, s);
+            case 11: return launch3d_variant<T, 256, 2, 1>(c, in, out, zc, s);
+            case 6: return launch3d_variant<T, 64, 8, 2>(c, in, out, zc, s);
+            case 12: return launch3d_variant<T, 128, 8, 1>(c, in, out, zc, s);
+            default: return launch3d_variant<T, 64, 8, 1>(c, in, out, zc, s);  // measured best at 256^3
+        }
     }
 }
 
