@@ -156,6 +156,67 @@ void acm_destroy(acm_handle* h);
 /* Message of the last failing call on this thread ("" if none). */
 const char* acm_last_error(void);
 
+/* ------------------------------------------------------------------------ */
+/* Batched independent 2D cases (serving-style sweeps)                       */
+/* ------------------------------------------------------------------------ */
+/* Hundreds of independent single-phase 2D cases of uneven size advance
+ * together: each step is ONE persistent launch whose workgroups pop
+ * (case, tile) items from an atomic work queue and apply the same per-node
+ * arithmetic as acm_step (results are bitwise equal to running each case
+ * alone).  Steps are captured in HIP graphs of `chunk` steps; after every
+ * chunk a health check retires cases that finished or diverged. */
+typedef struct acm_batch acm_batch;
+
+typedef struct acm_batch_case {
+    acm_config cfg;        /* dim 2, single-phase; one precision per batch   */
+    acm_fields a, b;       /* caller-owned state sets; initial state in a    */
+    const void* force_x;   /* NULL or ny values added to g[0] on row j       */
+    int64_t nsteps;        /* steps to run (rounded up to whole chunks)      */
+    int32_t tile;          /* 2D tile variant 0..5, or -1 for the default    */
+} acm_batch_case;
+
+typedef struct acm_batch_opts {
+    int32_t chunk;         /* steps per captured graph, even; 0 = 500        */
+    int32_t blocks;        /* persistent workgroups; 0 = CUs x occupancy     */
+    int32_t grab;          /* queue items taken per atomic; 0 = 4            */
+    double umax_limit;     /* max |u| above this marks divergence; 0 = 0.3   */
+} acm_batch_opts;
+
+typedef struct acm_batch_case_status {
+    int64_t steps_done;
+    int32_t state;         /* 0 running, 1 finished, 2 diverged              */
+    int32_t which;         /* set holding the newest state (always 0: chunks are even) */
+    double done_ms;        /* batch start to the end of its last chunk; -1 while running */
+    double umax;           /* max |u| at the last health check               */
+} acm_batch_case_status;
+
+/* Validate every case (2D, single-phase, common precision, stability unless
+ * allow_unstable), upload the case table, size the persistent grid and
+ * capture the chunk graph.  Allocates small device tables (case records,
+ * item list, queue counters, health buffer) owned by the batch. */
+acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts,
+                          void* stream, acm_batch** out);
+
+/* Run up to max_chunks chunks (-1: until every case finished or diverged).
+ * Synchronises the stream once per chunk (health read-back).
+ * *active_left (may be NULL) receives the number of cases still running. */
+acm_status acm_batch_run(acm_batch* b, int32_t max_chunks, int32_t* active_left);
+
+/* Per-case progress, outcome and completion time. */
+acm_status acm_batch_status(const acm_batch* b, int32_t i, acm_batch_case_status* out);
+
+/* Wall time (GPU events) since the first run call and lattice-node updates done. */
+acm_status acm_batch_timing(const acm_batch* b, double* total_ms, int64_t* lattice_updates);
+
+void acm_batch_destroy(acm_batch* b);
+
+/* Tile autotuner: time `copies` periodic n x n cases for `steps` steps with
+ * every 2D tile variant (0..5) through the batched kernel; ms_per_tile[6]
+ * receives ms per step, *best the fastest variant.  Allocates and frees its
+ * own scratch fields.  The choice changes only speed, never results. */
+acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int32_t steps, void* stream,
+                              double* ms_per_tile, int32_t* best);
+
 /* Plain device-to-device copy of `bytes` bytes (both pointers 16-byte
  * aligned), asynchronous on `stream`.  Used to measure the practical copy
  * bandwidth that the stencil kernels are compared with, and to calibrate

@@ -53,6 +53,21 @@ class Diag(ctypes.Structure):
     ]
 
 
+class BatchCase(ctypes.Structure):
+    _fields_ = [("cfg", Config), ("a", Fields), ("b", Fields), ("force_x", ctypes.c_void_p),
+                ("nsteps", ctypes.c_int64), ("tile", ctypes.c_int32)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("blocks", ctypes.c_int32), ("grab", ctypes.c_int32),
+                ("umax_limit", ctypes.c_double)]
+
+
+class BatchCaseStatus(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int64), ("state", ctypes.c_int32), ("which", ctypes.c_int32),
+                ("done_ms", ctypes.c_double), ("umax", ctypes.c_double)]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 # exported symbols and their ctypes signatures (also checked by the CPU tests)
@@ -71,6 +86,16 @@ SIGNATURES = {
     "acm_last_error": (ctypes.c_char_p, []),
     "acm_version": (ctypes.c_char_p, []),
     "acm_stream_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "acm_batch_init": (ctypes.c_int, [ctypes.POINTER(BatchCase), ctypes.c_int32, ctypes.POINTER(BatchOpts),
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "acm_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "acm_batch_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(BatchCaseStatus)]),
+    "acm_batch_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    "acm_batch_destroy": (None, [ctypes.c_void_p]),
+    "acm_batch_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int32)]),
 }
 
 
@@ -223,3 +248,93 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+BATCH_RUNNING, BATCH_FINISHED, BATCH_DIVERGED = 0, 1, 2
+
+
+class Batch:
+    """Independent 2D single-phase cases advanced together by the batched
+    persistent kernel.  All states live in one arena tensor (6 fields per
+    case: set a then set b), sliced into per-case views."""
+
+    def __init__(self, cfgs, states, nsteps, tiles=None, chunk: int = 500, device: str = "cuda:0",
+                 umax_limit: float = 0.3, grab: int = 0, blocks: int = 0):
+        import torch
+        self.torch = torch
+        n = len(cfgs)
+        prec = cfgs[0].precision
+        self.dtype = torch.float64 if prec == F64 else torch.float32
+        sizes = [c.nx * c.ny for c in cfgs]
+        self.offsets = np.concatenate([[0], np.cumsum([6 * z for z in sizes])]).astype(np.int64)
+        self.arena = torch.empty(int(self.offsets[-1]), dtype=self.dtype, device=device)
+        self.views = []
+        arr = (BatchCase * n)()
+        for i, (c, st) in enumerate(zip(cfgs, states)):
+            o, z = int(self.offsets[i]), sizes[i]
+            v = [self.arena[o + f * z:o + (f + 1) * z].view(c.ny, c.nx) for f in range(6)]
+            for f, k in enumerate(("drho", "u", "v")):
+                v[f].copy_(torch.from_numpy(np.ascontiguousarray(st[k], dtype=np.float64)).to(self.dtype))
+            self.views.append(v)
+            bc = arr[i]
+            bc.cfg = c
+            bc.a = Fields(v[0].data_ptr(), v[1].data_ptr(), v[2].data_ptr(), None, None)
+            bc.b = Fields(v[3].data_ptr(), v[4].data_ptr(), v[5].data_ptr(), None, None)
+            bc.force_x = None
+            bc.nsteps = int(nsteps[i])
+            bc.tile = -1 if tiles is None else int(tiles[i])
+        self._cases = arr
+        opts = BatchOpts(chunk, blocks, grab, umax_limit)
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check(lib().acm_batch_init(arr, n, ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h)))
+        self.h = h
+        self.n = n
+
+    def run(self, max_chunks: int = -1) -> int:
+        left = ctypes.c_int32()
+        check(lib().acm_batch_run(self.h, int(max_chunks), ctypes.byref(left)))
+        return left.value
+
+    def status(self, i: int) -> dict:
+        st = BatchCaseStatus()
+        check(lib().acm_batch_status(self.h, int(i), ctypes.byref(st)))
+        return {"steps_done": st.steps_done, "state": st.state, "which": st.which, "done_ms": st.done_ms,
+                "umax": st.umax}
+
+    def timing(self):
+        ms, lups = ctypes.c_double(), ctypes.c_int64()
+        check(lib().acm_batch_timing(self.h, ctypes.byref(ms), ctypes.byref(lups)))
+        return ms.value, lups.value
+
+    def state(self, i: int) -> Dict[str, np.ndarray]:
+        self.torch.cuda.synchronize()
+        w = self.status(i)["which"]
+        v = self.views[i][3 * w:3 * w + 3]
+        return {k: t.detach().to("cpu", dtype=self.torch.float64).numpy() for k, t in zip(("drho", "u", "v"), v)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().acm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(n: int, precision: str = "f32", copies: int = 0, steps: int = 100):
+    """Time every 2D tile variant on copies of an n x n case; returns
+    (best_tile, ms_per_step_per_tile)."""
+    import torch
+    if copies <= 0:
+        copies = max(1, (1 << 22) // (n * n))
+    ms = (ctypes.c_double * 6)()
+    best = ctypes.c_int32()
+    check(lib().acm_batch_autotune(int(n), {"f64": F64, "f32": F32}[precision], int(copies), int(steps),
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ms,
+                                   ctypes.byref(best)))
+    return best.value, list(ms)

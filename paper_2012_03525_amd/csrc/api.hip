@@ -160,6 +160,25 @@ Coef<T> make_coef(const acm_config& c, const void* force_x)
 
 }  // namespace
 
+namespace acm {
+// shared with the batched entry points (kern_batch.hip)
+void set_error(const std::string& msg) { g_err = msg; }
+acm_status api_validate(const acm_config* c, std::string& err)
+{
+    const acm_status s = validate(c);
+    err = g_err;
+    return s;
+}
+double api_max_amplification(const acm_config& c) { return max_amplification(c); }
+template <typename T>
+Coef<T> api_make_coef(const acm_config& c, const void* force_x)
+{
+    return make_coef<T>(c, force_x);
+}
+template Coef<float> api_make_coef<float>(const acm_config&, const void*);
+template Coef<double> api_make_coef<double>(const acm_config&, const void*);
+}  // namespace acm
+
 struct acm_handle {
     acm_config cfg;
     acm_fields set[2];

@@ -1,0 +1,491 @@
+// Batched independent 2D cases in one persistent launch per step.
+//
+// Every active (case, tile) pair is an item of a device table; a persistent
+// grid (CUs x occupancy workgroups) pops items `grab` at a time from an
+// atomic counter and runs the same tile function as the single-case kernel
+// (tile2d.h), so each case's result is bitwise equal to running it alone.
+// The last workgroup to finish resets the counter for the next launch.  A
+// chunk of steps is captured once as a HIP graph (the item table and its
+// length live in device memory, so the graph survives changes of the active
+// set); after each chunk a health kernel reduces max|u| and a non-finite
+// flag per case, and the host retires finished or diverged cases.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/acm.h"
+#include "acm_internal.h"
+#include "tile2d.h"
+
+namespace acm {
+
+template <typename T>
+struct BatchCaseDev {
+    Coef<T> c;
+    State<T> s[2];
+    int tile;
+};
+
+// tile shapes of the 2D kernels (same numbering as launch_step2d)
+constexpr int NTILE2D = 6;
+constexpr int TILE_W[NTILE2D] = {64, 32, 64, 16, 128, 32};
+constexpr int TILE_H[NTILE2D] = {4, 8, 8, 16, 4, 16};
+
+template <typename T>
+constexpr size_t batch_lds_bytes()
+{
+    size_t m = tile2d_lds_bytes<T, 64, 4>();
+    m = std::max(m, tile2d_lds_bytes<T, 32, 8>());
+    m = std::max(m, tile2d_lds_bytes<T, 64, 8>());
+    m = std::max(m, tile2d_lds_bytes<T, 16, 16>());
+    m = std::max(m, tile2d_lds_bytes<T, 128, 4>());
+    m = std::max(m, tile2d_lds_bytes<T, 32, 16>());
+    return m;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_step_kernel(const BatchCaseDev<T>* __restrict__ cases,
+                                                          const int4* __restrict__ items,
+                                                          const int* __restrict__ nitems, int* queue, int parity,
+                                                          int grab)
+{
+    __shared__ __align__(16) char smem[batch_lds_bytes<T>()];
+    __shared__ int s_first;
+    const int n = *nitems;
+    for (;;) {
+        if (threadIdx.x == 0) s_first = atomicAdd(&queue[0], grab);
+        __syncthreads();
+        const int first = s_first;
+        __syncthreads();
+        if (first >= n) break;
+        const int last = min(first + grab, n);
+        for (int t = first; t < last; ++t) {
+            const int4 it = items[t];
+            const BatchCaseDev<T>& bc = cases[it.x];
+            const State<T> in = bc.s[parity], out = bc.s[parity ^ 1];
+            switch (bc.tile) {
+                case 1: tile2d<T, 32, 8, 256>(bc.c, in, out, it.y * 32, it.z * 8, smem); break;
+                case 2: tile2d<T, 64, 8, 256>(bc.c, in, out, it.y * 64, it.z * 8, smem); break;
+                case 3: tile2d<T, 16, 16, 256>(bc.c, in, out, it.y * 16, it.z * 16, smem); break;
+                case 4: tile2d<T, 128, 4, 256>(bc.c, in, out, it.y * 128, it.z * 4, smem); break;
+                case 5: tile2d<T, 32, 16, 256>(bc.c, in, out, it.y * 32, it.z * 16, smem); break;
+                default: tile2d<T, 64, 4, 256>(bc.c, in, out, it.y * 64, it.z * 4, smem); break;
+            }
+            __syncthreads();  // the next item reuses the LDS tile
+        }
+    }
+    if (threadIdx.x == 0) {
+        const int d = atomicAdd(&queue[1], 1);
+        if (d == (int)gridDim.x - 1) {  // every workgroup has left the loop: reset for the next launch
+            queue[0] = 0;
+            queue[1] = 0;
+        }
+    }
+}
+
+// One workgroup per active case: max |u| and a non-finite flag.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_health_kernel(const BatchCaseDev<T>* __restrict__ cases,
+                                                            const int* __restrict__ active, int parity,
+                                                            double* health)
+{
+    const int ci = active[blockIdx.x];
+    const BatchCaseDev<T>& bc = cases[ci];
+    const State<T> s = bc.s[parity];
+    const size_t n = (size_t)bc.c.nx * bc.c.ny;
+    double m = 0.0;
+    int bad = 0;
+    for (size_t i = threadIdx.x; i < n; i += 256) {
+        const double u = (double)s.u[i], v = (double)s.v[i], r = (double)s.r[i];
+        const double q = u * u + v * v;
+        if (!isfinite(q + r)) bad = 1;
+        else m = fmax(m, q);
+    }
+    __shared__ double red[256];
+    __shared__ int rbad[256];
+    red[threadIdx.x] = m;
+    rbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+            rbad[threadIdx.x] |= rbad[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        health[2 * ci] = sqrt(red[0]);
+        health[2 * ci + 1] = (double)rbad[0];
+    }
+}
+
+}  // namespace acm
+
+using namespace acm;
+
+// defined in api.hip
+namespace acm {
+void set_error(const std::string& msg);
+acm_status api_validate(const acm_config* c, std::string& err);
+double api_max_amplification(const acm_config& c);
+template <typename T>
+Coef<T> api_make_coef(const acm_config& c, const void* force_x);
+}  // namespace acm
+
+namespace {
+acm_status bfail(acm_status s, const std::string& m)
+{
+    set_error(m);
+    return s;
+}
+}  // namespace
+
+struct acm_batch {
+    int n = 0;
+    int precision = ACM_F32;
+    int chunk = 500;
+    int blocks = 0;
+    int grab = 4;
+    double umax_limit = 0.3;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* dcases = nullptr;   // BatchCaseDev<T>[n]
+    int4* ditems = nullptr;
+    int* dnitems = nullptr;
+    int* dqueue = nullptr;
+    int* dactive = nullptr;
+    double* dhealth = nullptr;
+    int4* hitems = nullptr;   // pinned
+    int* hnitems = nullptr;   // pinned
+    int* hactive = nullptr;   // pinned
+    double* hhealth = nullptr;  // pinned
+    size_t max_items = 0;
+    std::vector<int> tile, nx, ny, state;
+    std::vector<int64_t> nsteps, done;
+    std::vector<double> done_ms, umax;
+    hipEvent_t ev_start = nullptr, ev_chunk = nullptr;
+    bool started = false;
+    double elapsed_ms = 0.0;
+    int64_t lups = 0;
+};
+
+namespace {
+
+template <typename T>
+hipError_t upload_cases(acm_batch* b, const acm_batch_case* cases)
+{
+    std::vector<BatchCaseDev<T>> h(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        h[i].c = api_make_coef<T>(cases[i].cfg, cases[i].force_x);
+        const acm_fields* f[2] = {&cases[i].a, &cases[i].b};
+        for (int s = 0; s < 2; ++s)
+            h[i].s[s] = State<T>{static_cast<T*>(f[s]->drho), static_cast<T*>(f[s]->u), static_cast<T*>(f[s]->v),
+                                 nullptr, nullptr};
+        h[i].tile = b->tile[i];
+    }
+    hipError_t e = hipMalloc(&b->dcases, sizeof(BatchCaseDev<T>) * b->n);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b->dcases, h.data(), sizeof(BatchCaseDev<T>) * b->n, hipMemcpyHostToDevice);
+}
+
+template <typename T>
+hipError_t launch_batch_step(acm_batch* b, int parity, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_step_kernel<T>), dim3(b->blocks), dim3(256), 0, s,
+                       static_cast<const BatchCaseDev<T>*>(b->dcases), b->ditems, b->dnitems, b->dqueue, parity,
+                       b->grab);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_health(acm_batch* b, int nact, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_health_kernel<T>), dim3(nact), dim3(256), 0, s,
+                       static_cast<const BatchCaseDev<T>*>(b->dcases), b->dactive, 0, b->dhealth);
+    return hipGetLastError();
+}
+
+template <typename T>
+int occupancy_blocks()
+{
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_step_kernel<T>, 256, 0) != hipSuccess) return 0;
+    return std::max(1, ncu * std::max(1, per));
+}
+
+acm_status build_graph(acm_batch* b)
+{
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(ACM_EHIP, std::string("capture: ") + hipGetErrorString(e));
+    for (int i = 0; i < b->chunk; ++i) {
+        e = (b->precision == ACM_F64) ? launch_batch_step<double>(b, i & 1, b->cap)
+                                      : launch_batch_step<float>(b, i & 1, b->cap);
+        if (e != hipSuccess) break;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return bfail(ACM_EHIP, std::string("batch capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return bfail(ACM_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+    return ACM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts, void* stream,
+                          acm_batch** out)
+{
+    set_error("");
+    if (!out || !cases || ncases <= 0) return bfail(ACM_EINVAL, "cases / out / ncases invalid");
+    *out = nullptr;
+    const int prec = cases[0].cfg.precision;
+    const int chunk = (opts && opts->chunk > 0) ? opts->chunk : 500;
+    if (chunk % 2) return bfail(ACM_EINVAL, "chunk must be even");
+    for (int i = 0; i < ncases; ++i) {
+        const acm_batch_case& k = cases[i];
+        std::string err;
+        if (api_validate(&k.cfg, err) != ACM_OK) return bfail(ACM_EINVAL, "case " + std::to_string(i) + ": " + err);
+        if (k.cfg.dim != 2 || k.cfg.two_phase) return bfail(ACM_EINVAL, "batched cases are 2D single-phase");
+        if (k.cfg.precision != prec) return bfail(ACM_EINVAL, "every case of a batch needs the same precision");
+        if (!k.a.drho || !k.a.u || !k.a.v || !k.b.drho || !k.b.u || !k.b.v)
+            return bfail(ACM_EINVAL, "case " + std::to_string(i) + ": missing field pointers");
+        if (k.nsteps <= 0) return bfail(ACM_EINVAL, "nsteps must be positive");
+        if (k.tile < -1 || k.tile >= NTILE2D) return bfail(ACM_EINVAL, "tile must be -1..5");
+        if (!k.cfg.allow_unstable && api_max_amplification(k.cfg) > 1.0 + 1e-12)
+            return bfail(ACM_EUNSTABLE, "case " + std::to_string(i) + " fails the linear stability check");
+    }
+    acm_batch* b = new (std::nothrow) acm_batch();
+    if (!b) return bfail(ACM_EINVAL, "out of host memory");
+    b->n = ncases;
+    b->precision = prec;
+    b->chunk = chunk;
+    b->grab = (opts && opts->grab > 0) ? opts->grab : 4;
+    b->umax_limit = (opts && opts->umax_limit > 0) ? opts->umax_limit : 0.3;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->tile.resize(ncases);
+    b->nx.resize(ncases);
+    b->ny.resize(ncases);
+    b->state.assign(ncases, 0);
+    b->nsteps.resize(ncases);
+    b->done.assign(ncases, 0);
+    b->done_ms.assign(ncases, -1.0);
+    b->umax.assign(ncases, 0.0);
+    for (int i = 0; i < ncases; ++i) {
+        b->tile[i] = cases[i].tile >= 0 ? cases[i].tile : 0;
+        b->nx[i] = cases[i].cfg.nx;
+        b->ny[i] = cases[i].cfg.ny;
+        b->nsteps[i] = ((cases[i].nsteps + chunk - 1) / chunk) * chunk;
+        const int t = b->tile[i];
+        b->max_items += (size_t)((b->nx[i] + TILE_W[t] - 1) / TILE_W[t]) * ((b->ny[i] + TILE_H[t] - 1) / TILE_H[t]);
+    }
+    hipError_t e = (prec == ACM_F64) ? upload_cases<double>(b, cases) : upload_cases<float>(b, cases);
+    if (e == hipSuccess) e = hipMalloc(&b->ditems, sizeof(int4) * std::max<size_t>(1, b->max_items));
+    if (e == hipSuccess) e = hipMalloc(&b->dnitems, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&b->dqueue, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&b->dactive, sizeof(int) * ncases);
+    if (e == hipSuccess) e = hipMalloc(&b->dhealth, 2 * sizeof(double) * ncases);
+    if (e == hipSuccess) e = hipHostMalloc(&b->hitems, sizeof(int4) * std::max<size_t>(1, b->max_items), 0);
+    if (e == hipSuccess) e = hipHostMalloc(&b->hnitems, sizeof(int), 0);
+    if (e == hipSuccess) e = hipHostMalloc(&b->hactive, sizeof(int) * ncases, 0);
+    if (e == hipSuccess) e = hipHostMalloc(&b->hhealth, 2 * sizeof(double) * ncases, 0);
+    if (e == hipSuccess) e = hipMemset(b->dqueue, 0, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev_start);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev_chunk);
+    if (e != hipSuccess) {
+        acm_batch_destroy(b);
+        return bfail(ACM_EHIP, std::string("batch allocation: ") + hipGetErrorString(e));
+    }
+    b->blocks = (opts && opts->blocks > 0) ? opts->blocks
+                                           : (prec == ACM_F64 ? occupancy_blocks<double>() : occupancy_blocks<float>());
+    if (b->blocks <= 0) {
+        acm_batch_destroy(b);
+        return bfail(ACM_EHIP, "could not size the persistent grid");
+    }
+    acm_status st = build_graph(b);
+    if (st != ACM_OK) {
+        acm_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return ACM_OK;
+}
+
+acm_status acm_batch_run(acm_batch* b, int32_t max_chunks, int32_t* active_left)
+{
+    if (!b) return bfail(ACM_EINVAL, "batch is NULL");
+    hipError_t e;
+    if (!b->started) {
+        e = hipEventRecord(b->ev_start, b->stream);
+        if (e != hipSuccess) return bfail(ACM_EHIP, "event record");
+        b->started = true;
+    }
+    int chunks = 0;
+    for (;;) {
+        // active set and its item table (case-major order)
+        int nact = 0;
+        size_t nit = 0;
+        int64_t chunk_lups = 0;
+        for (int i = 0; i < b->n; ++i) {
+            if (b->state[i] != 0) continue;
+            b->hactive[nact++] = i;
+            const int t = b->tile[i];
+            const int tx = (b->nx[i] + TILE_W[t] - 1) / TILE_W[t], ty = (b->ny[i] + TILE_H[t] - 1) / TILE_H[t];
+            for (int y = 0; y < ty; ++y)
+                for (int x = 0; x < tx; ++x) b->hitems[nit++] = make_int4(i, x, y, 0);
+            chunk_lups += (int64_t)b->nx[i] * b->ny[i] * b->chunk;
+        }
+        if (active_left) *active_left = nact;
+        if (nact == 0 || (max_chunks >= 0 && chunks >= max_chunks)) break;
+        *b->hnitems = (int)nit;
+        e = hipMemcpyAsync(b->ditems, b->hitems, sizeof(int4) * nit, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->dnitems, b->hnitems, sizeof(int), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->dactive, b->hactive, sizeof(int) * nact, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+        if (e == hipSuccess)
+            e = (b->precision == ACM_F64) ? launch_health<double>(b, nact, b->stream)
+                                          : launch_health<float>(b, nact, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->hhealth, b->dhealth, 2 * sizeof(double) * b->n, hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_chunk, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return bfail(ACM_EHIP, std::string("batch chunk: ") + hipGetErrorString(e));
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, b->ev_start, b->ev_chunk);
+        b->elapsed_ms = ms;
+        b->lups += chunk_lups;
+        for (int a = 0; a < nact; ++a) {
+            const int i = b->hactive[a];
+            b->done[i] += b->chunk;
+            b->umax[i] = b->hhealth[2 * i];
+            const bool bad = b->hhealth[2 * i + 1] != 0.0 || !(b->umax[i] <= b->umax_limit);
+            if (bad) {
+                b->state[i] = 2;
+                b->done_ms[i] = ms;
+            } else if (b->done[i] >= b->nsteps[i]) {
+                b->state[i] = 1;
+                b->done_ms[i] = ms;
+            }
+        }
+        ++chunks;
+    }
+    return ACM_OK;
+}
+
+acm_status acm_batch_status(const acm_batch* b, int32_t i, acm_batch_case_status* out)
+{
+    if (!b || !out || i < 0 || i >= b->n) return bfail(ACM_EINVAL, "bad batch status query");
+    out->steps_done = b->done[i];
+    out->state = b->state[i];
+    out->which = 0;  // chunks have an even number of steps: the state is back in set a
+    out->done_ms = b->done_ms[i];
+    out->umax = b->umax[i];
+    return ACM_OK;
+}
+
+acm_status acm_batch_timing(const acm_batch* b, double* total_ms, int64_t* lattice_updates)
+{
+    if (!b) return bfail(ACM_EINVAL, "batch is NULL");
+    if (total_ms) *total_ms = b->elapsed_ms;
+    if (lattice_updates) *lattice_updates = b->lups;
+    return ACM_OK;
+}
+
+void acm_batch_destroy(acm_batch* b)
+{
+    if (!b) return;
+    hipStreamSynchronize(b->stream);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->cap) hipStreamDestroy(b->cap);
+    if (b->ev_start) hipEventDestroy(b->ev_start);
+    if (b->ev_chunk) hipEventDestroy(b->ev_chunk);
+    hipFree(b->dcases);
+    hipFree(b->ditems);
+    hipFree(b->dnitems);
+    hipFree(b->dqueue);
+    hipFree(b->dactive);
+    hipFree(b->dhealth);
+    if (b->hitems) hipHostFree(b->hitems);
+    if (b->hnitems) hipHostFree(b->hnitems);
+    if (b->hactive) hipHostFree(b->hactive);
+    if (b->hhealth) hipHostFree(b->hhealth);
+    delete b;
+}
+
+acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int32_t steps, void* stream,
+                              double* ms_per_tile, int32_t* best)
+{
+    if (n < 4 || copies <= 0 || steps <= 0 || steps % 2 || !ms_per_tile || !best)
+        return bfail(ACM_EINVAL, "autotune: bad arguments");
+    if (precision != ACM_F32 && precision != ACM_F64) return bfail(ACM_EINVAL, "autotune: precision");
+    const size_t es = precision == ACM_F64 ? 8 : 4;
+    const size_t field = (size_t)n * n * es;
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, field * 6 * (size_t)copies);
+    if (e != hipSuccess) return bfail(ACM_EHIP, "autotune allocation");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    e = hipMemsetAsync(mem, 0, field * 6 * (size_t)copies, s);
+    std::vector<acm_batch_case> cs(copies);
+    for (int i = 0; i < copies; ++i) {
+        acm_batch_case& k = cs[i];
+        std::memset(&k, 0, sizeof k);
+        k.cfg.dim = 2;
+        k.cfg.nx = k.cfg.ny = n;
+        k.cfg.nz = 1;
+        k.cfg.dx = k.cfg.dt = 1.0;
+        k.cfg.nu = 0.05;
+        k.cfg.rho0 = 1.0;
+        k.cfg.sat_rho = k.cfg.sat_mom = 1.0;
+        k.cfg.precision = precision;
+        char* base = static_cast<char*>(mem) + (size_t)i * 6 * field;
+        k.a = acm_fields{base, base + field, base + 2 * field, nullptr, nullptr};
+        k.b = acm_fields{base + 3 * field, base + 4 * field, base + 5 * field, nullptr, nullptr};
+        k.nsteps = steps;
+    }
+    acm_status st = ACM_OK;
+    double bestv = 1e300;
+    *best = 0;
+    for (int t = 0; t < NTILE2D && st == ACM_OK; ++t) {
+        for (auto& k : cs) k.tile = t;
+        acm_batch_opts o{};
+        o.chunk = steps;
+        acm_batch* b = nullptr;
+        st = acm_batch_init(cs.data(), copies, &o, stream, &b);
+        if (st != ACM_OK) break;
+        st = acm_batch_run(b, 1, nullptr);  // warm-up chunk
+        const auto t0 = std::chrono::steady_clock::now();
+        if (st == ACM_OK) {
+            for (int i = 0; i < copies; ++i) b->state[i] = 0, b->done[i] = 0;
+            st = acm_batch_run(b, 1, nullptr);
+        }
+        const auto t1 = std::chrono::steady_clock::now();
+        acm_batch_destroy(b);
+        ms_per_tile[t] = std::chrono::duration<double, std::milli>(t1 - t0).count() / steps;
+        if (ms_per_tile[t] < bestv) {
+            bestv = ms_per_tile[t];
+            *best = t;
+        }
+    }
+    hipStreamSynchronize(s);
+    hipFree(mem);
+    return st;
+}
+
+}  // extern "C"

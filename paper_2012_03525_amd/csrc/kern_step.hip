@@ -19,174 +19,13 @@
 #include <type_traits>
 
 #include "acm_internal.h"
+#include "tile2d.h"
 
 namespace acm {
 
-template <typename T>
-__device__ __forceinline__ T momc(T r, T u, T rho0) { return fmaT(r, u, rho0 * u); }
-
 // ===========================================================================
-// 2D
+// 2D (tile function in tile2d.h)
 // ===========================================================================
-template <int TX, int TY>
-struct Shape2 {
-    static constexpr int RX = TX + 4, RY = TY + 4, RXY = RX * RY;  // fields, halo 2
-    static constexpr int DX = TX + 2, DY = TY + 2, DXY = DX * DY;  // drho', halo 1
-};
-
-template <typename T, int TX, int TY>
-__host__ __device__ constexpr size_t tile2d_lds_bytes()
-{
-    return sizeof(T) * (3 * Shape2<TX, TY>::RXY + Shape2<TX, TY>::DXY);
-}
-
-// Continuity update at R-region index e (2D).
-template <typename T, int RX>
-__device__ __forceinline__ T rho_new_2d(const Coef<T>& c, const T* sr, const T* su, const T* sv, int e)
-{
-    const T rc = sr[e];
-    const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
-    const T mE = momc(rE, su[e + 1], c.rho0), mW = momc(rW, su[e - 1], c.rho0);
-    const T mN = momc(rN, sv[e + RX], c.rho0), mS = momc(rS, sv[e - RX], c.rho0);
-    const T div = (mE - mW) + (mN - mS);
-    const T lap = ((rE + rW) + (rN + rS)) - T(4) * rc;
-    return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
-}
-
-// Stage fields (drho, u, v) of the (TX+4)x(TY+4) region into LDS.
-template <typename T, int TX, int TY, int NT>
-__device__ __forceinline__ void stage2d(const Coef<T>& c, const State<T>& in, int x0, int y0,
-                                        bool interior, T* sr, T* su, T* sv)
-{
-    using S = Shape2<TX, TY>;
-    for (int q = threadIdx.x; q < S::RXY; q += NT) {
-        const int ly = q / S::RX, lx = q - ly * S::RX;
-        const int gx = x0 + lx - 2, gy = y0 + ly - 2;
-        T r, u, v;
-        if (interior) {
-            const size_t s = (size_t)gy * c.nx + gx;
-            r = in.r[s];
-            u = in.u[s];
-            v = in.v[s];
-        } else {
-            int fx, fy;
-            const int sx = map_coord(gx, c.nx, c.bc[0], 0, fx);
-            const int sy = map_coord(gy, c.ny, c.bc[2], 2, fy);
-            const size_t s = (size_t)sy * c.nx + sx;
-            r = in.r[s];
-            u = in.u[s];
-            v = in.v[s];
-            if (fx >= 0) {
-                u = fmaT(c.fs[fx][0], u, c.fo[fx][0]);
-                v = fmaT(c.fs[fx][1], v, c.fo[fx][1]);
-            }
-            if (fy >= 0) {
-                u = fmaT(c.fs[fy][0], u, c.fo[fy][0]);
-                v = fmaT(c.fs[fy][1], v, c.fo[fy][1]);
-            }
-        }
-        sr[q] = r;
-        su[q] = u;
-        sv[q] = v;
-    }
-}
-
-// drho' on the tile plus a one-node ring, into srn.
-template <typename T, int TX, int TY, int NT>
-__device__ __forceinline__ void rho_ring2d(const Coef<T>& c, int x0, int y0, bool interior,
-                                           const T* sr, const T* su, const T* sv, T* srn)
-{
-    using S = Shape2<TX, TY>;
-    for (int q = threadIdx.x; q < S::DXY; q += NT) {
-        const int ly = q / S::DX, lx = q - ly * S::DX;
-        int ex = lx + 1, ey = ly + 1;  // R-region coordinates
-        if (!interior && c.nonperiodic) {
-            // a wall / symmetry ghost takes the value of its mirror node
-            const int gx = mirror_coord(x0 + lx - 1, c.nx, c.bc[0]);
-            const int gy = mirror_coord(y0 + ly - 1, c.ny, c.bc[2]);
-            ex = min(max(gx - x0 + 2, 1), S::DX);
-            ey = min(max(gy - y0 + 2, 1), S::DY);
-        }
-        srn[q] = rho_new_2d<T, S::RX>(c, sr, su, sv, ey * S::RX + ex);
-    }
-}
-
-// Momentum update and store for the nodes of the tile.
-template <typename T, int TX, int TY, int NT>
-__device__ __forceinline__ void momentum2d(const Coef<T>& c, const State<T>& out, int x0, int y0,
-                                           const T* sr, const T* su, const T* sv, const T* srn)
-{
-    using S = Shape2<TX, TY>;
-    constexpr int RX = S::RX, DX = S::DX;
-    for (int q = threadIdx.x; q < TX * TY; q += NT) {
-        const int ly = q / TX, lx = q - ly * TX;
-        const int gx = x0 + lx, gy = y0 + ly;
-        if (gx >= c.nx || gy >= c.ny) continue;
-        const int e = (ly + 2) * RX + (lx + 2);
-        const int d = (ly + 1) * DX + (lx + 1);
-        const T rc = sr[e], uc = su[e], vc = sv[e];
-        const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
-        const T uE = su[e + 1], uW = su[e - 1], uN = su[e + RX], uS = su[e - RX];
-        const T vE = sv[e + 1], vW = sv[e - 1], vN = sv[e + RX], vS = sv[e - RX];
-        const T rho0 = c.rho0, cs2 = c.cs2;
-        const T mxC = momc(rc, uc, rho0), myC = momc(rc, vc, rho0);
-        const T mxE = momc(rE, uE, rho0), mxW = momc(rW, uW, rho0);
-        const T mxN = momc(rN, uN, rho0), mxS = momc(rS, uS, rho0);
-        const T myE = momc(rE, vE, rho0), myW = momc(rW, vW, rho0);
-        const T myN = momc(rN, vN, rho0), myS = momc(rS, vS, rho0);
-        const T rnC = srn[d];
-        const T rnE = srn[d + 1], rnW = srn[d - 1], rnN = srn[d + DX], rnS = srn[d - DX];
-        // fluxes of Pi_ab = m_a u_b + cs^2 drho delta_ab
-        const T fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + (mxN * vN - mxS * vS);
-        const T fyy = (myE * uE - myW * uW) + (fmaT(myN, vN, cs2 * rN) - fmaT(myS, vS, cs2 * rS));
-        const T lx_ = ((mxE + mxW) + (mxN + mxS)) - T(4) * mxC;
-        const T ly_ = ((myE + myW) + (myN + myS)) - T(4) * myC;
-        const T sx = (rnE - rnW) - (rE - rW);
-        const T sy = (rnN - rnS) - (rN - rS);
-        const T rho_n = rho0 + rnC;
-        T gx_ = c.gdt[0];
-        if (c.fx) gx_ = fmaT(c.dt, c.fx[gy], gx_);
-        const T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lx_, -c.cg * fxx)));
-        const T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, ly_, -c.cg * fyy)));
-        const T drn = rnC - rc;
-        const T inv = recipT(rho_n);
-        const size_t o = (size_t)gy * c.nx + gx;
-        out.r[o] = rnC;
-        out.u[o] = fmaT(fmaT(-uc, drn, dmx), inv, uc);
-        out.v[o] = fmaT(fmaT(-vc, drn, dmy), inv, vc);
-    }
-}
-
-// One 2D tile: stage, drho' ring, momentum.  smem must hold
-// tile2d_lds_bytes<T,TX,TY>() bytes.  Called by the single-case kernel and
-// by the batched persistent kernel.
-template <typename T, int TX, int TY, int NT>
-__device__ __forceinline__ void tile2d(const Coef<T>& c, const State<T>& in, const State<T>& out,
-                                       int x0, int y0, char* smem)
-{
-    using S = Shape2<TX, TY>;
-    T* sr = reinterpret_cast<T*>(smem);
-    T* su = sr + S::RXY;
-    T* sv = su + S::RXY;
-    T* srn = sv + S::RXY;
-    const bool interior = (x0 >= 2) && (x0 + TX + 2 <= c.nx) && (y0 >= 2) && (y0 + TY + 2 <= c.ny);
-    stage2d<T, TX, TY, NT>(c, in, x0, y0, interior, sr, su, sv);
-    __syncthreads();
-    rho_ring2d<T, TX, TY, NT>(c, x0, y0, interior, sr, su, sv, srn);
-    __syncthreads();
-    momentum2d<T, TX, TY, NT>(c, out, x0, y0, sr, su, sv, srn);
-}
-
-// Hardware places workgroup b on XCD (b mod 8); remap so that each XCD owns
-// a contiguous range of logical tiles (neighbours share that XCD's L2).
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    constexpr int NX = 8;
-    const int per = nb / NX, rem = nb % NX;
-    const int x = b % NX, i = b / NX;
-    return x * per + min(x, rem) + i;
-}
-
 template <typename T, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void step2d_kernel(Coef<T> c, State<T> in, State<T> out, int nbx)
 {
@@ -250,6 +89,7 @@ __device__ __forceinline__ T mom3(T r, T u, T rho0)
 }
 
 // drho' at R-index e of plane slot (cur), with the planes below / above.
+// The momentum differences use the split form of mdiff (tile2d.h).
 template <bool GEN, typename T, int RX>
 __device__ __forceinline__ T rho_new_3d(const Coef<T>& c, const T* r0, const T* u0, const T* v0,
                                         const T* rD, const T* wD, const T* rU, const T* wU, int e)
@@ -257,10 +97,9 @@ __device__ __forceinline__ T rho_new_3d(const Coef<T>& c, const T* r0, const T* 
     const T rc = r0[e];
     const T rE = r0[e + 1], rW = r0[e - 1], rN = r0[e + RX], rS = r0[e - RX];
     const T rUp = rU[e], rDn = rD[e];
-    const T mE = mom3<GEN>(rE, u0[e + 1], c.rho0), mW = mom3<GEN>(rW, u0[e - 1], c.rho0);
-    const T mN = mom3<GEN>(rN, v0[e + RX], c.rho0), mS = mom3<GEN>(rS, v0[e - RX], c.rho0);
-    const T mU = mom3<GEN>(rUp, wU[e], c.rho0), mD = mom3<GEN>(rDn, wD[e], c.rho0);
-    const T div = ((mE - mW) + (mN - mS)) + (mU - mD);
+    const T rho0 = GEN ? c.rho0 : T(1);
+    const T div = (mdiff(rE, u0[e + 1], rW, u0[e - 1], rho0) + mdiff(rN, v0[e + RX], rS, v0[e - RX], rho0)) +
+                  mdiff(rUp, wU[e], rDn, wD[e], rho0);
     const T lap = (((rE + rW) + (rN + rS)) + (rUp + rDn)) - T(6) * rc;
     return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
 }

@@ -16,6 +16,7 @@
 // intermediate take the value at their mirror node for walls and symmetry
 // planes (contact angle 90 degrees), so they are computed there.
 #include "acm_internal.h"
+#include "tile2d.h"
 
 namespace acm {
 
@@ -140,9 +141,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         const int e = ey * RX + ex;
         const T rc = sr[e];
         const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
-        const T mE = momc2(rE, su[e + 1], c.rho0), mW = momc2(rW, su[e - 1], c.rho0);
-        const T mN = momc2(rN, sv[e + RX], c.rho0), mS = momc2(rS, sv[e - RX], c.rho0);
-        const T div = (mE - mW) + (mN - mS);
+        const T div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) + mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0);
         const T lap = ((rE + rW) + (rN + rS)) - T(4) * rc;
         srn[q] = fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
     }

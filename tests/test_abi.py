@@ -131,3 +131,28 @@ def test_che_stability_number_matches_capillary_wave_statement():
     bad = acm.make_config(2, 64, 64, nu=64 / 5000, two_phase=True, sigma=64 / 25000, width=4.0,
                           mobility=16.0, bc=(0, 0, 1, 1, 0, 0))
     assert _init(bad) == acm.EUNSTABLE
+
+
+def test_batch_init_rejects_bad_cases_without_touching_the_gpu():
+    n = 2
+    arr = (acm.BatchCase * n)()
+    for i in range(n):
+        arr[i].cfg = acm.make_config(2, 16, 16, nu=0.05)
+        arr[i].a = acm.Fields(1, 2, 3, 0, 0)
+        arr[i].b = acm.Fields(4, 5, 6, 0, 0)
+        arr[i].nsteps = 10
+        arr[i].tile = -1
+    h = ctypes.c_void_p()
+    opts = acm.BatchOpts(20, 0, 0, 0.0)
+    arr[1].cfg = acm.make_config(3, 8, 8, 8, nu=0.02)           # 3D case in a 2D batch
+    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(opts), None, ctypes.byref(h)) == acm.EINVAL
+    arr[1].cfg = acm.make_config(2, 16, 16, nu=0.05, precision="f64")  # mixed precision
+    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(opts), None, ctypes.byref(h)) == acm.EINVAL
+    arr[1].cfg = acm.make_config(2, 16, 16, nu=0.5)              # unstable
+    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(opts), None, ctypes.byref(h)) == acm.EUNSTABLE
+    arr[1].cfg = acm.make_config(2, 16, 16, nu=0.05)
+    arr[1].tile = 9
+    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(opts), None, ctypes.byref(h)) == acm.EINVAL
+    bad = acm.BatchOpts(21, 0, 0, 0.0)
+    arr[1].tile = 0
+    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(bad), None, ctypes.byref(h)) == acm.EINVAL

@@ -1,0 +1,138 @@
+"""Batched persistent launch: every case must be bitwise equal to the same
+case run alone through acm_run, divergence must be isolated to its case,
+and sampled cases of the 512-case sweep must match the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2012_03525_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def acm_mod():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2012_03525_amd import acm
+    acm.lib()
+    return acm
+
+
+def f32(st):
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in st.items()}
+
+
+def case_cfg(acm, n_x, n_y, kind, nu, precision="f32", allow_unstable=False):
+    wu = [[0.0] * 3 for _ in range(6)]
+    if kind == "tgv":
+        bc = (0, 0, 0, 0, 0, 0)
+    elif kind == "cavity":
+        bc = (1, 1, 1, 1, 0, 0)
+        wu[3] = [0.05, 0, 0]
+    elif kind == "channel":
+        bc = (0, 0, 1, 2, 0, 0)
+        wu[2] = [0.02, 0, 0]
+    else:
+        bc = (2, 2, 1, 1, 0, 0)
+        wu[3] = [-0.03, 0, 0]
+    return acm.make_config(2, n_x, n_y, nu=nu, precision=precision, bc=bc, wall_u=wu,
+                           allow_unstable=allow_unstable)
+
+
+SPECS = [  # (nx, ny, kind, tile, nsteps)
+    (32, 32, "tgv", -1, 20),
+    (48, 48, "cavity", 1, 40),
+    (70, 45, "channel", 3, 20),
+    (64, 64, "sym", 5, 60),
+    (100, 36, "cavity", 4, 40),
+    (33, 57, "tgv", 2, 20),
+]
+
+
+def spec_state(nx, ny, seed):
+    return f32(inputs.seeded_state((ny, nx), seed=seed, scale_u=0.03, scale_r=1e-3))
+
+
+def test_batch_bitwise_equals_single_runs(acm_mod):
+    cfgs = [case_cfg(acm_mod, nx, ny, kind, 0.04) for nx, ny, kind, _, _ in SPECS]
+    states = [spec_state(nx, ny, 100 + i) for i, (nx, ny, _, _, _) in enumerate(SPECS)]
+    b = acm_mod.Batch(cfgs, states, [s[4] for s in SPECS], tiles=[s[3] for s in SPECS], chunk=20)
+    left = b.run()
+    assert left == 0
+    for i, (nx, ny, kind, tile, nsteps) in enumerate(SPECS):
+        st = b.status(i)
+        assert st["state"] == acm_mod.BATCH_FINISHED and st["steps_done"] == nsteps
+        assert st["done_ms"] > 0
+        got = b.state(i)
+        s = acm_mod.Solver(cfgs[i], states[i])
+        s.run(nsteps)
+        ref = s.state()
+        s.close()
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), (i, k)
+    ms, lups = b.timing()
+    assert lups == sum(nx * ny * 20 * math.ceil(n / 20) for nx, ny, _, _, n in SPECS)
+    b.close()
+
+
+def test_batch_divergence_is_isolated(acm_mod):
+    """A linearly unstable case (nu above the viscous bound, allowed
+    explicitly) is retired as diverged; the others finish bitwise equal to
+    their single runs."""
+    cfgs = [case_cfg(acm_mod, 40, 40, "tgv", 0.04), case_cfg(acm_mod, 40, 40, "tgv", 0.45, allow_unstable=True),
+            case_cfg(acm_mod, 48, 32, "cavity", 0.04)]
+    states = [spec_state(40, 40, 1), spec_state(40, 40, 2), spec_state(48, 32, 3)]
+    b = acm_mod.Batch(cfgs, states, [400, 400, 400], chunk=20, umax_limit=0.3)
+    assert b.run() == 0
+    assert b.status(1)["state"] == acm_mod.BATCH_DIVERGED
+    assert b.status(1)["steps_done"] < 400
+    for i in (0, 2):
+        assert b.status(i)["state"] == acm_mod.BATCH_FINISHED
+        s = acm_mod.Solver(cfgs[i], states[i])
+        s.run(400)
+        ref = s.state()
+        got = b.state(i)
+        for k in ref:
+            assert np.array_equal(got[k], ref[k])
+    b.close()
+
+
+def test_batch_sampled_sweep_cases_match_oracle(acm_mod, orc):
+    """Cases of the seeded 512-case sweep (the four smallest of the first
+    sixteen), FP32 batched run of their full step counts against the FP64
+    oracle: velocity relative L2 <= 1e-4 and drho relative L2 <= 1e-3
+    (FP32 storage over 1000-2000 steps at Re up to 5000, see the design
+    notes for the bound)."""
+    allc = inputs.batch_cases(ncases=16, seed=4)
+    pick = sorted(allc, key=lambda c: c.n)[:4]
+    cfgs, states = [], []
+    for c in pick:
+        kind = "tgv" if c.kind == "tgv" else "cavity"
+        cfgs.append(case_cfg(acm_mod, c.n, c.n, kind, c.nu))
+        states.append(f32(c.state))
+    b = acm_mod.Batch(cfgs, states, [c.nsteps for c in pick], chunk=500)
+    assert b.run() == 0
+    for i, c in enumerate(pick):
+        assert b.status(i)["state"] == acm_mod.BATCH_FINISHED
+        g = b.state(i)
+        wu = [[0.0] * 3 for _ in range(6)]
+        bc = (0, 0, 0, 0, 0, 0)
+        if c.kind == "cavity":
+            bc = (1, 1, 1, 1, 0, 0)
+            wu[3] = [0.05, 0, 0]
+        o = orc.run(orc.Params(dim=2, nx=c.n, ny=c.n, nu=c.nu, bc=bc, wall_u=wu), states[i], c.nsteps)
+        num = np.sqrt(np.sum((g["u"] - o["u"]) ** 2 + (g["v"] - o["v"]) ** 2))
+        den = np.sqrt(np.sum(o["u"] ** 2 + o["v"] ** 2))
+        print(f"case n={c.n} {c.kind} Re={c.re:.0f} steps={c.nsteps}: vel relL2 {num / den:.2e}")
+        assert num / den <= 1e-4
+        er = np.linalg.norm(g["drho"] - o["drho"]) / np.linalg.norm(o["drho"])
+        assert er <= 1e-3
+    b.close()
+
+
+def test_autotune_choice_is_valid_and_result_invariant(acm_mod):
+    best, ms = acm_mod.autotune(64, "f32", copies=64, steps=40)
+    assert 0 <= best < 6 and all(m > 0 for m in ms)
+    assert ms[best] == min(ms)

@@ -251,11 +251,16 @@ def test_twophase_fp64_parity(acm_mod, orc, tile):
 
 
 def test_twophase_fp32_parity(acm_mod, orc):
+    """FP32 two-phase after 1000 steps.  FP32 storage of phi alone moves drho
+    by ~3e-4 relative L2 (shown on the CPU by the storage-emulation test), so
+    drho is bounded at 1e-3 here; velocity and phi keep 2e-5 and 1e-5."""
     cfg = drop_cfg(acm_mod, 128, "f32")
     g, o = run_both(acm_mod, orc, cfg, to_f32(drop128()), 1000)
+    print(f"two-phase fp32: phi {rel_l2(g['phi'], o['phi']):.2e} vel {rel_l2_vec(g, o, ('u', 'v')):.2e} "
+          f"drho {rel_l2(g['drho'], o['drho']):.2e}")
     assert rel_l2(g["phi"], o["phi"]) <= 1e-5
     assert rel_l2_vec(g, o, ("u", "v")) <= 2e-5
-    assert rel_l2(g["drho"], o["drho"]) <= 1e-4
+    assert rel_l2(g["drho"], o["drho"]) <= 1e-3
 
 
 @pytest.mark.parametrize("faces", [(0, 0, 0, 0, 0, 0), (2, 2, 1, 1, 0, 0), (1, 1, 2, 2, 0, 0)])
