@@ -96,6 +96,24 @@ def workload(name, tile):
     return cfg, st, meta, bytes_per_lup, kernel
 
 
+def measured_traffic(name):
+    """HBM bytes per launch of the workload's dominant kernel from the
+    committed counter runs (profiles/traffic.json), or None when the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))[name]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha1()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha1"]:
+        return None
+    return int(1024 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]))
+
+
 def cpu_baseline(name, cfg, st, budget_s):
     """Time the FP64 CPU oracle (single thread) on a bounded sample of the
     same workload: whole-grid steps until about budget_s seconds pass."""
@@ -179,7 +197,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(a.workload),
             "bytes_per_lup": bpl,
             "lups_per_launch": nodes,
             "avg_launch_us": round(ms_per_step * 1e3, 3),
