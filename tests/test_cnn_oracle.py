@@ -1,0 +1,105 @@
+"""Pins of the FP64 network reference against finite differences, an
+independent convolution routine and closed forms."""
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def cnn():
+    from oracle import cnn
+    return cnn
+
+
+def small_params(cnn, seed=0, channels=(3, 4, 5, 3)):
+    return cnn.init_params(seed, channels=channels, last_scale=1.0)
+
+
+def test_conv_matches_torch_circular(cnn):
+    """Cross-check with torch.nn.functional.conv2d (CPU, FP64, circular pad)."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(1))
+    x = rng.standard_normal((7, 9, 4))
+    w = rng.standard_normal((9, 5, 4))
+    b = rng.standard_normal(5)
+    ours = cnn.conv(x, w, b)
+    # torch weight [out, in, kh, kw] with kh index = dy + 1, kw index = dx + 1
+    wt = np.zeros((5, 4, 3, 3))
+    for t, (dy, dx) in enumerate(cnn.TAPS):
+        wt[:, :, dy + 1, dx + 1] = w[t]
+    xt = torch.from_numpy(x.transpose(2, 0, 1)[None]).double()
+    xp = torch.nn.functional.pad(xt, (1, 1, 1, 1), mode="circular")
+    ref = torch.nn.functional.conv2d(xp, torch.from_numpy(wt).double(), torch.from_numpy(b).double())
+    np.testing.assert_allclose(ours, ref[0].numpy().transpose(1, 2, 0), rtol=1e-12, atol=1e-12)
+
+
+def test_conv_delta_kernel_is_shift(cnn):
+    """A one-hot tap weight reproduces a circular shift exactly."""
+    rng = np.random.Generator(np.random.PCG64(2))
+    x = rng.standard_normal((6, 5, 2))
+    for t, (dy, dx) in enumerate(cnn.TAPS):
+        w = np.zeros((9, 2, 2))
+        w[t] = np.eye(2)
+        y = cnn.conv(x, w, np.zeros(2))
+        np.testing.assert_array_equal(y, np.roll(x, shift=(-dy, -dx), axis=(0, 1)))
+
+
+def test_gradients_match_central_differences(cnn):
+    """d loss / d params and d loss / d input of a tiny net against central
+    differences (h = 1e-6): relative error <= 1e-7."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    params = small_params(cnn, seed=4)
+    x0 = rng.standard_normal((5, 6, 3))
+    tgt = rng.standard_normal((5, 6, 3))
+
+    def loss_of(ps):
+        raw, _ = cnn.forward(ps, x0)
+        return cnn.mse_loss_and_grad(raw, tgt)[0]
+
+    raw, acts = cnn.forward(params, x0)
+    _, g = cnn.mse_loss_and_grad(raw, tgt)
+    grads = cnn.backward(params, acts, g)
+    h = 1e-6
+    for l in range(len(params)):
+        for k in range(2):
+            p = params[l][k]
+            flat = p.reshape(-1)
+            idx = rng.choice(flat.size, size=min(6, flat.size), replace=False)
+            for i in idx:
+                old = flat[i]
+                flat[i] = old + h
+                lp = loss_of(params)
+                flat[i] = old - h
+                lm = loss_of(params)
+                flat[i] = old
+                fd = (lp - lm) / (2 * h)
+                an = grads[l][k].reshape(-1)[i]
+                assert abs(fd - an) <= 1e-7 * max(1.0, abs(fd)) + 1e-9, (l, k, i, fd, an)
+
+
+def test_adam_first_step_is_lr_times_sign(cnn):
+    """Closed form: after one Adam step from zero moments the update is
+    -lr * g / (|g| + eps), i.e. about -lr * sign(g)."""
+    g = np.array([0.3, -2.0, 1e-3])
+    p = np.zeros(3)
+    m = np.zeros(3)
+    v = np.zeros(3)
+    cnn.adam_step(p, g, m, v, t=1, lr=0.01)
+    np.testing.assert_allclose(p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_box_filter_and_prolongation(cnn):
+    """Box filter preserves the mean; bilinear prolongation is exact on
+    constants and on fields linear along a period-free direction slice, and
+    filtering the prolonged field of a smooth mode changes it by O(k^2)."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    f = rng.standard_normal((16, 24))
+    c = cnn.box_filter(f, 4)
+    assert c.shape == (4, 6)
+    assert c.mean() == pytest.approx(f.mean(), abs=1e-14)
+    np.testing.assert_allclose(cnn.prolong_bilinear(np.full((4, 6), 2.5), 4), 2.5, rtol=0, atol=1e-15)
+    n = 64
+    y = (np.arange(n // 4) * 4 + 1.5) * 2 * np.pi / n
+    cm = np.broadcast_to(np.sin(y)[:, None], (n // 4, n // 4)).copy()
+    fine = cnn.prolong_bilinear(cm, 4)
+    yf = np.arange(n) * 2 * np.pi / n
+    assert np.abs(fine - np.sin(yf)[:, None]).max() < (2 * np.pi * 4 / n) ** 2 / 8 + 1e-12
