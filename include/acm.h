@@ -217,6 +217,90 @@ void acm_batch_destroy(acm_batch* b);
 acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int32_t steps, void* stream,
                               double* ms_per_tile, int32_t* best);
 
+/* ------------------------------------------------------------------------ */
+/* Learned closure: a CNN correcting a 4x-coarser SMAME step                 */
+/* ------------------------------------------------------------------------ */
+/* Network: ACM_CNN_LAYERS 3x3 convolutions with circular padding, channels
+ * 3 -> 32 -> 32 -> 32 -> 32 -> 3 (the 3-channel input and output are padded
+ * to 16 channels in memory), ReLU after every layer but the last.  It is not
+ * part of the paper's method; it corrects the coarse step toward box-filtered
+ * fine-grid states: q <- S_c(q) + D f(N S_c(q)), N and D per-channel scales.
+ * Layouts: activations bf16 [ny][nx][C] (channel fastest); weights bf16
+ * [9][C_out][C_in] with tap t = (dy+1)*3 + (dx+1); biases, gradients, master
+ * weights and Adam moments fp32.  Grids need nx % 64 == 0 and ny % 8 == 0.
+ * All calls are asynchronous on `stream`; buffers are caller-owned. */
+#define ACM_CNN_LAYERS 5
+enum { ACM_CONV_RELU = 0, ACM_CONV_RAW = 1, ACM_CONV_MASK = 2 };
+
+/* Padded (C_in, C_out) of a layer: (16,32), (32,32) x3, (32,16). */
+acm_status acm_cnn_layer_shape(int32_t layer, int32_t* cin, int32_t* cout);
+
+/* y = conv3x3(x, w) on the bf16 matrix cores (FP32 accumulation):
+ * ACM_CONV_RELU: y bf16 = relu(conv + bias); ACM_CONV_RAW: y fp32 = conv + bias;
+ * ACM_CONV_MASK: y bf16 = conv * (mask > 0) (data gradient through a ReLU,
+ * with w the weights from acm_cnn_transpose; bias unused).
+ * Supported (cin, cout): (16,32), (32,32), (32,16) as the modes require. */
+acm_status acm_cnn_conv(int32_t nx, int32_t ny, int32_t cin, int32_t cout, int32_t mode, const void* x,
+                        const void* w, const float* bias, const void* mask, void* y, void* stream);
+
+/* Weights of the transposed convolution: wt[t][i][o] = w[8-t][o][i]. */
+acm_status acm_cnn_transpose(int32_t cin, int32_t cout, const void* w, void* wt, void* stream);
+
+/* Weight and bias gradients of sum(g * conv(x)): dw[9][cout][cin], db[cout]
+ * (fp32, overwritten), by per-workgroup MFMA partial sums in `workspace`
+ * (acm_cnn_wgrad_workspace bytes) reduced in a fixed order. */
+size_t acm_cnn_wgrad_workspace(int32_t nx, int32_t ny, int32_t cin, int32_t cout);
+acm_status acm_cnn_wgrad(int32_t nx, int32_t ny, int32_t cin, int32_t cout, const void* x, const void* g,
+                         float* workspace, float* dw, float* db, void* stream);
+
+/* Network input a0 (bf16, 16 channels) = in_scale[c] * (drho, u, v)[c]. */
+acm_status acm_cnn_pack(int32_t nx, int32_t ny, const float* drho, const float* u, const float* v,
+                        const float* in_scale, void* a0, void* stream);
+
+/* In-place correction: (drho, u, v)[c] += out_scale[c] * raw[p][c]. */
+acm_status acm_cnn_apply(int32_t nx, int32_t ny, const float* raw, const float* out_scale, float* drho,
+                         float* u, float* v, void* stream);
+
+/* Mean squared error of raw (fp32, 16 channels) against the target
+ * residual (target[c] - base[c]) / out_scale[c] over pixels and 3 channels;
+ * grad (bf16, 16 channels) = d loss / d raw; *loss (device double) is set. */
+size_t acm_cnn_loss_workspace(int32_t nx, int32_t ny);
+acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* const* base,
+                        const float* const* target, const float* out_scale, void* grad, double* workspace,
+                        double* loss, void* stream);
+
+/* Adam update of n fp32 parameters (bias-corrected, step t >= 1); p16
+ * (optional) receives the bf16 copy used by the convolutions. */
+acm_status acm_cnn_adam(int64_t n, float* p, const float* g, float* m, float* v, void* p16, float lr, float b1,
+                        float b2, float eps, int64_t t, void* stream);
+
+acm_status acm_cnn_to_bf16(size_t n, const float* src, void* dst, void* stream);
+
+/* Coarse (I, J) = mean of fine nodes (fI..fI+f-1, fJ..fJ+f-1) for drho, u, v. */
+acm_status acm_filter_box(int32_t nxf, int32_t nyf, int32_t factor, int32_t precision, const acm_fields* fine,
+                          const acm_fields* coarse, void* stream);
+
+/* Periodic bilinear interpolation coarse -> fine (coarse node I at fine
+ * coordinate f I + (f-1)/2); used to continue on the fine grid. */
+acm_status acm_prolong_bilinear(int32_t nxc, int32_t nyc, int32_t factor, int32_t precision,
+                                const acm_fields* coarse, const acm_fields* fine, void* stream);
+
+/* Closure inference: every coarse step runs the SMAME step then the network
+ * correction, captured in HIP graphs of `chunk` steps (even; 0 = 100).
+ * weights/biases: ACM_CNN_LAYERS device pointers (bf16 / fp32).  workspace:
+ * acm_closure_workspace bytes of device memory for the activations. */
+typedef struct acm_closure acm_closure;
+size_t acm_closure_workspace(int32_t nx, int32_t ny);
+acm_status acm_closure_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b, const void* force_x,
+                            const void* const* weights, const float* const* biases, const float* in_scale,
+                            const float* out_scale, void* workspace, int32_t chunk, void* stream,
+                            acm_closure** out);
+/* 0: plain coarse steps (the network is skipped), 1: corrected steps. */
+acm_status acm_closure_set_network(acm_closure* h, int32_t enabled);
+acm_status acm_closure_run(acm_closure* h, int64_t nsteps);
+acm_status acm_closure_current(const acm_closure* h, int32_t* which, int64_t* step);
+void acm_closure_destroy(acm_closure* h);
+
 /* Plain device-to-device copy of `bytes` bytes (both pointers 16-byte
  * aligned), asynchronous on `stream`.  Used to measure the practical copy
  * bandwidth that the stencil kernels are compared with, and to calibrate

@@ -96,6 +96,39 @@ SIGNATURES = {
     "acm_batch_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int32)]),
+    "acm_cnn_layer_shape": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32)]),
+    "acm_cnn_conv": (ctypes.c_int, [ctypes.c_int32] * 5 + [ctypes.c_void_p] * 6),
+    "acm_cnn_transpose": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "acm_cnn_wgrad_workspace": (ctypes.c_size_t, [ctypes.c_int32] * 4),
+    "acm_cnn_wgrad": (ctypes.c_int, [ctypes.c_int32] * 4 + [ctypes.c_void_p] * 6),
+    "acm_cnn_pack": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32] + [ctypes.c_void_p] * 3 +
+                     [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]),
+    "acm_cnn_apply": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]
+                      + [ctypes.c_void_p] * 4),
+    "acm_cnn_loss_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "acm_cnn_loss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                    ctypes.POINTER(ctypes.c_float)] + [ctypes.c_void_p] * 4),
+    "acm_cnn_adam": (ctypes.c_int, [ctypes.c_int64] + [ctypes.c_void_p] * 5 + [ctypes.c_float] * 4 +
+                     [ctypes.c_int64, ctypes.c_void_p]),
+    "acm_cnn_to_bf16": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "acm_filter_box": (ctypes.c_int, [ctypes.c_int32] * 4 + [ctypes.POINTER(Fields), ctypes.POINTER(Fields),
+                                                             ctypes.c_void_p]),
+    "acm_prolong_bilinear": (ctypes.c_int, [ctypes.c_int32] * 4 + [ctypes.POINTER(Fields), ctypes.POINTER(Fields),
+                                                                   ctypes.c_void_p]),
+    "acm_closure_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "acm_closure_init": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(Fields), ctypes.POINTER(Fields),
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "acm_closure_set_network": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "acm_closure_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "acm_closure_current": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int64)]),
+    "acm_closure_destroy": (None, [ctypes.c_void_p]),
 }
 
 

@@ -1,0 +1,474 @@
+"""Learned closure for a 4x-coarser SMAME grid (not part of the paper's
+method): q <- S_c(q) + D f(N S_c(q)), with f the 5-layer CNN of the HIP
+library (bf16 matrix-core convolutions), trained on pairs of box-filtered
+fine-grid states this solver generates, and a fine-grid fallback when a
+divergence / energy gate trips.
+
+Every numerical step runs in libacm (acm_cnn_*, acm_closure_*, acm_filter_box,
+acm_prolong_bilinear, acm_step/acm_run); this module allocates buffers with
+PyTorch and sequences the calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import time
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import acm, inputs
+
+LAYERS = 5
+CONV_RELU, CONV_RAW, CONV_MASK = 0, 1, 2
+REAL_CHANNELS = (3, 32, 32, 32, 32, 3)
+
+
+def _f3(v) -> ctypes.Array:
+    return (ctypes.c_float * 3)(*[float(x) for x in v])
+
+
+def _vp(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None else None)
+
+
+def _fields(d: Dict[str, "object"]) -> acm.Fields:
+    return acm.Fields(d["drho"].data_ptr(), d["u"].data_ptr(), d["v"].data_ptr(), None, None)
+
+
+def layer_shape(l: int) -> Tuple[int, int]:
+    ci, co = ctypes.c_int32(), ctypes.c_int32()
+    acm.check(acm.lib().acm_cnn_layer_shape(l, ctypes.byref(ci), ctypes.byref(co)))
+    return ci.value, co.value
+
+
+def he_init(seed: int, last_scale: float = 0.1):
+    """Seeded He-normal weights [9, C_out, C_in] (real channels), zero biases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for l in range(LAYERS):
+        ci, co = REAL_CHANNELS[l], REAL_CHANNELS[l + 1]
+        w = rng.standard_normal((9, co, ci)) * math.sqrt(2.0 / (9 * ci))
+        if l == LAYERS - 1:
+            w *= last_scale
+        out.append([w, np.zeros(co)])
+    return out
+
+
+class Network:
+    """Parameters, optimizer state and work buffers of the closure network
+    for one nx x ny grid (nx % 64 == 0, ny % 8 == 0)."""
+
+    def __init__(self, nx: int, ny: int, params=None, seed: int = 0, device: str = "cuda:0",
+                 in_scale=(1.0, 1.0, 1.0), out_scale=(1.0, 1.0, 1.0)):
+        import torch
+        self.torch = torch
+        self.nx, self.ny = nx, ny
+        self.dev = torch.device(device)
+        self.in_scale = list(in_scale)
+        self.out_scale = list(out_scale)
+        self.shapes = [layer_shape(l) for l in range(LAYERS)]
+        f32, b16 = torch.float32, torch.bfloat16
+        self.w32 = [torch.zeros((9, co, ci), dtype=f32, device=self.dev) for ci, co in self.shapes]
+        self.b32 = [torch.zeros(co, dtype=f32, device=self.dev) for ci, co in self.shapes]
+        self.w16 = [torch.zeros((9, co, ci), dtype=b16, device=self.dev) for ci, co in self.shapes]
+        self.wt16 = [torch.zeros((9, ci, co), dtype=b16, device=self.dev) for ci, co in self.shapes]
+        self.gw = [torch.zeros_like(w) for w in self.w32]
+        self.gb = [torch.zeros_like(b) for b in self.b32]
+        self.mw = [torch.zeros_like(w) for w in self.w32]
+        self.vw = [torch.zeros_like(w) for w in self.w32]
+        self.mb = [torch.zeros_like(b) for b in self.b32]
+        self.vb = [torch.zeros_like(b) for b in self.b32]
+        self.acts = [torch.zeros((ny, nx, ci), dtype=b16, device=self.dev) for ci, _ in self.shapes]
+        self.raw = torch.zeros((ny, nx, 16), dtype=f32, device=self.dev)
+        self.gout = torch.zeros((ny, nx, 16), dtype=b16, device=self.dev)
+        self.gacts = [torch.zeros((ny, nx, co), dtype=b16, device=self.dev) for _, co in self.shapes]
+        ws = max(acm.lib().acm_cnn_wgrad_workspace(nx, ny, ci, co) for ci, co in self.shapes)
+        self.wg_ws = torch.zeros(ws // 4 + 1, dtype=f32, device=self.dev)
+        self.loss_ws = torch.zeros(acm.lib().acm_cnn_loss_workspace(nx, ny) // 8 + 1, dtype=torch.float64,
+                                   device=self.dev)
+        self.loss_buf = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        self.t = 0
+        self.load(params if params is not None else he_init(seed))
+
+    @property
+    def stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.dev).cuda_stream)
+
+    def load(self, params):
+        """Set weights from real-channel numpy arrays (zero padding elsewhere)."""
+        torch = self.torch
+        for l, (w, b) in enumerate(params):
+            ci, co = REAL_CHANNELS[l], REAL_CHANNELS[l + 1]
+            self.w32[l].zero_()
+            self.b32[l].zero_()
+            self.w32[l][:, :co, :ci] = torch.from_numpy(np.asarray(w, dtype=np.float32)).to(self.dev)
+            self.b32[l][:co] = torch.from_numpy(np.asarray(b, dtype=np.float32)).to(self.dev)
+        self.refresh_bf16()
+
+    def export(self):
+        out = []
+        for l in range(LAYERS):
+            ci, co = REAL_CHANNELS[l], REAL_CHANNELS[l + 1]
+            out.append([self.w32[l][:, :co, :ci].double().cpu().numpy(), self.b32[l][:co].double().cpu().numpy()])
+        return out
+
+    def refresh_bf16(self):
+        L = acm.lib()
+        for l, (ci, co) in enumerate(self.shapes):
+            acm.check(L.acm_cnn_to_bf16(self.w32[l].numel(), _vp(self.w32[l]), _vp(self.w16[l]), self.stream))
+        self.refresh_transposed()
+
+    def refresh_transposed(self):
+        L = acm.lib()
+        for l, (ci, co) in enumerate(self.shapes):
+            acm.check(L.acm_cnn_transpose(ci, co, _vp(self.w16[l]), _vp(self.wt16[l]), self.stream))
+
+    # -- forward / backward ---------------------------------------------------
+    def forward(self, drho, u, v):
+        """raw = f(N q) for the state tensors (ny, nx) fp32."""
+        L = acm.lib()
+        acm.check(L.acm_cnn_pack(self.nx, self.ny, _vp(drho), _vp(u), _vp(v), _f3(self.in_scale),
+                                 _vp(self.acts[0]), self.stream))
+        for l, (ci, co) in enumerate(self.shapes):
+            last = l == LAYERS - 1
+            y = self.raw if last else self.acts[l + 1]
+            acm.check(L.acm_cnn_conv(self.nx, self.ny, ci, co, CONV_RAW if last else CONV_RELU, _vp(self.acts[l]),
+                                     _vp(self.w16[l]), _vp(self.b32[l]), None, _vp(y), self.stream))
+
+    def apply(self, drho, u, v):
+        acm.check(acm.lib().acm_cnn_apply(self.nx, self.ny, _vp(self.raw), _f3(self.out_scale), _vp(drho), _vp(u),
+                                          _vp(v), self.stream))
+
+    def loss_and_grads(self, base: Dict[str, "object"], target: Dict[str, "object"]):
+        """Loss of the last forward against target and gradients of all
+        parameters (into gw, gb).  Returns the device loss tensor."""
+        L = acm.lib()
+        b = (ctypes.c_void_p * 3)(*[base[k].data_ptr() for k in ("drho", "u", "v")])
+        t = (ctypes.c_void_p * 3)(*[target[k].data_ptr() for k in ("drho", "u", "v")])
+        acm.check(L.acm_cnn_loss(self.nx, self.ny, _vp(self.raw), b, t, _f3(self.out_scale), _vp(self.gout),
+                                 _vp(self.loss_ws), _vp(self.loss_buf), self.stream))
+        g = self.gout
+        for l in range(LAYERS - 1, -1, -1):
+            ci, co = self.shapes[l]
+            acm.check(L.acm_cnn_wgrad(self.nx, self.ny, ci, co, _vp(self.acts[l]), _vp(g), _vp(self.wg_ws),
+                                      _vp(self.gw[l]), _vp(self.gb[l]), self.stream))
+            if l > 0:
+                gx = self.gacts[l - 1]  # gradient w.r.t. the pre-activation producing acts[l]
+                acm.check(L.acm_cnn_conv(self.nx, self.ny, co, ci, CONV_MASK, _vp(g), _vp(self.wt16[l]), None,
+                                         _vp(self.acts[l]), _vp(gx), self.stream))
+                g = gx
+        return self.loss_buf
+
+    def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+        L = acm.lib()
+        self.t += 1
+        for l in range(LAYERS):
+            acm.check(L.acm_cnn_adam(self.w32[l].numel(), _vp(self.w32[l]), _vp(self.gw[l]), _vp(self.mw[l]),
+                                     _vp(self.vw[l]), _vp(self.w16[l]), lr, b1, b2, eps, self.t, self.stream))
+            acm.check(L.acm_cnn_adam(self.b32[l].numel(), _vp(self.b32[l]), _vp(self.gb[l]), _vp(self.mb[l]),
+                                     _vp(self.vb[l]), None, lr, b1, b2, eps, self.t, self.stream))
+        self.refresh_transposed()
+
+    def train_step(self, base, target, lr: float):
+        self.forward(base["drho"], base["u"], base["v"])
+        loss = self.loss_and_grads(base, target)
+        self.adam(lr)
+        return loss
+
+
+# ---------------------------------------------------------------------------
+# forced periodic flow: fine / coarse configurations
+# ---------------------------------------------------------------------------
+@dataclass
+class FlowSpec:
+    """2 pi periodic box with Kolmogorov forcing g_x = F sin(k_f y).  Lattice
+    units of the fine grid; the coarse grid uses the acoustic scaling
+    dx_c = r dx_f, dt_c = r dt_f (same Mach number): nu_c = nu_f / r and
+    g_c = r g_f in coarse lattice units."""
+    n_fine: int = 1024
+    ratio: int = 4
+    nu_fine: float = 0.02
+    k_force: int = 4
+    amp_laminar: float = 0.03   # F / (nu k^2) in fine lattice units
+    u_rms: float = 0.03
+    kmax: int = 16
+
+    @property
+    def n_coarse(self):
+        return self.n_fine // self.ratio
+
+    def force_amplitude(self):
+        k = 2 * math.pi * self.k_force / self.n_fine
+        return self.amp_laminar * self.nu_fine * k * k
+
+    def fine_config(self, tile: int = 0):
+        return acm.make_config(2, self.n_fine, self.n_fine, nu=self.nu_fine, precision="f32", tile=tile,
+                               graph_chunk=100)
+
+    def coarse_config(self):
+        return acm.make_config(2, self.n_coarse, self.n_coarse, nu=self.nu_fine / self.ratio, precision="f32",
+                               graph_chunk=100)
+
+    def fine_force(self):
+        y = 2 * math.pi * np.arange(self.n_fine) / self.n_fine
+        return self.force_amplitude() * np.sin(self.k_force * y)
+
+    def coarse_force(self):
+        r = self.ratio
+        y = 2 * math.pi * (r * np.arange(self.n_coarse) + 0.5 * (r - 1)) / self.n_fine
+        return r * self.force_amplitude() * np.sin(self.k_force * y)
+
+    def initial_state(self, seed: int):
+        return inputs.random_spectrum_field(self.n_fine, seed, self.u_rms, kmax=self.kmax)
+
+
+def filter_to(fine: Dict[str, "object"], coarse: Dict[str, "object"], spec: FlowSpec, stream):
+    acm.check(acm.lib().acm_filter_box(spec.n_fine, spec.n_fine, spec.ratio, acm.F32, ctypes.byref(_fields(fine)),
+                                       ctypes.byref(_fields(coarse)), stream))
+
+
+def prolong_to(coarse: Dict[str, "object"], fine: Dict[str, "object"], spec: FlowSpec, stream):
+    acm.check(acm.lib().acm_prolong_bilinear(spec.n_coarse, spec.n_coarse, spec.ratio, acm.F32,
+                                             ctypes.byref(_fields(coarse)), ctypes.byref(_fields(fine)), stream))
+
+
+def rel_l2_velocity(a: Dict[str, "object"], b: Dict[str, "object"]) -> float:
+    """Relative L2 velocity error ||a - b|| / ||b|| (device tensors, FP64 sum)."""
+    num = ((a["u"] - b["u"]).double() ** 2 + (a["v"] - b["v"]).double() ** 2).sum()
+    den = (b["u"].double() ** 2 + b["v"].double() ** 2).sum()
+    return float((num / den).sqrt())
+
+
+def generate_pairs(spec: FlowSpec, seeds: Sequence[int], warmup: int, pairs_per_seed: int, stride: int):
+    """Training pairs from fine runs: for each snapshot time t, base =
+    S_c(F(fine_t)) (one coarse step of the filtered state) and target =
+    F(fine_{t + r steps}).  Returns a list of (base, target) dicts of
+    device tensors."""
+    import torch
+    dev = torch.device("cuda:0")
+    shape_c = (spec.n_coarse, spec.n_coarse)
+    ff = spec.fine_force()
+    cf = spec.coarse_force()
+    out = []
+    for seed in seeds:
+        fine = acm.Solver(spec.fine_config(), spec.initial_state(seed), force_x=ff)
+        coarse = acm.Solver(spec.coarse_config(), {k: np.zeros(shape_c) for k in ("drho", "u", "v")}, force_x=cf)
+        fine.run(warmup)
+        for p in range(pairs_per_seed):
+            snap = {k: torch.empty(shape_c, dtype=torch.float32, device=dev) for k in ("drho", "u", "v")}
+            filter_to(fine.tensors(), snap, spec, ctypes.c_void_p(fine.stream.cuda_stream))
+            fine.run(spec.ratio)
+            target = {k: torch.empty(shape_c, dtype=torch.float32, device=dev) for k in ("drho", "u", "v")}
+            filter_to(fine.tensors(), target, spec, ctypes.c_void_p(fine.stream.cuda_stream))
+            w, s = coarse.current()
+            for k in snap:
+                coarse.sets[w][k].copy_(snap[k])
+            coarse.step()
+            base = {k: coarse.tensors()[k].clone() for k in ("drho", "u", "v")}
+            out.append((base, target))
+            fine.run(stride - spec.ratio)
+        fine.close()
+        coarse.close()
+    torch.cuda.synchronize()
+    return out
+
+
+def channel_scales(pairs, eps: float = 1e-12):
+    """N = 1 / rms of each base channel; D = rms of each target residual."""
+    n_in = np.zeros(3)
+    n_out = np.zeros(3)
+    for base, tgt in pairs:
+        for c, k in enumerate(("drho", "u", "v")):
+            n_in[c] += float((base[k].double() ** 2).mean())
+            n_out[c] += float(((tgt[k] - base[k]).double() ** 2).mean())
+    n_in = np.sqrt(n_in / len(pairs))
+    n_out = np.sqrt(n_out / len(pairs))
+    return (1.0 / np.maximum(n_in, eps)).tolist(), np.maximum(n_out, eps).tolist()
+
+
+def train(net: Network, pairs, epochs: int, lr: float, seed: int = 0, lr_decay: float = 1.0, log=None):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    losses = []
+    for ep in range(epochs):
+        order = rng.permutation(len(pairs))
+        tot = 0.0
+        for i in order:
+            base, tgt = pairs[i]
+            loss = net.train_step(base, tgt, lr)
+            tot += float(loss.item()) if log is not None else 0.0
+        losses.append(tot / len(pairs))
+        if log is not None:
+            log(f"epoch {ep}: mean loss {losses[-1]:.4e} lr {lr:.2e}")
+        lr *= lr_decay
+    return losses
+
+
+@dataclass
+class GateResult:
+    tripped: bool
+    at_step: int
+    reason: str
+
+
+class ClosureRun:
+    """Coarse run of the closure handle (network on or off) on its own pair
+    of state buffers, with a monitor handle on the same buffers for the
+    gate diagnostics."""
+
+    def __init__(self, spec: FlowSpec, net: Optional[Network], state_coarse: Dict[str, "object"], chunk: int = 100):
+        import torch
+        self.torch = torch
+        self.spec = spec
+        dev = torch.device("cuda:0")
+        shape = (spec.n_coarse, spec.n_coarse)
+        cfg = spec.coarse_config()
+        self.cf = torch.from_numpy(spec.coarse_force()).to(device=dev, dtype=torch.float32)
+        self.sets = [{k: torch.empty(shape, dtype=torch.float32, device=dev) for k in ("drho", "u", "v")}
+                     for _ in range(2)]
+        for k in self.sets[0]:
+            self.sets[0][k].copy_(state_coarse[k])
+        self.ws = torch.zeros(acm.lib().acm_closure_workspace(*shape) // 4 + 1, dtype=torch.float32, device=dev)
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        self.fa, self.fb = _fields(self.sets[0]), _fields(self.sets[1])
+        self.net = net if net is not None else Network(spec.n_coarse, spec.n_coarse)
+        ws16 = (ctypes.c_void_p * LAYERS)(*[self.net.w16[l].data_ptr() for l in range(LAYERS)])
+        bs = (ctypes.c_void_p * LAYERS)(*[self.net.b32[l].data_ptr() for l in range(LAYERS)])
+        h = ctypes.c_void_p()
+        acm.check(acm.lib().acm_closure_init(ctypes.byref(cfg), ctypes.byref(self.fa), ctypes.byref(self.fb),
+                                             _vp(self.cf), ws16, bs, _f3(self.net.in_scale),
+                                             _f3(self.net.out_scale), _vp(self.ws), chunk, stream, ctypes.byref(h)))
+        self.h = h
+        if net is None:
+            acm.check(acm.lib().acm_closure_set_network(self.h, 0))
+        self.mon = acm.Solver(cfg, None, tensors=self.sets, force_x=spec.coarse_force())
+
+    def current(self):
+        w, s = ctypes.c_int32(), ctypes.c_int64()
+        acm.check(acm.lib().acm_closure_current(self.h, ctypes.byref(w), ctypes.byref(s)))
+        return w.value, s.value
+
+    def state(self):
+        return self.sets[self.current()[0]]
+
+    def run(self, n: int):
+        acm.check(acm.lib().acm_closure_run(self.h, int(n)))
+
+    def diagnostics(self):
+        w, s = self.current()
+        self.mon.set_current(w, s)
+        return self.mon.diagnostics()
+
+    def close(self):
+        if getattr(self, "h", None):
+            acm.lib().acm_closure_destroy(self.h)
+            self.h = None
+        if getattr(self, "mon", None):
+            self.mon.close()
+            self.mon = None
+
+
+def divergence_ratio(d: dict) -> float:
+    """rms divergence over rms vorticity: O(Ma^2) for the weakly
+    compressible scheme, O(1) when a correction injects compression."""
+    return d["div_rms"] / max(math.sqrt(2.0 * d["enstrophy"]), 1e-300)
+
+
+def gated_run(spec: FlowSpec, net: Optional[Network], c0, coarse_steps: int, gate_every: int = 100,
+              energy_tol: float = 0.05, div_tol: float = 0.05, force_trip_at: Optional[int] = None,
+              keep_states: bool = True):
+    """Closure (or plain coarse, net=None) run with the gate every
+    `gate_every` coarse steps.  The gate trips on a non-finite value, on a
+    relative kinetic-energy change above energy_tol between two gates, or on
+    a divergence ratio above div_tol; the state is then prolonged to the
+    fine grid and plain fine steps finish the horizon.  Returns the filtered
+    state at every gate, the gate outcome and the wall time."""
+    import torch
+    dev = torch.device("cuda:0")
+    shape_c = (spec.n_coarse, spec.n_coarse)
+    run = ClosureRun(spec, net, c0)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    gate = GateResult(False, -1, "")
+    states = []
+    fine = None
+    e_prev = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(coarse_steps // gate_every):
+        step_no = (g + 1) * gate_every
+        if fine is None:
+            run.run(gate_every)
+            d = run.diagnostics()
+            reason = ""
+            if d["nonfinite"]:
+                reason = "non-finite"
+            elif e_prev is not None and abs(d["ke"] / e_prev - 1.0) > energy_tol:
+                reason = "energy drift"
+            elif divergence_ratio(d) > div_tol:
+                reason = "divergence"
+            elif force_trip_at is not None and step_no >= force_trip_at:
+                reason = "forced"
+            e_prev = d["ke"]
+            cur = run.state()
+            if reason:
+                gate = GateResult(True, step_no, reason)
+                fine = acm.Solver(spec.fine_config(), None,
+                                  tensors=[{k: torch.empty((spec.n_fine, spec.n_fine), dtype=torch.float32,
+                                                           device=dev) for k in ("drho", "u", "v")}
+                                           for _ in range(2)], force_x=spec.fine_force())
+                prolong_to(cur, fine.sets[0], spec, stream)
+        else:
+            fine.run(gate_every * spec.ratio)
+            cur = {k: torch.empty(shape_c, dtype=torch.float32, device=dev) for k in ("drho", "u", "v")}
+            filter_to(fine.tensors(), cur, spec, stream)
+        if keep_states:
+            states.append({k: t.clone() for k, t in cur.items()})
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    run.close()
+    if fine is not None:
+        fine.close()
+    return states, gate, wall
+
+
+def evaluate_seed(spec: FlowSpec, net: Network, seed: int, warmup: int, coarse_steps: int, gate_every: int = 100,
+                  energy_tol: float = 0.05, div_tol: float = 0.05, force_trip_at: Optional[int] = None):
+    """Fine reference, plain coarse run and closure run from the same
+    filtered state: velocity errors against the filtered fine reference at
+    every gate, the gate outcome and the time-to-solution of the closure
+    (gates included) and of the plain fine run."""
+    import torch
+    dev = torch.device("cuda:0")
+    shape_c = (spec.n_coarse, spec.n_coarse)
+    ff = spec.fine_force()
+    fine = acm.Solver(spec.fine_config(), spec.initial_state(seed), force_x=ff)
+    fine.run(warmup)
+    stream = ctypes.c_void_p(fine.stream.cuda_stream)
+    c0 = {k: torch.empty(shape_c, dtype=torch.float32, device=dev) for k in ("drho", "u", "v")}
+    filter_to(fine.tensors(), c0, spec, stream)
+    start = [{k: t.clone() for k, t in fine.tensors().items()},
+             {k: torch.empty_like(t) for k, t in fine.tensors().items()}]
+    ref = []
+    for g in range(coarse_steps // gate_every):
+        fine.run(gate_every * spec.ratio)
+        ck = {k: torch.empty(shape_c, dtype=torch.float32, device=dev) for k in ("drho", "u", "v")}
+        filter_to(fine.tensors(), ck, spec, stream)
+        ref.append(ck)
+    fine.close()
+    timed = acm.Solver(spec.fine_config(), None, tensors=start, force_x=ff)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timed.run(coarse_steps * spec.ratio)
+    torch.cuda.synchronize()
+    t_fine = time.perf_counter() - t0
+    timed.close()
+    plain_states, _, t_plain = gated_run(spec, None, c0, coarse_steps, gate_every, energy_tol=1e9, div_tol=1e9)
+    cnn_states, gate, t_closure = gated_run(spec, net, c0, coarse_steps, gate_every, energy_tol, div_tol,
+                                            force_trip_at)
+    err_plain = [rel_l2_velocity(a, b) for a, b in zip(plain_states, ref)]
+    err_cnn = [rel_l2_velocity(a, b) for a, b in zip(cnn_states, ref)]
+    return {"seed": seed, "err_cnn_end": err_cnn[-1], "err_cnn_max": max(err_cnn),
+            "err_plain_end": err_plain[-1], "err_plain_max": max(err_plain), "gate": gate.__dict__,
+            "t_fine_s": t_fine, "t_closure_s": t_closure, "t_plain_coarse_s": t_plain,
+            "err_cnn": err_cnn, "err_plain": err_plain}

@@ -1,0 +1,761 @@
+// Learned-closure network on gfx950: 3x3 convolutions as implicit GEMMs on
+// the bf16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation), the
+// weight gradient as an MFMA reduction over pixels, and the element-wise
+// pieces (input packing, loss gradient, correction, Adam, box filter,
+// bilinear prolongation).
+//
+// Layouts (all device memory, caller-owned unless stated):
+//   activations  bf16 [H][W][C], channel fastest; C = 16 (padded 3-channel
+//                input / output) or 32
+//   weights      bf16 [9][C_out][C_in], tap t = (dy+1)*3 + (dx+1)
+//   bias, grads  fp32
+// Convolution: y[p][o] = b[o] + sum_{t,i} w[t][o][i] x[p + off(t)][i] with
+// circular (periodic) wrap.  MFMA operand mapping (16x16x16): A[i][k] in lane
+// i + 16*(k/4), element k%4; B[k][n] in lane n + 16*(k/4); D[i][n] in lane
+// n + 16*(i/4), element i%4.  Here i = pixel (forward) and k, n = channels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/acm.h"
+#include "acm_internal.h"
+
+namespace acm {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16_t;
+
+// float -> bf16, round to nearest even (finite inputs)
+__device__ __forceinline__ bf16_t f2bf(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((unsigned)h) << 16); }
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+enum : int { CONV_RELU = 0, CONV_RAW = 1, CONV_MASK = 2 };
+
+// ---------------------------------------------------------------------------
+// forward convolution: workgroup tile 8 rows x 32 columns, 4 waves; wave w
+// owns rows 2w, 2w+1, i.e. four groups of 16 pixels.  The input tile (with a
+// one-pixel circular halo) is staged in LDS; every wave keeps all weights of
+// the layer as MFMA B operands in registers.
+// MODE: CONV_RELU  y = bf16(relu(conv + b))
+//       CONV_RAW   y = fp32(conv + b)
+//       CONV_MASK  y = bf16(conv * (mask > 0))   (data gradient through ReLU)
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t* __restrict__ x,
+                                                      const bf16_t* __restrict__ w, const float* __restrict__ bias,
+                                                      const bf16_t* __restrict__ mask, void* __restrict__ y)
+{
+    constexpr int TR = 8, TC = 32, IR = TR + 2, IC = TC + 2;
+    constexpr int KS = CIN / 16, NH = COUT / 16, CH4 = CIN / 4;
+    __shared__ __align__(16) bf16_t sx[IR * IC * CIN];
+    const int tiles_x = W / TC;
+    const int x0 = (blockIdx.x % tiles_x) * TC, y0 = (blockIdx.x / tiles_x) * TR;
+    for (int q = threadIdx.x; q < IR * IC * CH4; q += 256) {
+        const int c4 = q % CH4, pix = q / CH4;
+        const int r = pix / IC, cc = pix - r * IC;
+        const int gy = wrap(y0 + r - 1, H), gx = wrap(x0 + cc - 1, W);
+        const uint2 v = *reinterpret_cast<const uint2*>(x + ((size_t)gy * W + gx) * CIN + c4 * 4);
+        *reinterpret_cast<uint2*>(sx + pix * CIN + c4 * 4) = v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lg = lane >> 4;
+    bf16x4 bw[9][KS][NH];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int nh = 0; nh < NH; ++nh)
+                bw[t][ks][nh] = *reinterpret_cast<const bf16x4*>(w + ((size_t)(t * COUT + nh * 16 + l16) * CIN +
+                                                                      ks * 16 + lg * 4));
+    __syncthreads();
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+        const int r = 2 * wave + (g >> 1), c0 = (g & 1) * 16;
+        f32x4 acc[NH];
+#pragma unroll
+        for (int nh = 0; nh < NH; ++nh) acc[nh] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            const int pix = (r + 1 + dy) * IC + (c0 + l16 + 1 + dx);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4*>(sx + pix * CIN + ks * 16 + lg * 4);
+#pragma unroll
+                for (int nh = 0; nh < NH; ++nh)
+                    acc[nh] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[t][ks][nh], acc[nh], 0, 0, 0);
+            }
+        }
+        const int py = y0 + r;
+#pragma unroll
+        for (int nh = 0; nh < NH; ++nh) {
+            const int co = nh * 16 + l16;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int px = x0 + c0 + 4 * lg + j;
+                const size_t o = ((size_t)py * W + px) * COUT + co;
+                float val = acc[nh][j];
+                if constexpr (MODE == CONV_RELU) {
+                    val = fmaxf(val + bias[co], 0.f);
+                    static_cast<bf16_t*>(y)[o] = f2bf(val);
+                } else if constexpr (MODE == CONV_RAW) {
+                    static_cast<float*>(y)[o] = val + bias[co];
+                } else {
+                    const bf16_t m = mask[o];
+                    const bool pos = (m & 0x8000u) == 0 && (m & 0x7FFFu) != 0;
+                    static_cast<bf16_t*>(y)[o] = f2bf(pos ? val : 0.f);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: dW[t][o][i] = sum_p g[p][o] x[p + off(t)][i], db[o] = sum_p g[p][o]
+// Workgroup tile 4 rows x 64 columns; x (with halo) and g are staged in LDS
+// channel-major so that four consecutive pixels of one channel are one
+// MFMA operand.  Each wave owns a quarter of the (tap, o-block, i-block)
+// 16x16 output tiles and accumulates over the tile's pixels; the partial
+// sums of every workgroup go to a workspace reduced in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int WG_TR = 4, WG_TC = 64;
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void conv_wgrad_kernel(int H, int W, const bf16_t* __restrict__ x,
+                                                         const bf16_t* __restrict__ g, float* __restrict__ partial)
+{
+    constexpr int XR = WG_TR + 2, XC = WG_TC + 4;  // columns x0-1 .. x0+64 (+1 pad), 8-byte aligned rows
+    __shared__ __align__(16) bf16_t sxT[XR][CIN][XC];
+    __shared__ __align__(16) bf16_t sgT[WG_TR][COUT][WG_TC];
+    const int tiles_x = W / WG_TC;
+    const int x0 = (blockIdx.x % tiles_x) * WG_TC, y0 = (blockIdx.x / tiles_x) * WG_TR;
+    for (int q = threadIdx.x; q < XR * (WG_TC + 2) * CIN; q += 256) {
+        const int ci = q % CIN, pix = q / CIN;
+        const int r = pix / (WG_TC + 2), cc = pix - r * (WG_TC + 2);
+        const int gy = wrap(y0 + r - 1, H), gx = wrap(x0 + cc - 1, W);
+        sxT[r][ci][cc] = x[((size_t)gy * W + gx) * CIN + ci];
+    }
+    for (int q = threadIdx.x; q < WG_TR * WG_TC * COUT; q += 256) {
+        const int co = q % COUT, pix = q / COUT;
+        const int r = pix / WG_TC, cc = pix - r * WG_TC;
+        sgT[r][co][cc] = g[((size_t)(y0 + r) * W + x0 + cc) * COUT + co];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lg = lane >> 4;
+    constexpr int OB = COUT / 16, IB = CIN / 16;
+    constexpr int NTILE = 9 * OB * IB;
+    constexpr int PER = (NTILE + 3) / 4;
+    f32x4 acc[PER];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int r = 0; r < WG_TR; ++r) {
+#pragma unroll 1
+        for (int kc = 0; kc < WG_TC / 16; ++kc) {
+#pragma unroll
+            for (int s = 0; s < PER; ++s) {
+                const int t = wave + 4 * s;
+                if (t < NTILE) {
+                    const int tap = t / (OB * IB), rem = t % (OB * IB);
+                    const int ob = rem / IB, ib = rem % IB;
+                    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                    // A[i = o][k = pixel]
+                    const bf16x4 a =
+                        *reinterpret_cast<const bf16x4*>(&sgT[r][ob * 16 + l16][kc * 16 + lg * 4]);
+                    // B[k = pixel][n = i]: x at (row r + dy, column + dx); unaligned, read element-wise
+                    const bf16_t* src = &sxT[r + 1 + dy][ib * 16 + l16][kc * 16 + lg * 4 + 1 + dx];
+                    bf16x4 b;
+                    b[0] = (short)src[0];
+                    b[1] = (short)src[1];
+                    b[2] = (short)src[2];
+                    b[3] = (short)src[3];
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float* part = partial + (size_t)blockIdx.x * (9 * COUT * CIN + COUT);
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const int t = wave + 4 * s;
+        if (t < NTILE) {
+            const int tap = t / (OB * IB), rem = t % (OB * IB);
+            const int ob = rem / IB, ib = rem % IB;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = ob * 16 + 4 * lg + j, i = ib * 16 + l16;
+                part[((size_t)tap * COUT + o) * CIN + i] = acc[s][j];
+            }
+        }
+    }
+    if ((int)threadIdx.x < COUT) {
+        float sb = 0.f;
+        for (int r = 0; r < WG_TR; ++r)
+            for (int c = 0; c < WG_TC; ++c) sb += bf2f(sgT[r][threadIdx.x][c]);
+        part[9 * COUT * CIN + threadIdx.x] = sb;
+    }
+}
+
+// fixed-order sum of the per-workgroup partials: out[e] = sum_b partial[b][e]
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ partial, int nblk, int n,
+                                                              float* __restrict__ dw, float* __restrict__ db, int nw)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * n + e];
+    if (e < nw) dw[e] = s;
+    else db[e - nw] = s;
+}
+
+// wt[t][i][o] = w[8 - t][o][i]: weights of the transposed convolution
+__global__ void transpose_weights_kernel(int cin, int cout, const bf16_t* __restrict__ w, bf16_t* __restrict__ wt)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= 9 * cin * cout) return;
+    const int t = e / (cin * cout), rem = e % (cin * cout);
+    const int i = rem / cout, o = rem % cout;
+    wt[e] = w[((size_t)(8 - t) * cout + o) * cin + i];
+}
+
+// normalised network input: a0[p][c] = bf16(s_c q_c[p]) for c < 3, zero above
+__global__ void pack_input_kernel(int n, const float* __restrict__ r, const float* __restrict__ u,
+                                  const float* __restrict__ v, float s0, float s1, float s2, bf16_t* __restrict__ a0)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    bf16_t out[16];
+    out[0] = f2bf(r[p] * s0);
+    out[1] = f2bf(u[p] * s1);
+    out[2] = f2bf(v[p] * s2);
+    for (int c = 3; c < 16; ++c) out[c] = 0;
+    uint4* dst = reinterpret_cast<uint4*>(a0 + (size_t)p * 16);
+    dst[0] = *reinterpret_cast<uint4*>(&out[0]);
+    dst[1] = *reinterpret_cast<uint4*>(&out[8]);
+}
+
+// correction: q_c[p] += d_c raw[p][c]
+__global__ void apply_correction_kernel(int n, const float* __restrict__ raw, float d0, float d1, float d2,
+                                        float* __restrict__ r, float* __restrict__ u, float* __restrict__ v)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const float* o = raw + (size_t)p * 16;
+    r[p] = fmaf(d0, o[0], r[p]);
+    u[p] = fmaf(d1, o[1], u[p]);
+    v[p] = fmaf(d2, o[2], v[p]);
+}
+
+// loss: target residual t_c = (target_c - base_c) / d_c; e = raw_c - t_c;
+// grad[p][c] = bf16(2 e / (3 n)) (zero for padded channels); per-block sum of e^2
+__global__ __launch_bounds__(256) void loss_grad_kernel(int n, const float* __restrict__ raw,
+                                                        const float* __restrict__ b0, const float* __restrict__ b1,
+                                                        const float* __restrict__ b2, const float* __restrict__ t0,
+                                                        const float* __restrict__ t1, const float* __restrict__ t2,
+                                                        float id0, float id1, float id2, bf16_t* __restrict__ grad,
+                                                        double* __restrict__ partial)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    double se = 0.0;
+    if (p < n) {
+        const float* o = raw + (size_t)p * 16;
+        const float e0 = o[0] - (t0[p] - b0[p]) * id0;
+        const float e1 = o[1] - (t1[p] - b1[p]) * id1;
+        const float e2 = o[2] - (t2[p] - b2[p]) * id2;
+        se = (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
+        const float k = 2.f / (3.f * (float)n);
+        bf16_t out[16];
+        out[0] = f2bf(k * e0);
+        out[1] = f2bf(k * e1);
+        out[2] = f2bf(k * e2);
+        for (int c = 3; c < 16; ++c) out[c] = 0;
+        uint4* dst = reinterpret_cast<uint4*>(grad + (size_t)p * 16);
+        dst[0] = *reinterpret_cast<uint4*>(&out[0]);
+        dst[1] = *reinterpret_cast<uint4*>(&out[8]);
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = se;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void loss_final_kernel(const double* __restrict__ partial, int nblk, int n, double* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[b];
+    out[0] = s / (3.0 * n);
+}
+
+// Adam (Kingma & Ba) with bias correction; p16 (optional) receives bf16(p)
+__global__ void adam_kernel(int n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, bf16_t* __restrict__ p16, float lr, float b1, float b2, float eps,
+                            float c1, float c2)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float ge = g[e];
+    const float me = fmaf(b1, m[e], (1.f - b1) * ge);
+    const float ve = fmaf(b2, v[e], (1.f - b2) * ge * ge);
+    m[e] = me;
+    v[e] = ve;
+    const float pe = p[e] - lr * (me / c1) / (sqrtf(ve / c2) + eps);
+    p[e] = pe;
+    if (p16) p16[e] = f2bf(pe);
+}
+
+__global__ void to_bf16_kernel(size_t n, const float* __restrict__ s, bf16_t* __restrict__ d)
+{
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) d[e] = f2bf(s[e]);
+}
+
+// box filter: coarse node (I, J) averages fine nodes (rI..rI+r-1, rJ..rJ+r-1)
+template <typename T>
+__global__ void box_filter_kernel(int nxc, int nyc, int r, const T* __restrict__ f, T* __restrict__ c)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= nxc * nyc) return;
+    const int J = e / nxc, I = e - J * nxc;
+    const int nxf = nxc * r;
+    double s = 0.0;
+    for (int b = 0; b < r; ++b)
+        for (int a = 0; a < r; ++a) s += (double)f[(size_t)(J * r + b) * nxf + I * r + a];
+    c[e] = (T)(s / (double)(r * r));
+}
+
+// periodic bilinear prolongation; coarse node I sits at fine coordinate r I + (r-1)/2
+template <typename T>
+__global__ void prolong_kernel(int nxc, int nyc, int r, const T* __restrict__ c, T* __restrict__ f)
+{
+    const int nxf = nxc * r, nyf = nyc * r;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= nxf * nyf) return;
+    const int j = e / nxf, i = e - j * nxf;
+    const double sx = (i - 0.5 * (r - 1)) / r, sy = (j - 0.5 * (r - 1)) / r;
+    const int ix = (int)floor(sx), iy = (int)floor(sy);
+    const double tx = sx - ix, ty = sy - iy;
+    const int x0 = (ix % nxc + nxc) % nxc, x1 = (x0 + 1) % nxc;
+    const int y0 = (iy % nyc + nyc) % nyc, y1 = (y0 + 1) % nyc;
+    const double a = (double)c[(size_t)y0 * nxc + x0] * (1 - tx) + (double)c[(size_t)y0 * nxc + x1] * tx;
+    const double b = (double)c[(size_t)y1 * nxc + x0] * (1 - tx) + (double)c[(size_t)y1 * nxc + x1] * tx;
+    f[e] = (T)(a * (1 - ty) + b * ty);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, int MODE>
+hipError_t launch_conv(int H, int W, const bf16_t* x, const bf16_t* w, const float* b, const bf16_t* mask, void* y,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL((conv3x3_kernel<CIN, COUT, MODE>), dim3((W / 32) * (H / 8)), dim3(256), 0, s, H, W, x, w, b,
+                       mask, y);
+    return hipGetLastError();
+}
+
+hipError_t conv_dispatch(int H, int W, int cin, int cout, int mode, const void* x, const void* w, const float* b,
+                         const void* mask, void* y, hipStream_t s)
+{
+    const bf16_t* xx = static_cast<const bf16_t*>(x);
+    const bf16_t* ww = static_cast<const bf16_t*>(w);
+    const bf16_t* mm = static_cast<const bf16_t*>(mask);
+    if (cin == 16 && cout == 32 && mode == CONV_RELU) return launch_conv<16, 32, CONV_RELU>(H, W, xx, ww, b, mm, y, s);
+    if (cin == 32 && cout == 32 && mode == CONV_RELU) return launch_conv<32, 32, CONV_RELU>(H, W, xx, ww, b, mm, y, s);
+    if (cin == 32 && cout == 16 && mode == CONV_RAW) return launch_conv<32, 16, CONV_RAW>(H, W, xx, ww, b, mm, y, s);
+    if (cin == 16 && cout == 32 && mode == CONV_MASK) return launch_conv<16, 32, CONV_MASK>(H, W, xx, ww, b, mm, y, s);
+    if (cin == 32 && cout == 32 && mode == CONV_MASK) return launch_conv<32, 32, CONV_MASK>(H, W, xx, ww, b, mm, y, s);
+    if (cin == 32 && cout == 32 && mode == CONV_RAW) return launch_conv<32, 32, CONV_RAW>(H, W, xx, ww, b, mm, y, s);
+    if (cin == 16 && cout == 32 && mode == CONV_RAW) return launch_conv<16, 32, CONV_RAW>(H, W, xx, ww, b, mm, y, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace acm
+
+using namespace acm;
+
+namespace acm {
+void set_error(const std::string& msg);
+acm_status api_validate(const acm_config* c, std::string& err);
+double api_max_amplification(const acm_config& c);
+template <typename T>
+Coef<T> api_make_coef(const acm_config& c, const void* force_x);
+}  // namespace acm
+
+namespace {
+acm_status cfail(acm_status s, const std::string& m)
+{
+    set_error(m);
+    return s;
+}
+acm_status chip(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return ACM_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorInvalidValue ? ACM_EINVAL : ACM_EHIP;
+}
+bool grid_ok(int nx, int ny) { return nx > 0 && ny > 0 && nx % 64 == 0 && ny % 8 == 0; }
+int blocks_for(size_t n) { return (int)((n + 255) / 256); }
+}  // namespace
+
+extern "C" {
+
+acm_status acm_cnn_layer_shape(int32_t layer, int32_t* cin, int32_t* cout)
+{
+    static const int ci[ACM_CNN_LAYERS] = {16, 32, 32, 32, 32};
+    static const int co[ACM_CNN_LAYERS] = {32, 32, 32, 32, 16};
+    if (layer < 0 || layer >= ACM_CNN_LAYERS) return cfail(ACM_EINVAL, "layer out of range");
+    if (cin) *cin = ci[layer];
+    if (cout) *cout = co[layer];
+    return ACM_OK;
+}
+
+acm_status acm_cnn_conv(int32_t nx, int32_t ny, int32_t cin, int32_t cout, int32_t mode, const void* x, const void* w,
+                        const float* bias, const void* mask, void* y, void* stream)
+{
+    if (!grid_ok(nx, ny)) return cfail(ACM_EINVAL, "network grids need nx % 64 == 0 and ny % 8 == 0");
+    if (!x || !w || !y || (mode != CONV_MASK && !bias) || (mode == CONV_MASK && !mask))
+        return cfail(ACM_EINVAL, "NULL pointer");
+    return chip(conv_dispatch(ny, nx, cin, cout, mode, x, w, bias, mask, y, static_cast<hipStream_t>(stream)),
+                "unsupported (cin, cout, mode) or launch failure");
+}
+
+size_t acm_cnn_wgrad_workspace(int32_t nx, int32_t ny, int32_t cin, int32_t cout)
+{
+    if (!grid_ok(nx, ny)) return 0;
+    const size_t nblk = (size_t)(nx / WG_TC) * (ny / WG_TR);
+    return nblk * (size_t)(9 * cout * cin + cout) * sizeof(float);
+}
+
+acm_status acm_cnn_wgrad(int32_t nx, int32_t ny, int32_t cin, int32_t cout, const void* x, const void* g,
+                         float* workspace, float* dw, float* db, void* stream)
+{
+    if (!grid_ok(nx, ny)) return cfail(ACM_EINVAL, "network grids need nx % 64 == 0 and ny % 8 == 0");
+    if (!x || !g || !workspace || !dw || !db) return cfail(ACM_EINVAL, "NULL pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nblk = (nx / WG_TC) * (ny / WG_TR);
+    const bf16_t* xx = static_cast<const bf16_t*>(x);
+    const bf16_t* gg = static_cast<const bf16_t*>(g);
+    if (cin == 16 && cout == 32)
+        hipLaunchKernelGGL((conv_wgrad_kernel<16, 32>), dim3(nblk), dim3(256), 0, s, ny, nx, xx, gg, workspace);
+    else if (cin == 32 && cout == 32)
+        hipLaunchKernelGGL((conv_wgrad_kernel<32, 32>), dim3(nblk), dim3(256), 0, s, ny, nx, xx, gg, workspace);
+    else if (cin == 32 && cout == 16)
+        hipLaunchKernelGGL((conv_wgrad_kernel<32, 16>), dim3(nblk), dim3(256), 0, s, ny, nx, xx, gg, workspace);
+    else
+        return cfail(ACM_EINVAL, "unsupported (cin, cout)");
+    acm_status st = chip(hipGetLastError(), "wgrad launch");
+    if (st != ACM_OK) return st;
+    const int n = 9 * cout * cin + cout;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(n)), dim3(256), 0, s, workspace, nblk, n, dw, db,
+                       9 * cout * cin);
+    return chip(hipGetLastError(), "reduce launch");
+}
+
+acm_status acm_cnn_transpose(int32_t cin, int32_t cout, const void* w, void* wt, void* stream)
+{
+    if (!w || !wt || cin <= 0 || cout <= 0) return cfail(ACM_EINVAL, "bad transpose arguments");
+    hipLaunchKernelGGL(transpose_weights_kernel, dim3(blocks_for((size_t)9 * cin * cout)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), cin, cout, static_cast<const bf16_t*>(w),
+                       static_cast<bf16_t*>(wt));
+    return chip(hipGetLastError(), "transpose launch");
+}
+
+acm_status acm_cnn_pack(int32_t nx, int32_t ny, const float* drho, const float* u, const float* v,
+                        const float* in_scale, void* a0, void* stream)
+{
+    if (!drho || !u || !v || !in_scale || !a0 || nx <= 0 || ny <= 0) return cfail(ACM_EINVAL, "bad pack arguments");
+    const int n = nx * ny;
+    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, drho,
+                       u, v, in_scale[0], in_scale[1], in_scale[2], static_cast<bf16_t*>(a0));
+    return chip(hipGetLastError(), "pack launch");
+}
+
+acm_status acm_cnn_apply(int32_t nx, int32_t ny, const float* raw, const float* out_scale, float* drho, float* u,
+                         float* v, void* stream)
+{
+    if (!raw || !out_scale || !drho || !u || !v || nx <= 0 || ny <= 0) return cfail(ACM_EINVAL, "bad apply arguments");
+    const int n = nx * ny;
+    hipLaunchKernelGGL(apply_correction_kernel, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       n, raw, out_scale[0], out_scale[1], out_scale[2], drho, u, v);
+    return chip(hipGetLastError(), "apply launch");
+}
+
+size_t acm_cnn_loss_workspace(int32_t nx, int32_t ny) { return (size_t)blocks_for((size_t)nx * ny) * sizeof(double); }
+
+acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* const* base, const float* const* target,
+                        const float* out_scale, void* grad, double* workspace, double* loss, void* stream)
+{
+    if (!raw || !base || !target || !out_scale || !grad || !workspace || !loss) return cfail(ACM_EINVAL, "NULL pointer");
+    const int n = nx * ny;
+    const int nb = blocks_for(n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, n, raw, base[0], base[1], base[2], target[0],
+                       target[1], target[2], 1.f / out_scale[0], 1.f / out_scale[1], 1.f / out_scale[2],
+                       static_cast<bf16_t*>(grad), workspace);
+    acm_status st = chip(hipGetLastError(), "loss launch");
+    if (st != ACM_OK) return st;
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, workspace, nb, n, loss);
+    return chip(hipGetLastError(), "loss final launch");
+}
+
+acm_status acm_cnn_adam(int64_t n, float* p, const float* g, float* m, float* v, void* p16, float lr, float b1,
+                        float b2, float eps, int64_t t, void* stream)
+{
+    if (n <= 0 || !p || !g || !m || !v || t < 1) return cfail(ACM_EINVAL, "bad Adam arguments");
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for((size_t)n)), dim3(256), 0, static_cast<hipStream_t>(stream), (int)n,
+                       p, g, m, v, static_cast<bf16_t*>(p16), lr, b1, b2, eps, c1, c2);
+    return chip(hipGetLastError(), "adam launch");
+}
+
+acm_status acm_cnn_to_bf16(size_t n, const float* src, void* dst, void* stream)
+{
+    if (!src || !dst) return cfail(ACM_EINVAL, "NULL pointer");
+    if (n == 0) return ACM_OK;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, src,
+                       static_cast<bf16_t*>(dst));
+    return chip(hipGetLastError(), "to_bf16 launch");
+}
+
+acm_status acm_filter_box(int32_t nxf, int32_t nyf, int32_t factor, int32_t precision, const acm_fields* fine,
+                          const acm_fields* coarse, void* stream)
+{
+    if (!fine || !coarse || factor < 1 || nxf % factor || nyf % factor) return cfail(ACM_EINVAL, "bad filter arguments");
+    const int nxc = nxf / factor, nyc = nyf / factor;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* const src[3] = {fine->drho, fine->u, fine->v};
+    void* const dst[3] = {coarse->drho, coarse->u, coarse->v};
+    for (int k = 0; k < 3; ++k) {
+        if (!src[k] || !dst[k]) return cfail(ACM_EINVAL, "NULL field");
+        if (precision == ACM_F64)
+            hipLaunchKernelGGL((box_filter_kernel<double>), dim3(blocks_for((size_t)nxc * nyc)), dim3(256), 0, s, nxc,
+                               nyc, factor, static_cast<const double*>(src[k]), static_cast<double*>(dst[k]));
+        else
+            hipLaunchKernelGGL((box_filter_kernel<float>), dim3(blocks_for((size_t)nxc * nyc)), dim3(256), 0, s, nxc,
+                               nyc, factor, static_cast<const float*>(src[k]), static_cast<float*>(dst[k]));
+    }
+    return chip(hipGetLastError(), "filter launch");
+}
+
+acm_status acm_prolong_bilinear(int32_t nxc, int32_t nyc, int32_t factor, int32_t precision, const acm_fields* coarse,
+                                const acm_fields* fine, void* stream)
+{
+    if (!fine || !coarse || factor < 1 || nxc < 1 || nyc < 1) return cfail(ACM_EINVAL, "bad prolongation arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t nf = (size_t)nxc * nyc * factor * factor;
+    void* const src[3] = {coarse->drho, coarse->u, coarse->v};
+    void* const dst[3] = {fine->drho, fine->u, fine->v};
+    for (int k = 0; k < 3; ++k) {
+        if (!src[k] || !dst[k]) return cfail(ACM_EINVAL, "NULL field");
+        if (precision == ACM_F64)
+            hipLaunchKernelGGL((prolong_kernel<double>), dim3(blocks_for(nf)), dim3(256), 0, s, nxc, nyc, factor,
+                               static_cast<const double*>(src[k]), static_cast<double*>(dst[k]));
+        else
+            hipLaunchKernelGGL((prolong_kernel<float>), dim3(blocks_for(nf)), dim3(256), 0, s, nxc, nyc, factor,
+                               static_cast<const float*>(src[k]), static_cast<float*>(dst[k]));
+    }
+    return chip(hipGetLastError(), "prolongation launch");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// closure inference: per coarse step, the SMAME step then the network
+// correction, captured as HIP graphs of `chunk` steps.
+// ---------------------------------------------------------------------------
+struct acm_closure {
+    acm_config cfg;
+    acm_fields set[2];
+    const void* force_x = nullptr;
+    const void* w[ACM_CNN_LAYERS];
+    const float* b[ACM_CNN_LAYERS];
+    float in_scale[3], out_scale[3];
+    bf16_t* act[ACM_CNN_LAYERS];  // layer inputs a0..a4 in the workspace
+    float* raw = nullptr;
+    hipStream_t stream = nullptr, cap = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int chunk = 100;
+    int which = 0;
+    int64_t step = 0;
+    int use_net = 1;
+    Coef<float> coef;
+};
+
+namespace {
+
+hipError_t closure_step(acm_closure* h, int from, hipStream_t s)
+{
+    const acm_fields& in = h->set[from];
+    const acm_fields& out = h->set[1 - from];
+    const State<float> si{static_cast<float*>(in.drho), static_cast<float*>(in.u), static_cast<float*>(in.v), nullptr,
+                          nullptr};
+    const State<float> so{static_cast<float*>(out.drho), static_cast<float*>(out.u), static_cast<float*>(out.v),
+                          nullptr, nullptr};
+    hipError_t e = launch_step2d<float>(h->coef, si, so, h->cfg.tile, s);
+    if (e != hipSuccess || !h->use_net) return e;
+    const int nx = h->cfg.nx, ny = h->cfg.ny, n = nx * ny;
+    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, so.r, so.u, so.v, h->in_scale[0],
+                       h->in_scale[1], h->in_scale[2], h->act[0]);
+    int ci, co;
+    for (int l = 0; l < ACM_CNN_LAYERS; ++l) {
+        acm_cnn_layer_shape(l, &ci, &co);
+        void* y = (l + 1 < ACM_CNN_LAYERS) ? static_cast<void*>(h->act[l + 1]) : static_cast<void*>(h->raw);
+        e = conv_dispatch(ny, nx, ci, co, l + 1 < ACM_CNN_LAYERS ? CONV_RELU : CONV_RAW, h->act[l], h->w[l], h->b[l],
+                          nullptr, y, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(apply_correction_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, h->raw, h->out_scale[0],
+                       h->out_scale[1], h->out_scale[2], so.r, so.u, so.v);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t acm_closure_workspace(int32_t nx, int32_t ny)
+{
+    const size_t n = (size_t)nx * ny;
+    return n * 16 * 2 + 4 * n * 32 * 2 + n * 16 * 4;  // a0 (16 ch) + a1..a4 (32 ch) bf16 + raw fp32 (16 ch)
+}
+
+acm_status acm_closure_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b, const void* force_x,
+                            const void* const* weights, const float* const* biases, const float* in_scale,
+                            const float* out_scale, void* workspace, int32_t chunk, void* stream, acm_closure** out)
+{
+    if (!out) return cfail(ACM_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string err;
+    if (api_validate(cfg, err) != ACM_OK) return cfail(ACM_EINVAL, err);
+    if (cfg->dim != 2 || cfg->two_phase || cfg->precision != ACM_F32)
+        return cfail(ACM_EINVAL, "the closure runs 2D single-phase FP32 coarse grids");
+    if (!grid_ok(cfg->nx, cfg->ny)) return cfail(ACM_EINVAL, "closure grids need nx % 64 == 0 and ny % 8 == 0");
+    if (!a || !b || !a->drho || !a->u || !a->v || !b->drho || !b->u || !b->v || !weights || !biases || !in_scale ||
+        !out_scale || !workspace)
+        return cfail(ACM_EINVAL, "NULL pointer");
+    if (chunk < 0 || chunk % 2) return cfail(ACM_EINVAL, "chunk must be even");
+    if (!cfg->allow_unstable && api_max_amplification(*cfg) > 1.0 + 1e-12)
+        return cfail(ACM_EUNSTABLE, "coarse step fails the linear stability check");
+    acm_closure* h = new (std::nothrow) acm_closure();
+    if (!h) return cfail(ACM_EINVAL, "out of host memory");
+    h->cfg = *cfg;
+    h->set[0] = *a;
+    h->set[1] = *b;
+    h->force_x = force_x;
+    for (int l = 0; l < ACM_CNN_LAYERS; ++l) {
+        h->w[l] = weights[l];
+        h->b[l] = biases[l];
+        if (!h->w[l] || !h->b[l]) {
+            delete h;
+            return cfail(ACM_EINVAL, "NULL layer parameters");
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        h->in_scale[c] = in_scale[c];
+        h->out_scale[c] = out_scale[c];
+    }
+    const size_t n = (size_t)cfg->nx * cfg->ny;
+    char* ws = static_cast<char*>(workspace);
+    h->act[0] = reinterpret_cast<bf16_t*>(ws);
+    ws += n * 16 * 2;
+    for (int l = 1; l < ACM_CNN_LAYERS; ++l) {
+        h->act[l] = reinterpret_cast<bf16_t*>(ws);
+        ws += n * 32 * 2;
+    }
+    h->raw = reinterpret_cast<float*>(ws);
+    h->chunk = chunk > 0 ? chunk : 100;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->coef = api_make_coef<float>(*cfg, force_x);
+    hipError_t e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete h;
+        return chip(e, "stream create");
+    }
+    *out = h;
+    return ACM_OK;
+}
+
+acm_status acm_closure_set_network(acm_closure* h, int32_t enabled)
+{
+    if (!h) return cfail(ACM_EINVAL, "closure is NULL");
+    if ((enabled != 0) != (h->use_net != 0)) {
+        for (int p = 0; p < 2; ++p)
+            if (h->exec[p]) {
+                hipGraphExecDestroy(h->exec[p]);
+                h->exec[p] = nullptr;
+            }
+    }
+    h->use_net = enabled ? 1 : 0;
+    return ACM_OK;
+}
+
+acm_status acm_closure_run(acm_closure* h, int64_t nsteps)
+{
+    if (!h || nsteps < 0) return cfail(ACM_EINVAL, "bad closure run arguments");
+    while (nsteps >= h->chunk) {
+        const int p = h->which;
+        if (!h->exec[p]) {
+            hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return chip(e, "capture");
+            for (int i = 0; i < h->chunk && e == hipSuccess; ++i) e = closure_step(h, (p + i) & 1, h->cap);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(h->cap, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) hipGraphDestroy(g);
+                return chip(e != hipSuccess ? e : e2, "closure capture");
+            }
+            e = hipGraphInstantiate(&h->exec[p], g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return chip(e, "closure instantiate");
+        }
+        acm_status st = chip(hipGraphLaunch(h->exec[p], h->stream), "closure graph launch");
+        if (st != ACM_OK) return st;
+        h->step += h->chunk;
+        nsteps -= h->chunk;
+    }
+    for (int64_t i = 0; i < nsteps; ++i) {
+        acm_status st = chip(closure_step(h, h->which, h->stream), "closure step");
+        if (st != ACM_OK) return st;
+        h->which ^= 1;
+        h->step += 1;
+    }
+    return ACM_OK;
+}
+
+acm_status acm_closure_current(const acm_closure* h, int32_t* which, int64_t* step)
+{
+    if (!h) return cfail(ACM_EINVAL, "closure is NULL");
+    if (which) *which = h->which;
+    if (step) *step = h->step;
+    return ACM_OK;
+}
+
+void acm_closure_destroy(acm_closure* h)
+{
+    if (!h) return;
+    hipStreamSynchronize(h->stream);
+    for (int p = 0; p < 2; ++p)
+        if (h->exec[p]) hipGraphExecDestroy(h->exec[p]);
+    if (h->cap) hipStreamDestroy(h->cap);
+    delete h;
+}
+
+}  // extern "C"
