@@ -40,34 +40,48 @@ __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((unsig
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-enum : int { CONV_RELU = 0, CONV_RAW = 1, CONV_MASK = 2 };
+enum : int { CONV_RELU = 0, CONV_RAW = 1, CONV_MASK = 2, CONV_APPLY = 3 };
+
+// fp32 state fields corrected in place by the last layer (CONV_APPLY)
+struct ApplyArgs {
+    float* q[3];
+    float d[3];
+};
+
+// Optional source of the first layer's input: the fp32 state itself,
+// normalised and rounded to bf16 while the tile is staged (channels 3..15
+// are zero), so no separate packing pass is needed.
+struct StateIn {
+    const float* q[3];
+    float s[3];
+};
 
 // ---------------------------------------------------------------------------
-// forward convolution: workgroup tile 8 rows x 32 columns, 4 waves; wave w
-// owns rows 2w, 2w+1, i.e. four groups of 16 pixels.  The input tile (with a
-// one-pixel circular halo) is staged in LDS; every wave keeps all weights of
-// the layer as MFMA B operands in registers.
-// MODE: CONV_RELU  y = bf16(relu(conv + b))
-//       CONV_RAW   y = fp32(conv + b)
-//       CONV_MASK  y = bf16(conv * (mask > 0))   (data gradient through ReLU)
+// forward convolution: workgroup tile TR rows x 32 columns, 4 waves; wave w
+// owns TR/4 rows, i.e. TR/2 groups of 16 pixels, whose accumulators are
+// advanced together so consecutive MFMAs are independent.  The weights of
+// the layer are fetched into registers (MFMA B operands) before the input
+// tile (with a one-pixel circular halo) is staged in LDS, so both loads are
+// in flight together.
+// MODE: CONV_RELU   y = bf16(relu(conv + b))
+//       CONV_RAW    y = fp32(conv + b)
+//       CONV_MASK   y = bf16(conv * (mask > 0))   (data gradient through ReLU)
+//       CONV_APPLY  q_c += d_c (conv + b)_c for c < 3  (closure correction)
+// FROM_STATE: the input is StateIn (fp32 state, CIN = 16) instead of x.
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, int MODE>
+template <int CIN, int COUT, int MODE, bool FROM_STATE = false, int TR = 4>
 __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t* __restrict__ x,
                                                       const bf16_t* __restrict__ w, const float* __restrict__ bias,
-                                                      const bf16_t* __restrict__ mask, void* __restrict__ y)
+                                                      const bf16_t* __restrict__ mask, void* __restrict__ y,
+                                                      ApplyArgs ap, StateIn sin)
 {
-    constexpr int TR = 8, TC = 32, IR = TR + 2, IC = TC + 2;
+    constexpr int TC = 32, IR = TR + 2, IC = TC + 2;
     constexpr int KS = CIN / 16, NH = COUT / 16, CH4 = CIN / 4;
+    constexpr int NG = TR / 2;  // 16-pixel groups per wave
+    static_assert(!FROM_STATE || CIN == 16, "state input has 16 (padded) channels");
     __shared__ __align__(16) bf16_t sx[IR * IC * CIN];
     const int tiles_x = W / TC;
     const int x0 = (blockIdx.x % tiles_x) * TC, y0 = (blockIdx.x / tiles_x) * TR;
-    for (int q = threadIdx.x; q < IR * IC * CH4; q += 256) {
-        const int c4 = q % CH4, pix = q / CH4;
-        const int r = pix / IC, cc = pix - r * IC;
-        const int gy = wrap(y0 + r - 1, H), gx = wrap(x0 + cc - 1, W);
-        const uint2 v = *reinterpret_cast<const uint2*>(x + ((size_t)gy * W + gx) * CIN + c4 * 4);
-        *reinterpret_cast<uint2*>(sx + pix * CIN + c4 * 4) = v;
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lg = lane >> 4;
     bf16x4 bw[9][KS][NH];
@@ -79,25 +93,82 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t
             for (int nh = 0; nh < NH; ++nh)
                 bw[t][ks][nh] = *reinterpret_cast<const bf16x4*>(w + ((size_t)(t * COUT + nh * 16 + l16) * CIN +
                                                                       ks * 16 + lg * 4));
-    __syncthreads();
-#pragma unroll 1
-    for (int g = 0; g < 4; ++g) {
-        const int r = 2 * wave + (g >> 1), c0 = (g & 1) * 16;
-        f32x4 acc[NH];
+    if constexpr (FROM_STATE) {
+        constexpr int NIT = (IR * IC + 255) / 256;
+        float v0[NIT], v1[NIT], v2[NIT];
 #pragma unroll
-        for (int nh = 0; nh < NH; ++nh) acc[nh] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int it = 0; it < NIT; ++it) {  // all loads first, then the LDS stores
+            const int pix = min((int)threadIdx.x + it * 256, IR * IC - 1);
+            const int r = pix / IC, cc = pix - r * IC;
+            const size_t src = (size_t)wrap(y0 + r - 1, H) * W + wrap(x0 + cc - 1, W);
+            v0[it] = sin.q[0][src];
+            v1[it] = sin.q[1][src];
+            v2[it] = sin.q[2][src];
+        }
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int dy = t / 3 - 1, dx = t % 3 - 1;
-            const int pix = (r + 1 + dy) * IC + (c0 + l16 + 1 + dx);
+        for (int it = 0; it < NIT; ++it) {
+            const int pix = threadIdx.x + it * 256;
+            if (pix < IR * IC) {
+                bf16_t v[16];
+                v[0] = f2bf(v0[it] * sin.s[0]);
+                v[1] = f2bf(v1[it] * sin.s[1]);
+                v[2] = f2bf(v2[it] * sin.s[2]);
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const bf16x4 a = *reinterpret_cast<const bf16x4*>(sx + pix * CIN + ks * 16 + lg * 4);
-#pragma unroll
-                for (int nh = 0; nh < NH; ++nh)
-                    acc[nh] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[t][ks][nh], acc[nh], 0, 0, 0);
+                for (int c = 3; c < 16; ++c) v[c] = 0;
+                uint4* dst = reinterpret_cast<uint4*>(sx + pix * 16);
+                dst[0] = *reinterpret_cast<uint4*>(&v[0]);
+                dst[1] = *reinterpret_cast<uint4*>(&v[8]);
             }
         }
+    } else {
+        constexpr int TOT = IR * IC * CH4;
+        constexpr int NIT = (TOT + 255) / 256;
+        uint2 v[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {  // all loads first, then the LDS stores
+            const int q = min((int)threadIdx.x + it * 256, TOT - 1);
+            const int c4 = q % CH4, pix = q / CH4;
+            const int r = pix / IC, cc = pix - r * IC;
+            const int gy = wrap(y0 + r - 1, H), gx = wrap(x0 + cc - 1, W);
+            v[it] = *reinterpret_cast<const uint2*>(x + ((size_t)gy * W + gx) * CIN + c4 * 4);
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = threadIdx.x + it * 256;
+            if (q < TOT) {
+                const int c4 = q % CH4, pix = q / CH4;
+                *reinterpret_cast<uint2*>(sx + pix * CIN + c4 * 4) = v[it];
+            }
+        }
+    }
+    __syncthreads();
+    f32x4 acc[NG][NH];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int nh = 0; nh < NH; ++nh) acc[g][nh] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            bf16x4 a[NG];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const int r = (TR / 4) * wave + (g >> 1), c0 = (g & 1) * 16;
+                const int pix = (r + 1 + dy) * IC + (c0 + l16 + 1 + dx);
+                a[g] = *reinterpret_cast<const bf16x4*>(sx + pix * CIN + ks * 16 + lg * 4);
+            }
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+#pragma unroll
+                for (int nh = 0; nh < NH; ++nh)
+                    acc[g][nh] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g], bw[t][ks][nh], acc[g][nh], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int r = (TR / 4) * wave + (g >> 1), c0 = (g & 1) * 16;
         const int py = y0 + r;
 #pragma unroll
         for (int nh = 0; nh < NH; ++nh) {
@@ -106,12 +177,18 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t
             for (int j = 0; j < 4; ++j) {
                 const int px = x0 + c0 + 4 * lg + j;
                 const size_t o = ((size_t)py * W + px) * COUT + co;
-                float val = acc[nh][j];
+                float val = acc[g][nh][j];
                 if constexpr (MODE == CONV_RELU) {
                     val = fmaxf(val + bias[co], 0.f);
                     static_cast<bf16_t*>(y)[o] = f2bf(val);
                 } else if constexpr (MODE == CONV_RAW) {
                     static_cast<float*>(y)[o] = val + bias[co];
+                } else if constexpr (MODE == CONV_APPLY) {
+                    if (co < 3) {
+                        float* qc = ap.q[co];
+                        const size_t p = (size_t)py * W + px;
+                        qc[p] = fmaf(ap.d[co], val + bias[co], qc[p]);
+                    }
                 } else {
                     const bf16_t m = mask[o];
                     const bool pos = (m & 0x8000u) == 0 && (m & 0x7FFFu) != 0;
@@ -362,12 +439,14 @@ __global__ void prolong_kernel(int nxc, int nyc, int r, const T* __restrict__ c,
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, int MODE>
+constexpr int CONV_TR = 4;  // rows per workgroup tile (two workgroups per CU at 256 x 256)
+
+template <int CIN, int COUT, int MODE, bool FROM_STATE = false>
 hipError_t launch_conv(int H, int W, const bf16_t* x, const bf16_t* w, const float* b, const bf16_t* mask, void* y,
-                       hipStream_t s)
+                       hipStream_t s, ApplyArgs ap = ApplyArgs{}, StateIn sin = StateIn{})
 {
-    hipLaunchKernelGGL((conv3x3_kernel<CIN, COUT, MODE>), dim3((W / 32) * (H / 8)), dim3(256), 0, s, H, W, x, w, b,
-                       mask, y);
+    hipLaunchKernelGGL((conv3x3_kernel<CIN, COUT, MODE, FROM_STATE, CONV_TR>), dim3((W / 32) * (H / CONV_TR)),
+                       dim3(256), 0, s, H, W, x, w, b, mask, y, ap, sin);
     return hipGetLastError();
 }
 
@@ -612,19 +691,23 @@ hipError_t closure_step(acm_closure* h, int from, hipStream_t s)
     hipError_t e = launch_step2d<float>(h->coef, si, so, h->cfg.tile, s);
     if (e != hipSuccess || !h->use_net) return e;
     const int nx = h->cfg.nx, ny = h->cfg.ny, n = nx * ny;
-    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, so.r, so.u, so.v, h->in_scale[0],
-                       h->in_scale[1], h->in_scale[2], h->act[0]);
+    (void)n;
+    // first layer reads the new state directly (normalised while staged)
+    StateIn sin{{so.r, so.u, so.v}, {h->in_scale[0], h->in_scale[1], h->in_scale[2]}};
+    e = launch_conv<16, 32, CONV_RELU, true>(ny, nx, nullptr, static_cast<const bf16_t*>(h->w[0]), h->b[0], nullptr,
+                                             h->act[1], s, ApplyArgs{}, sin);
+    if (e != hipSuccess) return e;
     int ci, co;
-    for (int l = 0; l < ACM_CNN_LAYERS; ++l) {
+    for (int l = 1; l + 1 < ACM_CNN_LAYERS; ++l) {
         acm_cnn_layer_shape(l, &ci, &co);
-        void* y = (l + 1 < ACM_CNN_LAYERS) ? static_cast<void*>(h->act[l + 1]) : static_cast<void*>(h->raw);
-        e = conv_dispatch(ny, nx, ci, co, l + 1 < ACM_CNN_LAYERS ? CONV_RELU : CONV_RAW, h->act[l], h->w[l], h->b[l],
-                          nullptr, y, s);
+        e = conv_dispatch(ny, nx, ci, co, CONV_RELU, h->act[l], h->w[l], h->b[l], nullptr, h->act[l + 1], s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(apply_correction_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, h->raw, h->out_scale[0],
-                       h->out_scale[1], h->out_scale[2], so.r, so.u, so.v);
-    return hipGetLastError();
+    // last layer: the correction is added to the new state in the epilogue
+    ApplyArgs ap{{so.r, so.u, so.v}, {h->out_scale[0], h->out_scale[1], h->out_scale[2]}};
+    const int L = ACM_CNN_LAYERS - 1;
+    return launch_conv<32, 16, CONV_APPLY>(ny, nx, h->act[L], static_cast<const bf16_t*>(h->w[L]), h->b[L], nullptr,
+                                           nullptr, s, ap);
 }
 
 }  // namespace

@@ -43,41 +43,60 @@ __device__ __forceinline__ T rho_new_2d(const Coef<T>& c, const T* sr, const T* 
     return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
 }
 
-// Stage fields (drho, u, v) of the (TX+4)x(TY+4) region into LDS.
+// Stage fields (drho, u, v) of the (TX+4)x(TY+4) region into LDS.  Every
+// load of the thread is issued before the first LDS store, so the memory
+// latencies overlap instead of adding up.
 template <typename T, int TX, int TY, int NT>
 __device__ __forceinline__ void stage2d(const Coef<T>& c, const State<T>& in, int x0, int y0,
                                         bool interior, T* sr, T* su, T* sv)
 {
     using S = Shape2<TX, TY>;
-    for (int q = threadIdx.x; q < S::RXY; q += NT) {
-        const int ly = q / S::RX, lx = q - ly * S::RX;
-        const int gx = x0 + lx - 2, gy = y0 + ly - 2;
-        T r, u, v;
-        if (interior) {
-            const size_t s = (size_t)gy * c.nx + gx;
-            r = in.r[s];
-            u = in.u[s];
-            v = in.v[s];
-        } else {
-            int fx, fy;
-            const int sx = map_coord(gx, c.nx, c.bc[0], 0, fx);
-            const int sy = map_coord(gy, c.ny, c.bc[2], 2, fy);
+    constexpr int NIT = (S::RXY + NT - 1) / NT;
+    T r[NIT], u[NIT], v[NIT];
+    if (interior) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = min((int)threadIdx.x + it * NT, S::RXY - 1);
+            const int ly = q / S::RX, lx = q - ly * S::RX;
+            const size_t s = (size_t)(y0 + ly - 2) * c.nx + (x0 + lx - 2);
+            r[it] = in.r[s];
+            u[it] = in.u[s];
+            v[it] = in.v[s];
+        }
+    } else {
+        int fxs[NIT], fys[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int q = min((int)threadIdx.x + it * NT, S::RXY - 1);
+            const int ly = q / S::RX, lx = q - ly * S::RX;
+            const int sx = map_coord(x0 + lx - 2, c.nx, c.bc[0], 0, fxs[it]);
+            const int sy = map_coord(y0 + ly - 2, c.ny, c.bc[2], 2, fys[it]);
             const size_t s = (size_t)sy * c.nx + sx;
-            r = in.r[s];
-            u = in.u[s];
-            v = in.v[s];
+            r[it] = in.r[s];
+            u[it] = in.u[s];
+            v[it] = in.v[s];
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int fx = fxs[it], fy = fys[it];
             if (fx >= 0) {
-                u = fmaT(c.fs[fx][0], u, c.fo[fx][0]);
-                v = fmaT(c.fs[fx][1], v, c.fo[fx][1]);
+                u[it] = fmaT(c.fs[fx][0], u[it], c.fo[fx][0]);
+                v[it] = fmaT(c.fs[fx][1], v[it], c.fo[fx][1]);
             }
             if (fy >= 0) {
-                u = fmaT(c.fs[fy][0], u, c.fo[fy][0]);
-                v = fmaT(c.fs[fy][1], v, c.fo[fy][1]);
+                u[it] = fmaT(c.fs[fy][0], u[it], c.fo[fy][0]);
+                v[it] = fmaT(c.fs[fy][1], v[it], c.fo[fy][1]);
             }
         }
-        sr[q] = r;
-        su[q] = u;
-        sv[q] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int q = threadIdx.x + it * NT;
+        if (q < S::RXY) {
+            sr[q] = r[it];
+            su[q] = u[it];
+            sv[q] = v[it];
+        }
     }
 }
 
