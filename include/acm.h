@@ -285,10 +285,23 @@ acm_status acm_filter_box(int32_t nxf, int32_t nyf, int32_t factor, int32_t prec
 acm_status acm_prolong_bilinear(int32_t nxc, int32_t nyc, int32_t factor, int32_t precision,
                                 const acm_fields* coarse, const acm_fields* fine, void* stream);
 
-/* Closure inference: every coarse step runs the SMAME step then the network
- * correction, captured in HIP graphs of `chunk` steps (even; 0 = 100).
- * weights/biases: ACM_CNN_LAYERS device pointers (bf16 / fp32).  workspace:
- * acm_closure_workspace bytes of device memory for the activations. */
+/* Whole-network inference in one launch:
+ *   out[c] = in[c] + out_scale[c] * f(in_scale * in)[c],  c = drho, u, v,
+ * f the five layers above with the same bf16 rounding of every activation
+ * (only the order of the FP32 sums differs from acm_cnn_conv).  Each 16x16
+ * tile evaluates layer l on the tile grown by 4 - l nodes, entirely in LDS.
+ * weights/biases: ACM_CNN_LAYERS device pointers (bf16 [9][C_out][C_in] /
+ * fp32).  Needs nx, ny multiples of 16; in and out fields must be distinct
+ * (ACM_EINVAL otherwise). */
+acm_status acm_cnn_correct(int32_t nx, int32_t ny, const acm_fields* in, const acm_fields* out,
+                           const void* const* weights, const float* const* biases, const float* in_scale,
+                           const float* out_scale, void* stream);
+
+/* Closure inference: every coarse step runs the SMAME step into the
+ * workspace, then acm_cnn_correct into the other buffer set, captured in HIP
+ * graphs of `chunk` steps (even; 0 = 100).  weights/biases as for
+ * acm_cnn_correct.  workspace: acm_closure_workspace bytes of device memory
+ * (the uncorrected state).  Grids need nx, ny multiples of 16. */
 typedef struct acm_closure acm_closure;
 size_t acm_closure_workspace(int32_t nx, int32_t ny);
 acm_status acm_closure_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b, const void* force_x,

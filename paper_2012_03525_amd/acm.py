@@ -118,6 +118,10 @@ SIGNATURES = {
                                                              ctypes.c_void_p]),
     "acm_prolong_bilinear": (ctypes.c_int, [ctypes.c_int32] * 4 + [ctypes.POINTER(Fields), ctypes.POINTER(Fields),
                                                                    ctypes.c_void_p]),
+    "acm_cnn_correct": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Fields), ctypes.POINTER(Fields),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                       ctypes.c_void_p]),
     "acm_closure_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "acm_closure_init": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(Fields), ctypes.POINTER(Fields),
                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),

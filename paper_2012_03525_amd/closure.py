@@ -137,6 +137,14 @@ class Network:
             acm.check(L.acm_cnn_conv(self.nx, self.ny, ci, co, CONV_RAW if last else CONV_RELU, _vp(self.acts[l]),
                                      _vp(self.w16[l]), _vp(self.b32[l]), None, _vp(y), self.stream))
 
+    def correct(self, src: Dict[str, "object"], dst: Dict[str, "object"]):
+        """dst = src + D f(N src) in one fused launch (nx, ny multiples of 16)."""
+        ws16 = (ctypes.c_void_p * LAYERS)(*[self.w16[l].data_ptr() for l in range(LAYERS)])
+        bs = (ctypes.c_void_p * LAYERS)(*[self.b32[l].data_ptr() for l in range(LAYERS)])
+        fi, fo = _fields(src), _fields(dst)
+        acm.check(acm.lib().acm_cnn_correct(self.nx, self.ny, ctypes.byref(fi), ctypes.byref(fo), ws16, bs,
+                                            _f3(self.in_scale), _f3(self.out_scale), self.stream))
+
     def apply(self, drho, u, v):
         acm.check(acm.lib().acm_cnn_apply(self.nx, self.ny, _vp(self.raw), _f3(self.out_scale), _vp(drho), _vp(u),
                                           _vp(v), self.stream))

@@ -466,6 +466,250 @@ hipError_t conv_dispatch(int H, int W, int cin, int cout, int mode, const void* 
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Whole-network inference on one 16x16 output tile per workgroup:
+//   q_out = q_in + D f(N q_in).
+// Layer l (0..4) is evaluated on the tile grown by 4 - l nodes on every side,
+// so the five-node receptive field is covered without exchanging data between
+// workgroups (the ring is recomputed by the neighbours: 1.6x the tile's own
+// work).  Weights of every layer and two activation buffers live in LDS.
+// The MFMA roles are transposed with respect to conv3x3_kernel: A = weights
+// (16 output channels x 32 inputs), B = activations (32 inputs x 16 pixels),
+// so each lane's accumulator holds four consecutive output channels of one
+// pixel and is written back as one 8-byte LDS store.  v_mfma_f32_16x16x32_bf16
+// pairs element e of lane (i, g) in A with element e of lane (n, g) in B, so
+// loading A and B with the same k order gives the product for any layout of
+// k inside a lane.  The first layer is one im2col product with K = 27
+// (9 taps x 3 channels, zero-padded to 32) instead of nine K = 16 products.
+// ---------------------------------------------------------------------------
+namespace fused {
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int T = 16;                     // output tile side
+constexpr int NT = 256;                   // 4 waves
+constexpr int AS = 40;                    // activation pixel stride (halfwords): 32 channels + 8, 16-byte aligned
+constexpr int SI = T + 10;                // staged input side (26)
+constexpr int S0 = T + 8, S1 = T + 6;     // output sides of layers 0 and 1 (24, 22); then 20, 18, 16
+constexpr int W0 = 32 * 32;               // layer 0 as im2col: [o][k], k = 3 t + c
+constexpr int WL = 9 * 32 * 32;           // layers 1..3: [t][o][i]
+constexpr int W4 = 9 * 16 * 32;           // layer 4: [t][o][i]
+constexpr int OW1 = W0, OW2 = OW1 + WL, OW3 = OW2 + WL, OW4 = OW3 + WL, WTOT = OW4 + W4;
+constexpr int BA = S0 * S0 * AS;          // outputs of layers 0 and 2
+constexpr int BB = S1 * S1 * AS;          // outputs of layers 1 and 3; the staged input before them
+constexpr int LDS_HALF = WTOT + BA + BB;  // 151,360 bytes
+static_assert(SI * SI * 4 <= BB, "input fits in buffer B");
+static_assert(WTOT % 8 == 0 && BA % 8 == 0, "16-byte aligned buffers");
+
+struct Args {
+    const float* qi[3];  // state after the coarse step (read only)
+    float* qo[3];        // corrected state
+    float s[3], d[3];    // input and output channel scales
+    const bf16_t* w[ACM_CNN_LAYERS];
+    const float* b[ACM_CNN_LAYERS];
+};
+
+__device__ __forceinline__ bf16x8 lds8(const bf16_t* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d)
+{
+    return uint2{(unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16), (unsigned)f2bf(c) | ((unsigned)f2bf(d) << 16)};
+}
+
+// One 32-input-channel layer: output side SO (input side SO + 2), NH blocks
+// of 16 output channels.  RELU: bias + ReLU into `out`; otherwise the lanes
+// holding channels 0..3 of the last layer apply the correction.
+template <int SO, int NH, bool LAST>
+__device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const float* __restrict__ bias,
+                                        const bf16_t* __restrict__ in, bf16_t* __restrict__ out, const Args& a,
+                                        int gx0, int gy0, int H, int W)
+{
+    constexpr int SN = SO + 2, NP = SO * SO, NG = (NP + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lg = lane >> 4;
+    bf16x8 wa[9][NH];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nh = 0; nh < NH; ++nh) wa[t][nh] = lds8(wl + ((t * NH * 16 + nh * 16 + l16) * 32 + 8 * lg));
+    float bb[NH][4];
+#pragma unroll
+    for (int nh = 0; nh < NH; ++nh)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bb[nh][j] = bias[nh * 16 + 4 * lg + j];
+
+    auto finish = [&](int g, const f32x4* acc) {
+        const int p = 16 * g + l16;
+        if (p >= NP) return;
+        if constexpr (!LAST) {
+#pragma unroll
+            for (int nh = 0; nh < NH; ++nh)
+                *reinterpret_cast<uint2*>(out + p * AS + nh * 16 + 4 * lg) =
+                    pack4(fmaxf(acc[nh][0] + bb[nh][0], 0.f), fmaxf(acc[nh][1] + bb[nh][1], 0.f),
+                          fmaxf(acc[nh][2] + bb[nh][2], 0.f), fmaxf(acc[nh][3] + bb[nh][3], 0.f));
+        } else {
+            if (lg == 0) {
+                const int py = p / SO, px = p - py * SO;
+                const size_t o = (size_t)(gy0 + py) * W + (gx0 + px);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a.qo[c][o] = fmaf(a.d[c], acc[0][c] + bb[0][c], a.qi[c][o]);
+            }
+        }
+    };
+    auto base_of = [&](int g) {
+        const int p = min(16 * g + l16, NP - 1);
+        const int py = p / SO, px = p - py * SO;
+        return ((py + 1) * SN + (px + 1)) * AS + 8 * lg;
+    };
+    // groups wave, wave + 4, ...: two at a time so consecutive MFMAs are independent
+    int g = wave;
+    for (; g + 4 < NG; g += 8) {
+        const int b0 = base_of(g), b1 = base_of(g + 4);
+        f32x4 a0[NH], a1[NH];
+#pragma unroll
+        for (int nh = 0; nh < NH; ++nh) a0[nh] = a1[nh] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int off = ((t / 3 - 1) * SN + (t % 3 - 1)) * AS;
+            const bf16x8 x0 = lds8(in + b0 + off), x1 = lds8(in + b1 + off);
+#pragma unroll
+            for (int nh = 0; nh < NH; ++nh) {
+                a0[nh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nh], x0, a0[nh], 0, 0, 0);
+                a1[nh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nh], x1, a1[nh], 0, 0, 0);
+            }
+        }
+        finish(g, a0);
+        finish(g + 4, a1);
+    }
+    if (g < NG) {
+        const int b0 = base_of(g);
+        f32x4 a0[NH];
+#pragma unroll
+        for (int nh = 0; nh < NH; ++nh) a0[nh] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int off = ((t / 3 - 1) * SN + (t % 3 - 1)) * AS;
+            const bf16x8 x0 = lds8(in + b0 + off);
+#pragma unroll
+            for (int nh = 0; nh < NH; ++nh)
+                a0[nh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nh], x0, a0[nh], 0, 0, 0);
+        }
+        finish(g, a0);
+    }
+}
+
+__global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a)
+{
+    __shared__ __align__(16) bf16_t lds[LDS_HALF];
+    bf16_t* const sw = lds;
+    bf16_t* const sa = lds + WTOT;
+    bf16_t* const sb = sa + BA;
+    const int tiles_x = W / T;
+    const int gx0 = (blockIdx.x % tiles_x) * T, gy0 = (blockIdx.x / tiles_x) * T;
+    const int tid = threadIdx.x;
+
+    // ---- staging: weights of layers 1..4 (straight copies), the layer-0
+    // im2col weights and the normalised input region; all loads are issued
+    // before the first LDS store.
+    constexpr int NV = WL / 8, NV4 = W4 / 8;  // uint4 per layer
+    constexpr int IW = (NV + NT - 1) / NT, IW4 = (NV4 + NT - 1) / NT;
+    uint4 wv[3][IW], wv4[IW4];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int i = 0; i < IW; ++i)
+            wv[l][i] = reinterpret_cast<const uint4*>(a.w[l + 1])[min(tid + i * NT, NV - 1)];
+#pragma unroll
+    for (int i = 0; i < IW4; ++i) wv4[i] = reinterpret_cast<const uint4*>(a.w[4])[min(tid + i * NT, NV4 - 1)];
+    constexpr int I0 = W0 / NT;  // 4 layer-0 entries per thread
+    bf16_t w0v[I0];
+#pragma unroll
+    for (int i = 0; i < I0; ++i) {
+        const int e = tid + i * NT, o = e / 32, k = e % 32;
+        w0v[i] = k < 27 ? a.w[0][((k / 3) * 32 + o) * 16 + (k % 3)] : bf16_t(0);
+    }
+    constexpr int NI = SI * SI, II = (NI + NT - 1) / NT;
+    float q0[II], q1[II], q2[II];
+#pragma unroll
+    for (int i = 0; i < II; ++i) {
+        const int e = min(tid + i * NT, NI - 1);
+        const int r = e / SI, c = e - r * SI;
+        const size_t src = (size_t)wrap(gy0 - 5 + r, H) * W + wrap(gx0 - 5 + c, W);
+        q0[i] = a.qi[0][src];
+        q1[i] = a.qi[1][src];
+        q2[i] = a.qi[2][src];
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int i = 0; i < IW; ++i)
+            if (tid + i * NT < NV) reinterpret_cast<uint4*>(sw + OW1 + l * WL)[tid + i * NT] = wv[l][i];
+#pragma unroll
+    for (int i = 0; i < IW4; ++i)
+        if (tid + i * NT < NV4) reinterpret_cast<uint4*>(sw + OW4)[tid + i * NT] = wv4[i];
+#pragma unroll
+    for (int i = 0; i < I0; ++i) sw[tid + i * NT] = w0v[i];
+#pragma unroll
+    for (int i = 0; i < II; ++i) {
+        const int e = tid + i * NT;
+        if (e < NI)
+            *reinterpret_cast<uint2*>(sb + 4 * e) = pack4(q0[i] * a.s[0], q1[i] * a.s[1], q2[i] * a.s[2], 0.f);
+    }
+    __syncthreads();
+
+    // ---- layer 0 (im2col, K = 27): staged input (side 26, 4 halfwords per
+    // node) -> buffer A (side 24)
+    {
+        constexpr int NP = S0 * S0, NG = NP / 16;
+        const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lg = lane >> 4;
+        // offsets of the lane's eight k = 8 lg + j taps/channels (k >= 27 is padding)
+        int koff[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = min(8 * lg + j, 26), t = k / 3, c = k - 3 * t;
+            koff[j] = ((t / 3 - 1) * SI + (t % 3 - 1)) * 4 + c;
+        }
+        const bf16x8 wa0 = lds8(sw + l16 * 32 + 8 * lg), wa1 = lds8(sw + (16 + l16) * 32 + 8 * lg);
+        float bb[2][4];
+#pragma unroll
+        for (int nh = 0; nh < 2; ++nh)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bb[nh][j] = a.b[0][nh * 16 + 4 * lg + j];
+        for (int g = wave; g < NG; g += 4) {
+            const int p = 16 * g + l16, py = p / S0, px = p - py * S0;
+            const int base = ((py + 1) * SI + (px + 1)) * 4;
+            bf16x8 x;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                x[j] = 8 * lg + j < 27 ? __builtin_bit_cast(__bf16, sb[base + koff[j]]) : __bf16(0.f);
+            f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, x, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, x, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            *reinterpret_cast<uint2*>(sa + p * AS + 4 * lg) =
+                pack4(fmaxf(c0[0] + bb[0][0], 0.f), fmaxf(c0[1] + bb[0][1], 0.f), fmaxf(c0[2] + bb[0][2], 0.f),
+                      fmaxf(c0[3] + bb[0][3], 0.f));
+            *reinterpret_cast<uint2*>(sa + p * AS + 16 + 4 * lg) =
+                pack4(fmaxf(c1[0] + bb[1][0], 0.f), fmaxf(c1[1] + bb[1][1], 0.f), fmaxf(c1[2] + bb[1][2], 0.f),
+                      fmaxf(c1[3] + bb[1][3], 0.f));
+        }
+    }
+    __syncthreads();
+    layer32<S1, 2, false>(sw + OW1, a.b[1], sa, sb, a, gx0, gy0, H, W);
+    __syncthreads();
+    layer32<S1 - 2, 2, false>(sw + OW2, a.b[2], sb, sa, a, gx0, gy0, H, W);
+    __syncthreads();
+    layer32<S1 - 4, 2, false>(sw + OW3, a.b[3], sa, sb, a, gx0, gy0, H, W);
+    __syncthreads();
+    // last layer: output side 16 = the tile; (gx0, gy0) is its origin
+    layer32<T, 1, true>(sw + OW4, a.b[4], sb, nullptr, a, gx0, gy0, H, W);
+}
+}  // namespace fused
+
+hipError_t launch_fused(int H, int W, const fused::Args& a, hipStream_t s)
+{
+    if (H % fused::T || W % fused::T) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fused::cnn_fused_kernel, dim3((W / fused::T) * (H / fused::T)), dim3(fused::NT), 0, s, H, W,
+                       a);
+    return hipGetLastError();
+}
+
 }  // namespace acm
 
 using namespace acm;
@@ -667,8 +911,7 @@ struct acm_closure {
     const void* w[ACM_CNN_LAYERS];
     const float* b[ACM_CNN_LAYERS];
     float in_scale[3], out_scale[3];
-    bf16_t* act[ACM_CNN_LAYERS];  // layer inputs a0..a4 in the workspace
-    float* raw = nullptr;
+    float* tmp[3] = {nullptr, nullptr, nullptr};  // uncorrected state after the coarse step (workspace)
     hipStream_t stream = nullptr, cap = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     int chunk = 100;
@@ -680,6 +923,25 @@ struct acm_closure {
 
 namespace {
 
+fused::Args fused_args(const acm_closure* h, const float* const* qi, float* const* qo)
+{
+    fused::Args a;
+    for (int c = 0; c < 3; ++c) {
+        a.qi[c] = qi[c];
+        a.qo[c] = qo[c];
+        a.s[c] = h->in_scale[c];
+        a.d[c] = h->out_scale[c];
+    }
+    for (int l = 0; l < ACM_CNN_LAYERS; ++l) {
+        a.w[l] = static_cast<const bf16_t*>(h->w[l]);
+        a.b[l] = h->b[l];
+    }
+    return a;
+}
+
+// one coarse step: SMAME step into the scratch state, then the network
+// correction into the other buffer set (plain step straight into it when
+// the network is off)
 hipError_t closure_step(acm_closure* h, int from, hipStream_t s)
 {
     const acm_fields& in = h->set[from];
@@ -688,26 +950,12 @@ hipError_t closure_step(acm_closure* h, int from, hipStream_t s)
                           nullptr};
     const State<float> so{static_cast<float*>(out.drho), static_cast<float*>(out.u), static_cast<float*>(out.v),
                           nullptr, nullptr};
-    hipError_t e = launch_step2d<float>(h->coef, si, so, h->cfg.tile, s);
-    if (e != hipSuccess || !h->use_net) return e;
-    const int nx = h->cfg.nx, ny = h->cfg.ny, n = nx * ny;
-    (void)n;
-    // first layer reads the new state directly (normalised while staged)
-    StateIn sin{{so.r, so.u, so.v}, {h->in_scale[0], h->in_scale[1], h->in_scale[2]}};
-    e = launch_conv<16, 32, CONV_RELU, true>(ny, nx, nullptr, static_cast<const bf16_t*>(h->w[0]), h->b[0], nullptr,
-                                             h->act[1], s, ApplyArgs{}, sin);
+    if (!h->use_net) return launch_step2d<float>(h->coef, si, so, h->cfg.tile, s);
+    const State<float> st{h->tmp[0], h->tmp[1], h->tmp[2], nullptr, nullptr};
+    hipError_t e = launch_step2d<float>(h->coef, si, st, h->cfg.tile, s);
     if (e != hipSuccess) return e;
-    int ci, co;
-    for (int l = 1; l + 1 < ACM_CNN_LAYERS; ++l) {
-        acm_cnn_layer_shape(l, &ci, &co);
-        e = conv_dispatch(ny, nx, ci, co, CONV_RELU, h->act[l], h->w[l], h->b[l], nullptr, h->act[l + 1], s);
-        if (e != hipSuccess) return e;
-    }
-    // last layer: the correction is added to the new state in the epilogue
-    ApplyArgs ap{{so.r, so.u, so.v}, {h->out_scale[0], h->out_scale[1], h->out_scale[2]}};
-    const int L = ACM_CNN_LAYERS - 1;
-    return launch_conv<32, 16, CONV_APPLY>(ny, nx, h->act[L], static_cast<const bf16_t*>(h->w[L]), h->b[L], nullptr,
-                                           nullptr, s, ap);
+    float* const qo[3] = {so.r, so.u, so.v};
+    return launch_fused(h->cfg.ny, h->cfg.nx, fused_args(h, h->tmp, qo), s);
 }
 
 }  // namespace
@@ -716,8 +964,35 @@ extern "C" {
 
 size_t acm_closure_workspace(int32_t nx, int32_t ny)
 {
-    const size_t n = (size_t)nx * ny;
-    return n * 16 * 2 + 4 * n * 32 * 2 + n * 16 * 4;  // a0 (16 ch) + a1..a4 (32 ch) bf16 + raw fp32 (16 ch)
+    if (nx <= 0 || ny <= 0) return 0;
+    return (size_t)nx * ny * 3 * sizeof(float);  // the uncorrected state (drho, u, v)
+}
+
+acm_status acm_cnn_correct(int32_t nx, int32_t ny, const acm_fields* in, const acm_fields* out,
+                           const void* const* weights, const float* const* biases, const float* in_scale,
+                           const float* out_scale, void* stream)
+{
+    if (nx < fused::T || ny < fused::T || nx % fused::T || ny % fused::T)
+        return cfail(ACM_EINVAL, "fused inference needs nx and ny multiples of 16");
+    if (!in || !out || !weights || !biases || !in_scale || !out_scale) return cfail(ACM_EINVAL, "NULL pointer");
+    fused::Args a;
+    const void* const qi[3] = {in->drho, in->u, in->v};
+    void* const qo[3] = {out->drho, out->u, out->v};
+    for (int c = 0; c < 3; ++c) {
+        if (!qi[c] || !qo[c]) return cfail(ACM_EINVAL, "NULL field");
+        for (int k = 0; k < 3; ++k)
+            if (qi[c] == qo[k]) return cfail(ACM_EINVAL, "in and out fields must be distinct");
+        a.qi[c] = static_cast<const float*>(qi[c]);
+        a.qo[c] = static_cast<float*>(qo[c]);
+        a.s[c] = in_scale[c];
+        a.d[c] = out_scale[c];
+    }
+    for (int l = 0; l < ACM_CNN_LAYERS; ++l) {
+        if (!weights[l] || !biases[l]) return cfail(ACM_EINVAL, "NULL layer parameters");
+        a.w[l] = static_cast<const bf16_t*>(weights[l]);
+        a.b[l] = biases[l];
+    }
+    return chip(launch_fused(ny, nx, a, static_cast<hipStream_t>(stream)), "fused inference launch");
 }
 
 acm_status acm_closure_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b, const void* force_x,
@@ -730,7 +1005,8 @@ acm_status acm_closure_init(const acm_config* cfg, const acm_fields* a, const ac
     if (api_validate(cfg, err) != ACM_OK) return cfail(ACM_EINVAL, err);
     if (cfg->dim != 2 || cfg->two_phase || cfg->precision != ACM_F32)
         return cfail(ACM_EINVAL, "the closure runs 2D single-phase FP32 coarse grids");
-    if (!grid_ok(cfg->nx, cfg->ny)) return cfail(ACM_EINVAL, "closure grids need nx % 64 == 0 and ny % 8 == 0");
+    if (cfg->nx < fused::T || cfg->ny < fused::T || cfg->nx % fused::T || cfg->ny % fused::T)
+        return cfail(ACM_EINVAL, "closure grids need nx and ny multiples of 16");
     if (!a || !b || !a->drho || !a->u || !a->v || !b->drho || !b->u || !b->v || !weights || !biases || !in_scale ||
         !out_scale || !workspace)
         return cfail(ACM_EINVAL, "NULL pointer");
@@ -756,14 +1032,7 @@ acm_status acm_closure_init(const acm_config* cfg, const acm_fields* a, const ac
         h->out_scale[c] = out_scale[c];
     }
     const size_t n = (size_t)cfg->nx * cfg->ny;
-    char* ws = static_cast<char*>(workspace);
-    h->act[0] = reinterpret_cast<bf16_t*>(ws);
-    ws += n * 16 * 2;
-    for (int l = 1; l < ACM_CNN_LAYERS; ++l) {
-        h->act[l] = reinterpret_cast<bf16_t*>(ws);
-        ws += n * 32 * 2;
-    }
-    h->raw = reinterpret_cast<float*>(ws);
+    for (int c = 0; c < 3; ++c) h->tmp[c] = static_cast<float*>(workspace) + c * n;
     h->chunk = chunk > 0 ? chunk : 100;
     h->stream = static_cast<hipStream_t>(stream);
     h->coef = api_make_coef<float>(*cfg, force_x);

@@ -156,3 +156,22 @@ def test_batch_init_rejects_bad_cases_without_touching_the_gpu():
     bad = acm.BatchOpts(21, 0, 0, 0.0)
     arr[1].tile = 0
     assert acm.lib().acm_batch_init(arr, n, ctypes.byref(bad), None, ctypes.byref(h)) == acm.EINVAL
+
+
+def test_fused_correction_rejects_bad_arguments_without_touching_the_gpu():
+    """acm_cnn_correct validates before any launch: tile-incompatible grids,
+    NULL parameters and in/out fields that alias are ACM_EINVAL."""
+    L = acm.lib()
+    P = ctypes.c_void_p * 5
+    w = P(*([16] * 5))
+    b = P(*([32] * 5))
+    sc = (ctypes.c_float * 3)(1.0, 1.0, 1.0)
+    fi = acm.Fields(1 << 20, 2 << 20, 3 << 20, 0, 0)
+    fo = acm.Fields(4 << 20, 5 << 20, 6 << 20, 0, 0)
+    assert L.acm_cnn_correct(24, 32, ctypes.byref(fi), ctypes.byref(fo), w, b, sc, sc, None) == acm.EINVAL
+    assert L.acm_cnn_correct(32, 8, ctypes.byref(fi), ctypes.byref(fo), w, b, sc, sc, None) == acm.EINVAL
+    alias = acm.Fields(4 << 20, 2 << 20, 3 << 20, 0, 0)
+    assert L.acm_cnn_correct(32, 32, ctypes.byref(alias), ctypes.byref(fo), w, b, sc, sc, None) == acm.EINVAL
+    w_null = P(16, 16, None, 16, 16)
+    assert L.acm_cnn_correct(32, 32, ctypes.byref(fi), ctypes.byref(fo), w_null, b, sc, sc, None) == acm.EINVAL
+    assert L.acm_cnn_correct(32, 32, None, ctypes.byref(fo), w, b, sc, sc, None) == acm.EINVAL

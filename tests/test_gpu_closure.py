@@ -95,6 +95,55 @@ def test_network_forward_and_gradients_match_reference(mods):
         assert rel(gb, grads[l][1]) < 5e-2
 
 
+@pytest.mark.parametrize("nx,ny", [(80, 48), (256, 256)])
+def test_fused_correction_matches_reference(mods, nx, ny):
+    """One-launch inference q + D f(N q) on several 16x16 tiles (periodic
+    wrap across the grid edges): the correction within 2e-2 relative L2 of
+    the FP64 reference with the same bf16 weights and bf16-rounded input."""
+    torch, acm, closure, cnn = mods
+    rng = np.random.Generator(np.random.PCG64(11))
+    params = closure.he_init(5, last_scale=1.0)
+    params = [[bf16_round(torch, w), (b + 0.01 * rng.standard_normal(b.shape)).astype(np.float32).astype(np.float64)]
+              for w, b in params]
+    s_in, d_out = [2.0, 0.5, 1.5], [1e-3, 2e-3, 3e-3]
+    net = closure.Network(64, 64, params=params, in_scale=s_in, out_scale=d_out)
+    net.nx, net.ny = nx, ny
+    dev = "cuda:0"
+    q = {k: rng.standard_normal((ny, nx)).astype(np.float32) for k in ("drho", "u", "v")}
+    qt = {k: torch.from_numpy(v).to(dev) for k, v in q.items()}
+    out = {k: torch.full((ny, nx), float("nan"), dtype=torch.float32, device=dev) for k in q}
+    net.correct(qt, out)
+    torch.cuda.synchronize()
+    x0 = np.stack([q["drho"] * np.float32(s_in[0]), q["u"] * np.float32(s_in[1]), q["v"] * np.float32(s_in[2])],
+                  axis=-1).astype(np.float64)
+    raw, _ = cnn.forward(params, bf16_round(torch, x0))
+    for c, k in enumerate(("drho", "u", "v")):
+        corr = (out[k].double().cpu().numpy() - q[k].astype(np.float64)) / d_out[c]
+        assert np.all(np.isfinite(corr)), k
+        assert rel(corr, raw[:, :, c]) < 2e-2, (k, rel(corr, raw[:, :, c]))
+
+
+def test_fused_correction_matches_layered_path(mods):
+    """The fused kernel and the per-layer kernels (acm_cnn_conv chain, then
+    acm_cnn_apply) agree to bf16 accuracy on the same weights and state."""
+    torch, acm, closure, cnn = mods
+    nx, ny = 128, 64
+    rng = np.random.Generator(np.random.PCG64(12))
+    net = closure.Network(nx, ny, seed=6, in_scale=[1.0, 2.0, 2.0], out_scale=[1e-2, 1e-2, 1e-2])
+    dev = "cuda:0"
+    q = {k: torch.from_numpy(rng.standard_normal((ny, nx)).astype(np.float32)).to(dev) for k in ("drho", "u", "v")}
+    out = {k: torch.empty_like(v) for k, v in q.items()}
+    net.correct(q, out)
+    lay = {k: v.clone() for k, v in q.items()}
+    net.forward(lay["drho"], lay["u"], lay["v"])
+    net.apply(lay["drho"], lay["u"], lay["v"])
+    torch.cuda.synchronize()
+    for k in q:
+        a = (out[k] - q[k]).double().cpu().numpy()
+        b = (lay[k] - q[k]).double().cpu().numpy()
+        assert rel(a, b) < 1e-2, (k, rel(a, b))
+
+
 def test_adam_matches_reference(mods):
     torch, acm, closure, cnn = mods
     rng = np.random.Generator(np.random.PCG64(11))
@@ -166,8 +215,8 @@ def test_training_overfits_one_pair(mods):
 
 def test_closure_handle_equals_manual_sequence(mods):
     """The closure handle (graph-captured) is bitwise equal to acm steps
-    followed by the network correction issued call by call, and with the
-    network switched off to plain acm_run."""
+    followed by the fused network correction issued call by call, and with
+    the network switched off to plain acm_run."""
     torch, acm, closure, cnn = mods
     from paper_2012_03525_amd import inputs
     spec = closure.FlowSpec(n_fine=256, nu_fine=0.02)
@@ -181,11 +230,13 @@ def test_closure_handle_equals_manual_sequence(mods):
     run.close()
     s = acm.Solver(spec.coarse_config(), {k: v.astype(np.float32).astype(np.float64) for k, v in st.items()},
                    force_x=spec.coarse_force())
+    tmp = {k: torch.empty((64, 64), dtype=torch.float32, device=dev) for k in ("drho", "u", "v")}
     for _ in range(4):
         s.step()
         q = s.tensors()
-        net.forward(q["drho"], q["u"], q["v"])
-        net.apply(q["drho"], q["u"], q["v"])
+        net.correct(q, tmp)
+        for k in q:
+            q[k].copy_(tmp[k])
     torch.cuda.synchronize()
     for k in got:
         assert torch.equal(got[k], s.tensors()[k]), k
