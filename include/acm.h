@@ -262,8 +262,11 @@ acm_status acm_cnn_apply(int32_t nx, int32_t ny, const float* raw, const float* 
                          float* u, float* v, void* stream);
 
 /* Mean squared error of raw (fp32, 16 channels) against the target
- * residual (target[c] - base[c]) / out_scale[c] over pixels and 3 channels;
- * grad (bf16, 16 channels) = d loss / d raw; *loss (device double) is set. */
+ * residual (target[c] - base[c]) / out_scale[c] over pixels and the active
+ * channels; grad (bf16, 16 channels) = d loss / d raw; *loss (device double)
+ * is set.  A channel with out_scale[c] == 0 is excluded (zero error and
+ * gradient; the closure then leaves that field uncorrected).  ACM_EINVAL for
+ * a negative or non-finite scale or when all three are zero. */
 size_t acm_cnn_loss_workspace(int32_t nx, int32_t ny);
 acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* const* base,
                         const float* const* target, const float* out_scale, void* grad, double* workspace,
@@ -288,7 +291,8 @@ acm_status acm_prolong_bilinear(int32_t nxc, int32_t nyc, int32_t factor, int32_
 /* Whole-network inference in one launch:
  *   out[c] = in[c] + out_scale[c] * f(in_scale * in)[c],  c = drho, u, v,
  * f the five layers above with the same bf16 rounding of every activation
- * (only the order of the FP32 sums differs from acm_cnn_conv).  Each 16x16
+ * (only the order of the FP32 sums differs from acm_cnn_conv); a channel
+ * with out_scale[c] == 0 is copied unchanged.  Each 16x16
  * tile evaluates layer l on the tile grown by 4 - l nodes, entirely in LDS.
  * weights/biases: ACM_CNN_LAYERS device pointers (bf16 [9][C_out][C_in] /
  * fp32).  Needs nx, ny multiples of 16; in and out fields must be distinct

@@ -141,6 +141,10 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2012_03525_amd.build`")
+        # torch first: its HIP runtime then satisfies the library's libamdhip64
+        # dependency, so the process holds one runtime and torch's device
+        # pointers and streams are valid in the library's calls
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -283,8 +283,12 @@ def generate_pairs(spec: FlowSpec, seeds: Sequence[int], warmup: int, pairs_per_
     return out
 
 
-def channel_scales(pairs, eps: float = 1e-12):
-    """N = 1 / rms of each base channel; D = rms of each target residual."""
+def channel_scales(pairs, correct_density: bool = False, eps: float = 1e-12):
+    """N = 1 / rms of each base channel; D = rms of each target residual.
+    Unless correct_density, D = 0 for drho: the density is left to the
+    scheme (a learned density correction feeds the acoustic mode, whose
+    divergence then grows until the gate trips) and the channel is left out
+    of the loss."""
     n_in = np.zeros(3)
     n_out = np.zeros(3)
     for base, tgt in pairs:
@@ -292,8 +296,10 @@ def channel_scales(pairs, eps: float = 1e-12):
             n_in[c] += float((base[k].double() ** 2).mean())
             n_out[c] += float(((tgt[k] - base[k]).double() ** 2).mean())
     n_in = np.sqrt(n_in / len(pairs))
-    n_out = np.sqrt(n_out / len(pairs))
-    return (1.0 / np.maximum(n_in, eps)).tolist(), np.maximum(n_out, eps).tolist()
+    n_out = np.maximum(np.sqrt(n_out / len(pairs)), eps)
+    if not correct_density:
+        n_out[0] = 0.0
+    return (1.0 / np.maximum(n_in, eps)).tolist(), n_out.tolist()
 
 
 def train(net: Network, pairs, epochs: int, lr: float, seed: int = 0, lr_decay: float = 1.0, log=None):
@@ -318,6 +324,7 @@ class GateResult:
     tripped: bool
     at_step: int
     reason: str
+    history: Optional[List[Tuple[int, float, float]]] = None  # (coarse step, E_k, divergence ratio) per gate
 
 
 class ClosureRun:
@@ -397,7 +404,7 @@ def gated_run(spec: FlowSpec, net: Optional[Network], c0, coarse_steps: int, gat
     shape_c = (spec.n_coarse, spec.n_coarse)
     run = ClosureRun(spec, net, c0)
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    gate = GateResult(False, -1, "")
+    gate = GateResult(False, -1, "", [])
     states = []
     fine = None
     e_prev = None
@@ -418,9 +425,10 @@ def gated_run(spec: FlowSpec, net: Optional[Network], c0, coarse_steps: int, gat
             elif force_trip_at is not None and step_no >= force_trip_at:
                 reason = "forced"
             e_prev = d["ke"]
+            gate.history.append((step_no, float(d["ke"]), float(divergence_ratio(d))))
             cur = run.state()
             if reason:
-                gate = GateResult(True, step_no, reason)
+                gate.tripped, gate.at_step, gate.reason = True, step_no, reason
                 fine = acm.Solver(spec.fine_config(), None,
                                   tensors=[{k: torch.empty((spec.n_fine, spec.n_fine), dtype=torch.float32,
                                                            device=dev) for k in ("drho", "u", "v")}
@@ -471,12 +479,13 @@ def evaluate_seed(spec: FlowSpec, net: Network, seed: int, warmup: int, coarse_s
     torch.cuda.synchronize()
     t_fine = time.perf_counter() - t0
     timed.close()
-    plain_states, _, t_plain = gated_run(spec, None, c0, coarse_steps, gate_every, energy_tol=1e9, div_tol=1e9)
+    plain_states, gate_plain, t_plain = gated_run(spec, None, c0, coarse_steps, gate_every, energy_tol=1e9,
+                                                  div_tol=1e9)
     cnn_states, gate, t_closure = gated_run(spec, net, c0, coarse_steps, gate_every, energy_tol, div_tol,
                                             force_trip_at)
     err_plain = [rel_l2_velocity(a, b) for a, b in zip(plain_states, ref)]
     err_cnn = [rel_l2_velocity(a, b) for a, b in zip(cnn_states, ref)]
     return {"seed": seed, "err_cnn_end": err_cnn[-1], "err_cnn_max": max(err_cnn),
-            "err_plain_end": err_plain[-1], "err_plain_max": max(err_plain), "gate": gate.__dict__,
+            "err_plain_end": err_plain[-1], "err_plain_max": max(err_plain), "gate": gate.__dict__, "gate_plain": gate_plain.__dict__,
             "t_fine_s": t_fine, "t_closure_s": t_closure, "t_plain_coarse_s": t_plain,
             "err_cnn": err_cnn, "err_plain": err_plain}

@@ -1,0 +1,152 @@
+"""Train and evaluate the learned closure on the forced periodic flow.
+
+    python -m paper_2012_03525_amd.closure_experiment [--preset full|small] [--out report.json]
+
+Everything runs on the GPU through the library:
+  1. training pairs from seeded fine runs: one coarse step of the filtered
+     fine state (base) and the filtered fine state r fine steps later (target);
+  2. per-channel scales N, D from the pairs, then Adam on the one-step
+     residual with the library's forward and backward kernels;
+  3. held-out seeds: filtered fine reference, plain coarse run and gated
+     closure run from the same filtered state; relative L2 velocity error
+     against the reference at every gate, and the time-to-solution of the
+     closure (gates and any fallback included) against plain fine steps over
+     the same physical horizon.
+The report also carries the error of the plain coarse run, i.e. what the
+network gains over the method without it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+from dataclasses import asdict
+
+import numpy as np
+
+from . import acm, closure
+
+PRESETS = {
+    # fine 1024^2 / coarse 256^2, 10,000 coarse steps = 40,000 fine steps
+    "full": dict(spec=dict(n_fine=1024), train_seeds=(0, 200), eval_seeds=(1000, 1050), warmup=4000,
+                 pairs_per_seed=8, stride=2000, epochs=6, lr=1e-3, lr_decay=0.7, coarse_steps=10000),
+    # fine 256^2 / coarse 64^2 with the same spectrum: the coarse grid sees
+    # only four nodes per shortest initial wavelength
+    "small": dict(spec=dict(n_fine=256), train_seeds=(0, 24), eval_seeds=(1000, 1004), warmup=1000,
+                  pairs_per_seed=8, stride=500, epochs=12, lr=1e-3, lr_decay=0.8, coarse_steps=2000),
+}
+
+
+def run_experiment(preset: str = "full", log=print, train_seeds=None, eval_seeds=None, epochs=None):
+    import torch
+    p = dict(PRESETS[preset])
+    spec = closure.FlowSpec(**p["spec"])
+    tr = range(*(train_seeds or p["train_seeds"]))
+    ev = range(*(eval_seeds or p["eval_seeds"]))
+    t0 = time.perf_counter()
+    pairs = closure.generate_pairs(spec, tr, warmup=p["warmup"], pairs_per_seed=p["pairs_per_seed"],
+                                   stride=p["stride"])
+    t_gen = time.perf_counter() - t0
+    n_in, d_out = closure.channel_scales(pairs)
+    log(f"{len(pairs)} pairs from {len(tr)} seeds in {t_gen:.1f} s; N = {n_in}, D = {d_out}")
+    net = closure.Network(spec.n_coarse, spec.n_coarse, seed=0, in_scale=n_in, out_scale=d_out)
+    # the one-step loss of the untrained (near-zero) correction is the
+    # plain coarse step's residual in units of D
+    t0 = time.perf_counter()
+    losses = closure.train(net, pairs, epochs or p["epochs"], p["lr"], seed=0, lr_decay=p["lr_decay"], log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del pairs
+    results = []
+    for seed in ev:
+        r = closure.evaluate_seed(spec, net, seed, warmup=p["warmup"], coarse_steps=p["coarse_steps"])
+        log(f"seed {seed}: err plain end {r['err_plain_end']:.4f} max {r['err_plain_max']:.4f} | "
+            f"closure end {r['err_cnn_end']:.4f} max {r['err_cnn_max']:.4f} | gate {r['gate']['reason'] or 'ok'} | "
+            f"t_fine {r['t_fine_s'] * 1e3:.1f} ms t_closure {r['t_closure_s'] * 1e3:.1f} ms "
+            f"t_plain_coarse {r['t_plain_coarse_s'] * 1e3:.1f} ms")
+        for name in ("gate", "gate_plain"):
+            h = r[name]["history"]
+            log(f"   {name} (step, E_k, div ratio): {[(a, round(b, 2), round(c, 4)) for a, b, c in h[:3]]} ... "
+                f"{[(a, round(b, 2), round(c, 4)) for a, b, c in h[-2:]]}")
+        results.append(r)
+    def mean(k):
+        return float(np.mean([r[k] for r in results]))
+    summary = {
+        "preset": preset, "spec": asdict(spec), "train_seeds": [tr.start, tr.stop], "eval_seeds": [ev.start, ev.stop],
+        "coarse_steps": p["coarse_steps"], "fine_steps": p["coarse_steps"] * spec.ratio,
+        "t_generate_s": t_gen, "t_train_s": t_train, "epoch_loss": losses,
+        "mean_err_plain_end": mean("err_plain_end"), "mean_err_plain_max": mean("err_plain_max"),
+        "mean_err_closure_end": mean("err_cnn_end"), "mean_err_closure_max": mean("err_cnn_max"),
+        "max_err_closure_max": float(max(r["err_cnn_max"] for r in results)),
+        "gate_trips": sum(1 for r in results if r["gate"]["tripped"]),
+        "mean_t_fine_s": mean("t_fine_s"), "mean_t_closure_s": mean("t_closure_s"),
+        "mean_t_plain_coarse_s": mean("t_plain_coarse_s"),
+        "seeds_closure_within_2pct_and_faster": sum(
+            1 for r in results if r["err_cnn_max"] <= 0.02 and r["t_closure_s"] < r["t_fine_s"]),
+        "per_seed": [{k: v for k, v in r.items() if k not in ("err_cnn", "err_plain")} for r in results],
+    }
+    return summary, net
+
+
+def step_timing(preset: str = "full", steps: int = 2000, log=print):
+    """Per-step wall time of plain fine steps and of closure steps (SMAME
+    step + fused network correction, graph-launched) on the preset's grids;
+    the network weights do not change the cost, so they are untrained."""
+    import ctypes
+    import torch
+    spec = closure.FlowSpec(**PRESETS[preset]["spec"])
+    f = acm.Solver(spec.fine_config(), spec.initial_state(1), force_x=spec.fine_force())
+    f.run(200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.run(steps)
+    torch.cuda.synchronize()
+    t_fine = (time.perf_counter() - t0) / steps
+    shape = (spec.n_coarse, spec.n_coarse)
+    c0 = {k: torch.zeros(shape, dtype=torch.float32, device="cuda:0") for k in ("drho", "u", "v")}
+    closure.filter_to(f.tensors(), c0, spec, ctypes.c_void_p(f.stream.cuda_stream))
+    f.close()
+    out = {"fine_step_us": t_fine * 1e6, "fine_steps_per_coarse_step_us": spec.ratio * t_fine * 1e6}
+    for name, net in (("closure_step_us", closure.Network(*shape, seed=0, out_scale=[0.0, 1e-6, 1e-6])),
+                      ("plain_coarse_step_us", None)):
+        run = closure.ClosureRun(spec, net, c0)
+        run.run(200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.run(steps)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) / steps * 1e6
+        run.close()
+    log(json.dumps(out))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--preset", choices=sorted(PRESETS), default="full")
+    ap.add_argument("--out", default=None, help="write the JSON report here")
+    ap.add_argument("--timing", action="store_true", help="only time fine steps and closure steps")
+    args = ap.parse_args(argv)
+    acm.lib()
+
+    def log(msg):
+        print(msg, flush=True)
+
+    if args.timing:
+        step_timing(args.preset, log=log)
+        return 0
+
+    summary, _ = run_experiment(args.preset, log=log)
+    keys = ("mean_err_plain_end", "mean_err_plain_max", "mean_err_closure_end", "mean_err_closure_max",
+            "max_err_closure_max", "gate_trips", "mean_t_fine_s", "mean_t_closure_s", "mean_t_plain_coarse_s",
+            "seeds_closure_within_2pct_and_faster")
+    log(json.dumps({k: summary[k] for k in keys}))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(summary, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

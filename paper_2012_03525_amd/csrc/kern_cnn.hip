@@ -338,22 +338,30 @@ __global__ void apply_correction_kernel(int n, const float* __restrict__ raw, fl
 
 // loss: target residual t_c = (target_c - base_c) / d_c; e = raw_c - t_c;
 // grad[p][c] = bf16(2 e / (3 n)) (zero for padded channels); per-block sum of e^2
+// Channels with a zero output scale take no part in the loss: their error
+// and gradient are zero (w = 0) and nact counts the others.
+struct LossChannels {
+    float id[3];  // 1 / out_scale, or 0 for an excluded channel
+    float w[3];   // 1 or 0
+    int nact;
+};
+
 __global__ __launch_bounds__(256) void loss_grad_kernel(int n, const float* __restrict__ raw,
                                                         const float* __restrict__ b0, const float* __restrict__ b1,
                                                         const float* __restrict__ b2, const float* __restrict__ t0,
                                                         const float* __restrict__ t1, const float* __restrict__ t2,
-                                                        float id0, float id1, float id2, bf16_t* __restrict__ grad,
+                                                        LossChannels lc, bf16_t* __restrict__ grad,
                                                         double* __restrict__ partial)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
     double se = 0.0;
     if (p < n) {
         const float* o = raw + (size_t)p * 16;
-        const float e0 = o[0] - (t0[p] - b0[p]) * id0;
-        const float e1 = o[1] - (t1[p] - b1[p]) * id1;
-        const float e2 = o[2] - (t2[p] - b2[p]) * id2;
+        const float e0 = lc.w[0] * (o[0] - (t0[p] - b0[p]) * lc.id[0]);
+        const float e1 = lc.w[1] * (o[1] - (t1[p] - b1[p]) * lc.id[1]);
+        const float e2 = lc.w[2] * (o[2] - (t2[p] - b2[p]) * lc.id[2]);
         se = (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
-        const float k = 2.f / (3.f * (float)n);
+        const float k = 2.f / ((float)lc.nact * (float)n);
         bf16_t out[16];
         out[0] = f2bf(k * e0);
         out[1] = f2bf(k * e1);
@@ -373,12 +381,12 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(int n, const float* __re
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void loss_final_kernel(const double* __restrict__ partial, int nblk, int n, double* __restrict__ out)
+__global__ void loss_final_kernel(const double* __restrict__ partial, int nblk, double count, double* __restrict__ out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += partial[b];
-    out[0] = s / (3.0 * n);
+    out[0] = s / count;
 }
 
 // Adam (Kingma & Ba) with bias correction; p16 (optional) receives bf16(p)
@@ -550,7 +558,8 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
                 const int py = p / SO, px = p - py * SO;
                 const size_t o = (size_t)(gy0 + py) * W + (gx0 + px);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) a.qo[c][o] = fmaf(a.d[c], acc[0][c] + bb[0][c], a.qi[c][o]);
+                for (int c = 0; c < 3; ++c)
+                    a.qo[c][o] = a.d[c] != 0.f ? fmaf(a.d[c], acc[0][c] + bb[0][c], a.qi[c][o]) : a.qi[c][o];
             }
         }
     };
@@ -830,12 +839,19 @@ acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* c
     const int n = nx * ny;
     const int nb = blocks_for(n);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    LossChannels lc{};
+    for (int c = 0; c < 3; ++c) {
+        if (!(out_scale[c] >= 0.f) || !std::isfinite(out_scale[c])) return cfail(ACM_EINVAL, "out_scale must be >= 0");
+        lc.w[c] = out_scale[c] > 0.f ? 1.f : 0.f;
+        lc.id[c] = out_scale[c] > 0.f ? 1.f / out_scale[c] : 0.f;
+        lc.nact += out_scale[c] > 0.f;
+    }
+    if (lc.nact == 0) return cfail(ACM_EINVAL, "every output channel is excluded");
     hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, n, raw, base[0], base[1], base[2], target[0],
-                       target[1], target[2], 1.f / out_scale[0], 1.f / out_scale[1], 1.f / out_scale[2],
-                       static_cast<bf16_t*>(grad), workspace);
+                       target[1], target[2], lc, static_cast<bf16_t*>(grad), workspace);
     acm_status st = chip(hipGetLastError(), "loss launch");
     if (st != ACM_OK) return st;
-    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, workspace, nb, n, loss);
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, workspace, nb, (double)lc.nact * n, loss);
     return chip(hipGetLastError(), "loss final launch");
 }
 

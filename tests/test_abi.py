@@ -175,3 +175,14 @@ def test_fused_correction_rejects_bad_arguments_without_touching_the_gpu():
     w_null = P(16, 16, None, 16, 16)
     assert L.acm_cnn_correct(32, 32, ctypes.byref(fi), ctypes.byref(fo), w_null, b, sc, sc, None) == acm.EINVAL
     assert L.acm_cnn_correct(32, 32, None, ctypes.byref(fo), w, b, sc, sc, None) == acm.EINVAL
+
+
+def test_loss_rejects_bad_output_scales_without_touching_the_gpu():
+    """acm_cnn_loss: a negative or non-finite scale, or all three channels
+    excluded (zero scale), is ACM_EINVAL before any launch."""
+    L = acm.lib()
+    P3 = ctypes.c_void_p * 3
+    base, tgt = P3(1 << 20, 2 << 20, 3 << 20), P3(4 << 20, 5 << 20, 6 << 20)
+    for sc in ((0.0, 0.0, 0.0), (1.0, -1.0, 1.0), (1.0, float("nan"), 1.0), (float("inf"), 1.0, 1.0)):
+        s = (ctypes.c_float * 3)(*sc)
+        assert L.acm_cnn_loss(64, 64, 7 << 20, base, tgt, s, 8 << 20, 9 << 20, 10 << 20, None) == acm.EINVAL, sc
