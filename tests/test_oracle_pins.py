@@ -11,6 +11,7 @@ import pytest
 
 from paper_2012_03525_amd import inputs
 
+import golden
 from analytic import capillary_wave_height, crossing_height, first_maximum_time
 
 CS2 = 1.0 / 3.0
@@ -311,10 +312,11 @@ def _tgv_run(orc, NL, c, Re, t_end, sat_rho=1.0, sat_mom=1.0, samples=4):
 def test_tgv_error_magnitude(orc):
     """Sec. 3.1: with N_L = 50, c = 20, Re = 20 the error Er_u (Eq. 3.2) stays
     around 1e-3 for t < 1, and E_k follows exp(-4 pi^2 t / Re)."""
-    res = _tgv_run(orc, 50, 20, 20, 1.0, samples=2)
+    NL, c, Re, order = golden.table("sec3_1_tgv_settings.txt")[0]
+    res = _tgv_run(orc, int(NL), c, Re, 1.0, samples=2)
     for t, er, ek in res:
-        assert 1e-4 < er < 3e-3, (t, er)
-        assert ek == pytest.approx(math.exp(-4 * math.pi ** 2 * t / 20), rel=2e-3)
+        assert 0.1 * order < er < 3 * order, (t, er)
+        assert ek == pytest.approx(math.exp(-4 * math.pi ** 2 * t / Re), rel=2e-3)
 
 
 def test_sat_ablation_matches_paper(orc):
@@ -413,7 +415,9 @@ def test_capillary_wave_analytic_table2():
     """Eq. 3.5 evaluated here reproduces Table 2's analytic periods 20.071
     (Re = 1000) and 38.751 (Re = 4000) within 0.2 % (period = time of the first
     maximum of h~; the paper does not define it)."""
-    for Re, T in ((1000, 20.071), (4000, 38.751)):
+    rows = golden.table("table2_capillary_wave_periods.txt")
+    assert rows.shape[0] == 2
+    for Re, T in rows[:, :2]:
         nu = 1.0 / Re
         t = np.linspace(0, 1.3 * T, 20001)
         h = capillary_wave_height(t, nu, nu, 2 * math.pi)
@@ -439,7 +443,9 @@ def test_capillary_wave_period(orc):
         ts.append((b + 1) * every / steps_per_t)
         hs.append((0.5 - crossing_height(st["phi"][:, 0], y)) / 0.01)
     T = first_maximum_time(np.array(ts), np.array(hs))
-    assert T == pytest.approx(20.669, rel=5e-3), T
+    row = golden.table("table2_capillary_wave_periods.txt")[0]
+    assert row[0] == 1000
+    assert T == pytest.approx(row[2], rel=5e-3), T
     assert hs[0] == pytest.approx(1.0, abs=0.05)
 
 
