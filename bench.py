@@ -30,7 +30,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="tgv3d_256",
-                    choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024"])
+                    choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024", "batch512"])
+    ap.add_argument("--no-closure", action="store_true",
+                    help="skip the closure step timing in the default workload's line")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -114,6 +116,63 @@ def measured_traffic(name):
     return int(1024 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]))
 
 
+def run_batch(a, copy):
+    """The 512-case sweep in one batched persistent launch (FP32, autotuned
+    tiles, 500-step graph chunks): aggregate MLUPS over the whole job and the
+    p50 / p99 case completion times."""
+    import numpy as np
+    from paper_2012_03525_amd import acm, inputs
+    cases = inputs.batch_cases(512, seed=4)
+    cfgs, states = [], []
+    for c in cases:
+        wu = [[0.0] * 3 for _ in range(6)]
+        bc = (0, 0, 0, 0, 0, 0)
+        if c.kind == "cavity":
+            bc = (1, 1, 1, 1, 0, 0)
+            wu[3] = [c.u_ref, 0.0, 0.0]
+        cfgs.append(acm.make_config(2, c.n, c.n, nu=c.nu, precision="f32", bc=bc, wall_u=wu))
+        states.append(c.state)
+    print(f"[bench] batch: {len(cases)} cases, {sum(c.n * c.n for c in cases)} nodes", file=sys.stderr, flush=True)
+    b = acm.Batch(cfgs, states, [c.nsteps for c in cases], chunk=500)
+    b.run()
+    ms, lups = b.timing()
+    st = [b.status(i) for i in range(len(cases))]
+    done = np.array([s["done_ms"] for s in st if s["state"] == acm.BATCH_FINISHED])
+    diverged = sum(1 for s in st if s["state"] != acm.BATCH_FINISHED)
+    b.close()
+    mlups = lups / (ms * 1e-3) / 1e6
+    gbs = 24 * lups / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS + HBM GB/s vs peak; learned-coarse vs plain-fine time at <=2% L2 err",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": int(max(c.nsteps for c in cases)),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched sweep: 512 2D cases n in {32..256}, half periodic TGV / half lid-driven "
+                               "cavity, Re log-uniform [100, 5000], FP32, one persistent launch per 500-step chunk",
+                   "cases": len(cases), "lattice_updates": int(lups), "parallelism": "single GPU"},
+        "wall_ms": round(ms, 2),
+        "case_completion_ms": {"p50": round(float(np.percentile(done, 50)), 2),
+                               "p99": round(float(np.percentile(done, 99)), 2),
+                               "finished": int(done.size), "diverged": diverged},
+        "roofline": {"bound": "hbm", "kernel": "batch_step_kernel", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_lup": 24, "copy_kernel_gbs": copy["gbs"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def closure_timing(steps: int = 2000):
+    """Closure step (coarse 256^2 SMAME step + fused network correction) against
+    the four fine 1024^2 steps it replaces, graph-launched; the network's
+    accuracy comes from the closure experiment, not from this timing."""
+    from paper_2012_03525_amd import closure_experiment
+    t = closure_experiment.step_timing("full", steps=steps, log=lambda m: None)
+    return {"fine_1024_x4_us": round(t["fine_steps_per_coarse_step_us"], 2),
+            "closure_256_step_us": round(t["closure_step_us"], 2),
+            "plain_coarse_256_step_us": round(t["plain_coarse_step_us"], 2),
+            "speedup_vs_fine": round(t["fine_steps_per_coarse_step_us"] / t["closure_step_us"], 3)}
+
+
 def cpu_baseline(name, cfg, st, budget_s):
     """Time the FP64 CPU oracle (single thread) on a bounded sample of the
     same workload: whole-grid steps until about budget_s seconds pass."""
@@ -152,6 +211,9 @@ def main():
         return
     copy = copy_bandwidth(1024)
     print(f"[bench] plain copy kernel: {copy['gbs']} GB/s", file=sys.stderr, flush=True)
+    if a.workload == "batch512":
+        run_batch(a, copy)
+        return
     cfg, st, meta, bpl, kname = workload(a.workload, a.tile)
     solver = acm.Solver(cfg, st)
     nodes = cfg.nx * cfg.ny * (cfg.nz if cfg.dim == 3 else 1)
@@ -207,6 +269,9 @@ def main():
         "state_check": {"nonfinite": d["nonfinite"], "ke": d["ke"], "step": d["step"]},
     }
     solver.close()
+    if a.workload == "tgv3d_256" and not a.no_closure:
+        print("[bench] closure step timing...", file=sys.stderr, flush=True)
+        out["closure"] = closure_timing()
     if not a.no_cpu:
         print("[bench] CPU oracle baseline...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.workload, cfg, st, a.cpu_seconds)

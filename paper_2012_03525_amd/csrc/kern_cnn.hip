@@ -1,6 +1,8 @@
-// Learned-closure network on gfx950: 3x3 convolutions as implicit GEMMs on
-// the bf16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation), the
-// weight gradient as an MFMA reduction over pixels, and the element-wise
+// Learned-closure network on gfx950: per-layer 3x3 convolutions as implicit
+// GEMMs on the bf16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32
+// accumulation) for training, the weight gradient as an MFMA reduction over
+// pixels, a one-launch whole-network inference kernel (16x16x32 bf16 MFMA,
+// all layers of a tile in LDS) for the closure run, and the element-wise
 // pieces (input packing, loss gradient, correction, Adam, box filter,
 // bilinear prolongation).
 //
@@ -40,21 +42,7 @@ __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((unsig
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-enum : int { CONV_RELU = 0, CONV_RAW = 1, CONV_MASK = 2, CONV_APPLY = 3 };
-
-// fp32 state fields corrected in place by the last layer (CONV_APPLY)
-struct ApplyArgs {
-    float* q[3];
-    float d[3];
-};
-
-// Optional source of the first layer's input: the fp32 state itself,
-// normalised and rounded to bf16 while the tile is staged (channels 3..15
-// are zero), so no separate packing pass is needed.
-struct StateIn {
-    const float* q[3];
-    float s[3];
-};
+enum : int { CONV_RELU = 0, CONV_RAW = 1, CONV_MASK = 2 };
 
 // ---------------------------------------------------------------------------
 // forward convolution: workgroup tile TR rows x 32 columns, 4 waves; wave w
@@ -66,19 +54,15 @@ struct StateIn {
 // MODE: CONV_RELU   y = bf16(relu(conv + b))
 //       CONV_RAW    y = fp32(conv + b)
 //       CONV_MASK   y = bf16(conv * (mask > 0))   (data gradient through ReLU)
-//       CONV_APPLY  q_c += d_c (conv + b)_c for c < 3  (closure correction)
-// FROM_STATE: the input is StateIn (fp32 state, CIN = 16) instead of x.
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, int MODE, bool FROM_STATE = false, int TR = 4>
+template <int CIN, int COUT, int MODE, int TR = 4>
 __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t* __restrict__ x,
                                                       const bf16_t* __restrict__ w, const float* __restrict__ bias,
-                                                      const bf16_t* __restrict__ mask, void* __restrict__ y,
-                                                      ApplyArgs ap, StateIn sin)
+                                                      const bf16_t* __restrict__ mask, void* __restrict__ y)
 {
     constexpr int TC = 32, IR = TR + 2, IC = TC + 2;
     constexpr int KS = CIN / 16, NH = COUT / 16, CH4 = CIN / 4;
     constexpr int NG = TR / 2;  // 16-pixel groups per wave
-    static_assert(!FROM_STATE || CIN == 16, "state input has 16 (padded) channels");
     __shared__ __align__(16) bf16_t sx[IR * IC * CIN];
     const int tiles_x = W / TC;
     const int x0 = (blockIdx.x % tiles_x) * TC, y0 = (blockIdx.x / tiles_x) * TR;
@@ -93,34 +77,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t
             for (int nh = 0; nh < NH; ++nh)
                 bw[t][ks][nh] = *reinterpret_cast<const bf16x4*>(w + ((size_t)(t * COUT + nh * 16 + l16) * CIN +
                                                                       ks * 16 + lg * 4));
-    if constexpr (FROM_STATE) {
-        constexpr int NIT = (IR * IC + 255) / 256;
-        float v0[NIT], v1[NIT], v2[NIT];
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {  // all loads first, then the LDS stores
-            const int pix = min((int)threadIdx.x + it * 256, IR * IC - 1);
-            const int r = pix / IC, cc = pix - r * IC;
-            const size_t src = (size_t)wrap(y0 + r - 1, H) * W + wrap(x0 + cc - 1, W);
-            v0[it] = sin.q[0][src];
-            v1[it] = sin.q[1][src];
-            v2[it] = sin.q[2][src];
-        }
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int pix = threadIdx.x + it * 256;
-            if (pix < IR * IC) {
-                bf16_t v[16];
-                v[0] = f2bf(v0[it] * sin.s[0]);
-                v[1] = f2bf(v1[it] * sin.s[1]);
-                v[2] = f2bf(v2[it] * sin.s[2]);
-#pragma unroll
-                for (int c = 3; c < 16; ++c) v[c] = 0;
-                uint4* dst = reinterpret_cast<uint4*>(sx + pix * 16);
-                dst[0] = *reinterpret_cast<uint4*>(&v[0]);
-                dst[1] = *reinterpret_cast<uint4*>(&v[8]);
-            }
-        }
-    } else {
+    {
         constexpr int TOT = IR * IC * CH4;
         constexpr int NIT = (TOT + 255) / 256;
         uint2 v[NIT];
@@ -183,12 +140,6 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t
                     static_cast<bf16_t*>(y)[o] = f2bf(val);
                 } else if constexpr (MODE == CONV_RAW) {
                     static_cast<float*>(y)[o] = val + bias[co];
-                } else if constexpr (MODE == CONV_APPLY) {
-                    if (co < 3) {
-                        float* qc = ap.q[co];
-                        const size_t p = (size_t)py * W + px;
-                        qc[p] = fmaf(ap.d[co], val + bias[co], qc[p]);
-                    }
                 } else {
                     const bf16_t m = mask[o];
                     const bool pos = (m & 0x8000u) == 0 && (m & 0x7FFFu) != 0;
@@ -449,12 +400,12 @@ __global__ void prolong_kernel(int nxc, int nyc, int r, const T* __restrict__ c,
 // ---------------------------------------------------------------------------
 constexpr int CONV_TR = 4;  // rows per workgroup tile (two workgroups per CU at 256 x 256)
 
-template <int CIN, int COUT, int MODE, bool FROM_STATE = false>
+template <int CIN, int COUT, int MODE>
 hipError_t launch_conv(int H, int W, const bf16_t* x, const bf16_t* w, const float* b, const bf16_t* mask, void* y,
-                       hipStream_t s, ApplyArgs ap = ApplyArgs{}, StateIn sin = StateIn{})
+                       hipStream_t s)
 {
-    hipLaunchKernelGGL((conv3x3_kernel<CIN, COUT, MODE, FROM_STATE, CONV_TR>), dim3((W / 32) * (H / CONV_TR)),
-                       dim3(256), 0, s, H, W, x, w, b, mask, y, ap, sin);
+    hipLaunchKernelGGL((conv3x3_kernel<CIN, COUT, MODE, CONV_TR>), dim3((W / 32) * (H / CONV_TR)), dim3(256), 0, s, H,
+                       W, x, w, b, mask, y);
     return hipGetLastError();
 }
 
