@@ -92,32 +92,54 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
     const bool mirror = !interior && c.nonperiodic;
     const int tid = threadIdx.x;
 
-    // ---- stage phi (halo 4) and drho, u, v (halo 2)
-    for (int q = tid; q < S::PXY; q += NT) {
-        const int ly = q / PX, lx = q - ly * PX;
-        int fx, fy;
-        const int sx = map_coord(x0 + lx - 4, nx, c.bc[0], 0, fx);
-        const int sy = map_coord(y0 + ly - 4, ny, c.bc[2], 2, fy);
-        sp[q] = in.phi[(size_t)sy * nx + sx];
-    }
-    for (int q = tid; q < S::RXY; q += NT) {
-        const int ly = q / RX, lx = q - ly * RX;
-        int fx, fy;
-        const int sx = map_coord(x0 + lx - 2, nx, c.bc[0], 0, fx);
-        const int sy = map_coord(y0 + ly - 2, ny, c.bc[2], 2, fy);
-        const size_t s = (size_t)sy * nx + sx;
-        T r = in.r[s], u = in.u[s], v = in.v[s];
-        if (fx >= 0) {
-            u = fmaT(c.fs[fx][0], u, c.fo[fx][0]);
-            v = fmaT(c.fs[fx][1], v, c.fo[fx][1]);
+    // ---- stage phi (halo 4) and drho, u, v (halo 2); every load of the
+    // thread is issued before its first LDS store so the latencies overlap
+    {
+        constexpr int NP = (S::PXY + NT - 1) / NT, NR = (S::RXY + NT - 1) / NT;
+        T pv[NP], rv[NR], uv[NR], vv[NR];
+        int fxs[NR], fys[NR];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int q = min(tid + i * NT, S::PXY - 1);
+            const int ly = q / PX, lx = q - ly * PX;
+            int fx, fy;
+            const int sx = map_coord(x0 + lx - 4, nx, c.bc[0], 0, fx);
+            const int sy = map_coord(y0 + ly - 4, ny, c.bc[2], 2, fy);
+            pv[i] = in.phi[(size_t)sy * nx + sx];
         }
-        if (fy >= 0) {
-            u = fmaT(c.fs[fy][0], u, c.fo[fy][0]);
-            v = fmaT(c.fs[fy][1], v, c.fo[fy][1]);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int q = min(tid + i * NT, S::RXY - 1);
+            const int ly = q / RX, lx = q - ly * RX;
+            const int sx = map_coord(x0 + lx - 2, nx, c.bc[0], 0, fxs[i]);
+            const int sy = map_coord(y0 + ly - 2, ny, c.bc[2], 2, fys[i]);
+            const size_t s = (size_t)sy * nx + sx;
+            rv[i] = in.r[s];
+            uv[i] = in.u[s];
+            vv[i] = in.v[s];
         }
-        sr[q] = r;
-        su[q] = u;
-        sv[q] = v;
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            if (tid + i * NT < S::PXY) sp[tid + i * NT] = pv[i];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int q = tid + i * NT;
+            if (q < S::RXY) {
+                T u = uv[i], v = vv[i];
+                const int fx = fxs[i], fy = fys[i];
+                if (fx >= 0) {
+                    u = fmaT(c.fs[fx][0], u, c.fo[fx][0]);
+                    v = fmaT(c.fs[fx][1], v, c.fo[fx][1]);
+                }
+                if (fy >= 0) {
+                    u = fmaT(c.fs[fy][0], u, c.fo[fy][0]);
+                    v = fmaT(c.fs[fy][1], v, c.fo[fy][1]);
+                }
+                sr[q] = rv[i];
+                su[q] = u;
+                sv[q] = v;
+            }
+        }
     }
     __syncthreads();
 
