@@ -444,7 +444,8 @@ hipError_t conv_dispatch(int H, int W, int cin, int cout, int mode, const void* 
 namespace fused {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int T = 16;                     // output tile side
-constexpr int NT = 256;                   // 4 waves
+constexpr int NT = 512;                   // threads per workgroup
+constexpr int NW = NT / 64;               // waves
 constexpr int AS = 40;                    // activation pixel stride (halfwords): 32 channels + 8, 16-byte aligned
 constexpr int SI = T + 10;                // staged input side (26)
 constexpr int S0 = T + 8, S1 = T + 6;     // output sides of layers 0 and 1 (24, 22); then 20, 18, 16
@@ -519,10 +520,10 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
         const int py = p / SO, px = p - py * SO;
         return ((py + 1) * SN + (px + 1)) * AS + 8 * lg;
     };
-    // groups wave, wave + 4, ...: two at a time so consecutive MFMAs are independent
+    // groups wave, wave + NW, ...: two at a time so consecutive MFMAs are independent
     int g = wave;
-    for (; g + 4 < NG; g += 8) {
-        const int b0 = base_of(g), b1 = base_of(g + 4);
+    for (; g + NW < NG; g += 2 * NW) {
+        const int b0 = base_of(g), b1 = base_of(g + NW);
         f32x4 a0[NH], a1[NH];
 #pragma unroll
         for (int nh = 0; nh < NH; ++nh) a0[nh] = a1[nh] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -537,7 +538,7 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
             }
         }
         finish(g, a0);
-        finish(g + 4, a1);
+        finish(g + NW, a1);
     }
     if (g < NG) {
         const int b0 = base_of(g);
@@ -579,7 +580,8 @@ __global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a)
             wv[l][i] = reinterpret_cast<const uint4*>(a.w[l + 1])[min(tid + i * NT, NV - 1)];
 #pragma unroll
     for (int i = 0; i < IW4; ++i) wv4[i] = reinterpret_cast<const uint4*>(a.w[4])[min(tid + i * NT, NV4 - 1)];
-    constexpr int I0 = W0 / NT;  // 4 layer-0 entries per thread
+    constexpr int I0 = W0 / NT;  // layer-0 entries per thread
+    static_assert(W0 % NT == 0, "layer-0 staging covers the im2col weights exactly");
     bf16_t w0v[I0];
 #pragma unroll
     for (int i = 0; i < I0; ++i) {
@@ -633,7 +635,7 @@ __global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a)
         for (int nh = 0; nh < 2; ++nh)
 #pragma unroll
             for (int j = 0; j < 4; ++j) bb[nh][j] = a.b[0][nh * 16 + 4 * lg + j];
-        for (int g = wave; g < NG; g += 4) {
+        for (int g = wave; g < NG; g += NW) {
             const int p = 16 * g + l16, py = p / S0, px = p - py * S0;
             const int base = ((py + 1) * SI + (px + 1)) * 4;
             bf16x8 x;
