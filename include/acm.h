@@ -172,12 +172,15 @@ typedef struct acm_batch_case {
     acm_fields a, b;       /* caller-owned state sets; initial state in a    */
     const void* force_x;   /* NULL or ny values added to g[0] on row j       */
     int64_t nsteps;        /* steps to run (rounded up to whole chunks)      */
-    int32_t tile;          /* 2D tile variant 0..5, or -1 for the default    */
+    int32_t tile;          /* 2D tile variant 0..5, or -1: the autotuner's
+                              choice for this (nx, ny, precision), measured on
+                              first use and cached for the process             */
 } acm_batch_case;
 
 typedef struct acm_batch_opts {
     int32_t chunk;         /* steps per captured graph, even; 0 = 500        */
-    int32_t blocks;        /* persistent workgroups; 0 = CUs x occupancy     */
+    int32_t blocks;        /* persistent workgroups; 0 = CUs x resident
+                              workgroups per CU (from LDS and VGPR use)      */
     int32_t grab;          /* queue items taken per atomic; 0 = 4            */
     double umax_limit;     /* max |u| above this marks divergence; 0 = 0.3   */
 } acm_batch_opts;

@@ -15,8 +15,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/acm.h"
@@ -222,6 +225,11 @@ int occupancy_blocks()
     return std::max(1, ncu * std::max(1, per));
 }
 
+// Tile variants chosen by the autotuner, per (nx, ny, precision), for the
+// life of the process.
+std::mutex g_tune_mutex;
+std::map<std::tuple<int, int, int>, int> g_tune_cache;
+
 acm_status build_graph(acm_batch* b)
 {
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
@@ -244,6 +252,11 @@ acm_status build_graph(acm_batch* b)
 }
 
 }  // namespace
+
+namespace {
+acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, void* stream, double* ms_per_tile,
+                          int32_t* best);
+}
 
 extern "C" {
 
@@ -269,6 +282,30 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
         if (!k.cfg.allow_unstable && api_max_amplification(k.cfg) > 1.0 + 1e-12)
             return bfail(ACM_EUNSTABLE, "case " + std::to_string(i) + " fails the linear stability check");
     }
+    // tile -1: the autotuner's choice for the case's shape (tuned on first use)
+    std::vector<int> tiles(ncases);
+    for (int i = 0; i < ncases; ++i) {
+        tiles[i] = cases[i].tile;
+        if (tiles[i] >= 0) continue;
+        const auto key = std::make_tuple((int)cases[i].cfg.nx, (int)cases[i].cfg.ny, (int)prec);
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mutex);
+            const auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                tiles[i] = it->second;
+                continue;
+            }
+        }
+        double ms[NTILE2D];
+        int32_t best = 0;
+        const int nxy = cases[i].cfg.nx * cases[i].cfg.ny;
+        const int copies = std::min(1024, std::max(1, (1 << 22) / nxy));  // about 4 M nodes
+        const acm_status st = autotune_shape(cases[i].cfg.nx, cases[i].cfg.ny, prec, copies, 20, stream, ms, &best);
+        if (st != ACM_OK) return st;
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        g_tune_cache[key] = best;
+        tiles[i] = best;
+    }
     acm_batch* b = new (std::nothrow) acm_batch();
     if (!b) return bfail(ACM_EINVAL, "out of host memory");
     b->n = ncases;
@@ -286,7 +323,7 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
     b->done_ms.assign(ncases, -1.0);
     b->umax.assign(ncases, 0.0);
     for (int i = 0; i < ncases; ++i) {
-        b->tile[i] = cases[i].tile >= 0 ? cases[i].tile : 0;
+        b->tile[i] = tiles[i];
         b->nx[i] = cases[i].cfg.nx;
         b->ny[i] = cases[i].cfg.ny;
         b->nsteps[i] = ((cases[i].nsteps + chunk - 1) / chunk) * chunk;
@@ -435,8 +472,17 @@ acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int3
     if (n < 4 || copies <= 0 || steps <= 0 || steps % 2 || !ms_per_tile || !best)
         return bfail(ACM_EINVAL, "autotune: bad arguments");
     if (precision != ACM_F32 && precision != ACM_F64) return bfail(ACM_EINVAL, "autotune: precision");
+    return autotune_shape(n, n, precision, copies, steps, stream, ms_per_tile, best);
+}
+
+}  // extern "C"
+
+namespace {
+acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, void* stream, double* ms_per_tile,
+                          int32_t* best)
+{
     const size_t es = precision == ACM_F64 ? 8 : 4;
-    const size_t field = (size_t)n * n * es;
+    const size_t field = (size_t)nx * ny * es;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, field * 6 * (size_t)copies);
     if (e != hipSuccess) return bfail(ACM_EHIP, "autotune allocation");
@@ -447,13 +493,15 @@ acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int3
         acm_batch_case& k = cs[i];
         std::memset(&k, 0, sizeof k);
         k.cfg.dim = 2;
-        k.cfg.nx = k.cfg.ny = n;
+        k.cfg.nx = nx;
+        k.cfg.ny = ny;
         k.cfg.nz = 1;
         k.cfg.dx = k.cfg.dt = 1.0;
         k.cfg.nu = 0.05;
         k.cfg.rho0 = 1.0;
         k.cfg.sat_rho = k.cfg.sat_mom = 1.0;
         k.cfg.precision = precision;
+        k.cfg.allow_unstable = 1;  // nu = 0.05 is inside the linear bound; skip the per-copy check
         char* base = static_cast<char*>(mem) + (size_t)i * 6 * field;
         k.a = acm_fields{base, base + field, base + 2 * field, nullptr, nullptr};
         k.b = acm_fields{base + 3 * field, base + 4 * field, base + 5 * field, nullptr, nullptr};
@@ -487,5 +535,4 @@ acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int3
     hipFree(mem);
     return st;
 }
-
-}  // extern "C"
+}  // namespace
