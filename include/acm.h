@@ -179,8 +179,7 @@ typedef struct acm_batch_case {
 
 typedef struct acm_batch_opts {
     int32_t chunk;         /* steps per captured graph, even; 0 = 500        */
-    int32_t blocks;        /* persistent workgroups; 0 = CUs x resident
-                              workgroups per CU (from LDS and VGPR use)      */
+    int32_t blocks;        /* persistent workgroups; 0 = CUs x occupancy     */
     int32_t grab;          /* queue items taken per atomic; 0 = 4            */
     double umax_limit;     /* max |u| above this marks divergence; 0 = 0.3   */
 } acm_batch_opts;
