@@ -211,13 +211,19 @@ class FlowSpec:
         k = 2 * math.pi * self.k_force / self.n_fine
         return self.amp_laminar * self.nu_fine * k * k
 
-    def fine_config(self, tile: int = 0):
+    # 2D tile variant 5 (32 x 16) is the fastest step kernel shape on the
+    # 1024^2 fine grid (8.2 us vs 9.1 us for the default), so the fine
+    # reference runs at its best; on the 256^2 coarse grid the default 64 x 4
+    # (twice as many workgroups) is faster (3.4 us vs 4.1 us)
+    FINE_TILE, COARSE_TILE = 5, 0
+
+    def fine_config(self, tile: int = FINE_TILE):
         return acm.make_config(2, self.n_fine, self.n_fine, nu=self.nu_fine, precision="f32", tile=tile,
                                graph_chunk=100)
 
-    def coarse_config(self):
+    def coarse_config(self, tile: int = COARSE_TILE):
         return acm.make_config(2, self.n_coarse, self.n_coarse, nu=self.nu_fine / self.ratio, precision="f32",
-                               graph_chunk=100)
+                               tile=tile, graph_chunk=100)
 
     def fine_force(self):
         y = 2 * math.pi * np.arange(self.n_fine) / self.n_fine
