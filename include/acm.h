@@ -82,7 +82,14 @@ typedef struct acm_config {
     int32_t precision;      /* acm_precision                                  */
     int32_t allow_unstable; /* 1: skip the stability check                    */
     int32_t graph_chunk;    /* steps per captured HIP graph (even); 0 = 64    */
-    int32_t tile;           /* kernel tile variant; 0 = default               */
+    int32_t tile;           /* kernel tile variant; 0 = default.  2D single-
+                               phase: 1 32x8, 2 64x8, 3 16x16, 4 128x4,
+                               5 32x16 (0: 64x4).  2D two-phase: 1 32x8,
+                               2 64x8, 3 16x16 (0: 32x16).  3D: low byte
+                               1 32x8, 3 32x4, 4 64x4, 5 64x16, 7 32x16,
+                               9 128x4, 12 128x8 (0: 64x8; FP64 accepts 3, 4,
+                               else 32x8), bits 8+ = z chunk / 16 (0: 64
+                               planes).  Results do not depend on the tile. */
 } acm_config;
 
 /* Device pointers of one complete state.  w is used in 3D only, phi in

@@ -96,6 +96,29 @@ __device__ __forceinline__ T fmaT(T a, T b, T c) { return fma(a, b, c); }
 __device__ __forceinline__ float recipT(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recipT(double x) { return 1.0 / x; }
 
+// Velocity of a ghost node from its mirror node across face f (0..5):
+// u_a = fs[f][a] u_a + fo[f][a].  f differs between lanes, so the six faces
+// are selected explicitly instead of indexing the coefficient arrays with a
+// per-lane value (which would copy the coefficients to scratch memory).
+template <typename T>
+__device__ __forceinline__ void ghost_velocity(const Coef<T>& c, int f, T& u, T& v, T& w)
+{
+    T s[3], o[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s[a] = c.fs[0][a];
+        o[a] = c.fo[0][a];
+#pragma unroll
+        for (int k = 1; k < 6; ++k) {
+            s[a] = f == k ? c.fs[k][a] : s[a];
+            o[a] = f == k ? c.fo[k][a] : o[a];
+        }
+    }
+    u = fmaT(s[0], u, o[0]);
+    v = fmaT(s[1], v, o[1]);
+    w = fmaT(s[2], w, o[2]);
+}
+
 // ---------------------------------------------------------------------------
 // launchers (kern_step.hip, kern_twophase.hip, kern_diag.hip)
 // ---------------------------------------------------------------------------

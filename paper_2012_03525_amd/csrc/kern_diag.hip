@@ -25,16 +25,13 @@ __device__ __forceinline__ void load_vel(const Coef<T>& c, int dim, const State<
     const int sy = map_coord(gy, c.ny, c.bc[2], 2, fy);
     const int sz = (dim == 3) ? map_coord(gz, c.nz, c.bc[4], 4, fz) : 0;
     const size_t o = ((size_t)sz * c.ny + sy) * c.nx + sx;
-    T q[3] = {s.u[o], s.v[o], dim == 3 ? s.w[o] : T(0)};
-    const int faces[3] = {fx, fy, fz};
-    for (int a = 0; a < 3; ++a) {
-        const int f = faces[a];
-        if (f < 0) continue;
-        for (int k = 0; k < 3; ++k) q[k] = fmaT(c.fs[f][k], q[k], c.fo[f][k]);
-    }
-    u = (double)q[0];
-    v = (double)q[1];
-    w = (double)q[2];
+    T qu = s.u[o], qv = s.v[o], qw = dim == 3 ? s.w[o] : T(0);
+    if (fx >= 0) ghost_velocity(c, fx, qu, qv, qw);
+    if (fy >= 0) ghost_velocity(c, fy, qu, qv, qw);
+    if (fz >= 0) ghost_velocity(c, fz, qu, qv, qw);
+    u = (double)qu;
+    v = (double)qv;
+    w = (double)qw;
 }
 
 template <typename T>

@@ -218,15 +218,10 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
             if (c.nonperiodic) {
 #pragma unroll
                 for (int i = 0; i < NL; ++i) {
-                    const int fc[3] = {sfx[i], sfy[i], fz};
-                    for (int a = 0; a < 3; ++a) {
-                        const int f = fc[a];
-                        if (f >= 0) {
-                            pu[b][i] = fmaT(c.fs[f][0], pu[b][i], c.fo[f][0]);
-                            pv[b][i] = fmaT(c.fs[f][1], pv[b][i], c.fo[f][1]);
-                            pw[b][i] = fmaT(c.fs[f][2], pw[b][i], c.fo[f][2]);
-                        }
-                    }
+                    // faces crossed in x, then y, then z order
+                    if (sfx[i] >= 0) ghost_velocity(c, sfx[i], pu[b][i], pv[b][i], pw[b][i]);
+                    if (sfy[i] >= 0) ghost_velocity(c, sfy[i], pu[b][i], pv[b][i], pw[b][i]);
+                    if (fz >= 0) ghost_velocity(c, fz, pu[b][i], pv[b][i], pw[b][i]);
                 }
             }
         }
@@ -422,11 +417,7 @@ hipError_t launch_step3d(const Coef<T>& c, const State<T>& in, const State<T>& o
             case 4: return launch3d_variant<T, 64, 4, 1>(c, in, out, zc, s);
             case 5: return launch3d_variant<T, 64, 16, 2>(c, in, out, zc, s);
             case 7: return launch3d_variant<T, 32, 16, 2>(c, in, out, zc, s);
-            case 8: return launch3d_variant<T, 128, 8, 2>(c, in, out, zc, s);
             case 9: return launch3d_variant<T, 128, 4, 1>(c, in, out, zc, s);
-            case 10: return launch3d_variant<T, 256, 4, 2>(c, in, out, zc, s);
-            case 11: return launch3d_variant<T, 256, 2, 1>(c, in, out, zc, s);
-            case 6: return launch3d_variant<T, 64, 8, 2>(c, in, out, zc, s);
             case 12: return launch3d_variant<T, 128, 8, 1>(c, in, out, zc, s);
             default: return launch3d_variant<T, 64, 8, 1>(c, in, out, zc, s);  // measured best at 256^3
         }
