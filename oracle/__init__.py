@@ -6,8 +6,9 @@ shares no code with it.
 
 `smame_oracle.c` is a plain single-thread FP64 C implementation of the
 simplified continuity and momentum updates (Eqs. 2.10-2.13), the body
-force, and the two-phase extension (surface-tension force, chemical
-potential and the Cahn-Hilliard equation 2.14 with Heun's RK2).  This module
+force, and the two-phase extension in 2D and 3D (surface-tension force,
+chemical potential, the Cahn-Hilliard equation 2.14 with Heun's RK2 and the
+wetting condition on walls).  This module
 compiles it with gcc and exposes it through ctypes with numpy arrays.
 `cnn.py` holds the FP64 reference of the learned-closure network.
 """
@@ -50,6 +51,7 @@ class _Params(ctypes.Structure):
         ("wall_u", (ctypes.c_double * 3) * 6),
         ("two_phase", ctypes.c_int),
         ("sigma", ctypes.c_double), ("width", ctypes.c_double), ("mobility", ctypes.c_double),
+        ("wet_cos", ctypes.c_double * 6),
     ]
 
 
@@ -78,6 +80,7 @@ class Params:
     sigma: float = 0.0
     width: float = 4.0
     mobility: float = 0.0
+    wet_cos: Sequence[float] = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)  # cos(contact angle) per wall face
 
     def c(self) -> _Params:
         p = _Params()
@@ -92,6 +95,8 @@ class Params:
                 p.wall_u[f][a] = float(self.wall_u[f][a])
         p.two_phase = 1 if self.two_phase else 0
         p.sigma, p.width, p.mobility = self.sigma, self.width, self.mobility
+        for f in range(6):
+            p.wet_cos[f] = float(self.wet_cos[f])
         return p
 
     @property

@@ -26,10 +26,16 @@
  *     of drho (the constant rho0 c_s^2 drops out of a difference);
  *   - walls sit halfway between nodes: ghost drho = mirror value, ghost
  *     velocity = 2 u_wall - mirror value; a symmetry plane mirrors every
- *     field and flips the normal velocity; phi and mu are mirrored
- *     (contact angle 90 degrees); the rules are applied to the level-n fields,
- *     to rho^{n+1} and to every intermediate phase-field quantity;
- *   - isotropic stencils are the D2Q9-weighted 9-point ones;
+ *     field and flips the normal velocity; mu is mirrored (no flux); phi
+ *     obeys the wetting condition of Sec. 2 across a wall (mirrored when the
+ *     contact angle is 90 degrees or at a symmetry plane); the rules are
+ *     applied to the level-n fields, to rho^{n+1} and to every intermediate
+ *     phase-field quantity, face by face in the order x, y, z;
+ *   - the wetting condition d_n phi = -(2/W) cos(theta) (1 - phi_w^2) is
+ *     taken across the halfway wall, (phi_m - phi_g)/dx, with phi_w the
+ *     wall value (phi_g + phi_m)/2, and solved for the ghost exactly;
+ *   - isotropic stencils are the D2Q9-weighted ones in 2D and the
+ *     D3Q19-weighted ones in 3D;
  *   - Heun's method; both stages use u^n.
  */
 #include "smame_oracle.h"
@@ -112,6 +118,39 @@ static void fill_scalar(const orc_params* p, const pgrid* g, double* f)
             }
 }
 
+/* Ghost order parameter across a wall face (Sec. 2 wetting condition):
+ * (phi_m - phi_g)/dx = -(2/W) cos(theta) (1 - phi_w^2), phi_w = (phi_g + phi_m)/2.
+ * With b = dx (2/W) cos(theta) and s = phi_w this is b s^2 + 2 s - (2 phi_m + b) = 0,
+ * whose root that tends to phi_m as b -> 0 is s = (2 phi_m + b) / (1 + sqrt(1 + b (2 phi_m + b))). */
+static double wet_ghost(double m, double b)
+{
+    double s = (2.0 * m + b) / (1.0 + sqrt(1.0 + b * (2.0 * m + b)));
+    return 2.0 * s - m;
+}
+
+/* Fill the ghost layer of the order parameter: periodic wrap or mirror,
+ * then the wetting rule of each crossed wall face (x, y, z order). */
+static void fill_phi(const orc_params* p, const pgrid* g, double* f)
+{
+    int kl = (g->dim == 3) ? -1 : 0, kh = (g->dim == 3) ? g->nz : 0;
+    for (int k = kl; k <= kh; ++k)
+        for (int j = -1; j <= g->ny; ++j)
+            for (int i = -1; i <= g->nx; ++i) {
+                if (!is_ghost(g, i, j, k)) continue;
+                int fc[3] = {-1, -1, -1};
+                int si = map_axis(i, g->nx, p->bc[0], p->bc[1], 0, &fc[0]);
+                int sj = map_axis(j, g->ny, p->bc[2], p->bc[3], 2, &fc[1]);
+                int sk = (g->dim == 3) ? map_axis(k, g->nz, p->bc[4], p->bc[5], 4, &fc[2]) : 0;
+                double val = f[P(g, si, sj, sk)];
+                for (int a = 0; a < 3; ++a) {
+                    int face = fc[a];
+                    if (face >= 0 && p->bc[face] == ORC_WALL)
+                        val = wet_ghost(val, p->dx * (2.0 / p->width) * p->wet_cos[face]);
+                }
+                f[P(g, i, j, k)] = val;
+            }
+}
+
 /* Velocity rule when a face is crossed: wall -> 2 u_w - u (every component),
  * symmetry -> normal component negated. */
 static void apply_face(const orc_params* p, int face, double* uvw)
@@ -166,7 +205,7 @@ static int check_params(const orc_params* p)
     if (p->dim != 2 && p->dim != 3) return -1;
     if (p->nx < 2 || p->ny < 2) return -1;
     if (p->dim == 3 && p->nz < 2) return -1;
-    if (p->two_phase && p->dim != 2) return -1;
+    if (p->two_phase && !(p->width > 0.0)) return -1;
     int nf = (p->dim == 3) ? 6 : 4;
     for (int a = 0; a < nf; a += 2) {
         int lo = p->bc[a], hi = p->bc[a + 1];
@@ -185,50 +224,67 @@ static void axis_strides(const pgrid* g, long s[3])
 }
 
 /* ------------------------------------------------------------------ */
-/* isotropic 2D stencils (D2Q9 weights)                                 */
+/* isotropic stencils: D2Q9 weights in 2D, D3Q19 weights in 3D           */
+/* (Sec. 2: "second-order isotropic schemes"; the weights w_i of the      */
+/* lattice give d_a f = 3 sum_i w_i e_ia f_i / dx and                     */
+/* d_aa f = 6 sum_i w_i (f_i - f_0) / dx^2)                               */
 /* ------------------------------------------------------------------ */
-/* gradient: [4 (f_E - f_W) + (f_NE + f_SE - f_NW - f_SW)] / (12 dx) for x */
-static double giso_x(const double* f, long c, long sy, double dx)
+/* gradient along axis a:
+ *   2D: [4 (f_{+a} - f_{-a}) + sum_{+-b} (f_{+a+-b} - f_{-a+-b})] / (12 dx)
+ *   3D: [2 (f_{+a} - f_{-a}) + sum_{b != a} sum_{+-b} (f_{+a+-b} - f_{-a+-b})] / (12 dx) */
+static double giso(const orc_params* p, const double* f, long c, const long st[3], int a)
 {
-    double e = f[c + 1], wv = f[c - 1];
-    double ne = f[c + 1 + sy], se = f[c + 1 - sy], nw = f[c - 1 + sy], sw = f[c - 1 - sy];
-    return (4.0 * (e - wv) + (ne + se - nw - sw)) / (12.0 * dx);
-}
-static double giso_y(const double* f, long c, long sy, double dx)
-{
-    double n = f[c + sy], s = f[c - sy];
-    double ne = f[c + 1 + sy], nw = f[c - 1 + sy], se = f[c + 1 - sy], sw = f[c - 1 - sy];
-    return (4.0 * (n - s) + (ne + nw - se - sw)) / (12.0 * dx);
-}
-/* Laplacian: [4 (E + W + N + S) + (NE + NW + SE + SW) - 20 C] / (6 dx^2) */
-static double liso(const double* f, long c, long sy, double dx)
-{
-    double ax = f[c + 1] + f[c - 1] + f[c + sy] + f[c - sy];
-    double dg = f[c + 1 + sy] + f[c - 1 + sy] + f[c + 1 - sy] + f[c - 1 - sy];
-    return (4.0 * ax + dg - 20.0 * f[c]) / (6.0 * dx * dx);
+    double face = f[c + st[a]] - f[c - st[a]];
+    double edge = 0.0;
+    for (int b = 0; b < p->dim; ++b) {
+        if (b == a) continue;
+        edge += (f[c + st[a] + st[b]] + f[c + st[a] - st[b]]) - (f[c - st[a] + st[b]] + f[c - st[a] - st[b]]);
+    }
+    double wf = (p->dim == 2) ? 4.0 : 2.0;
+    return (wf * face + edge) / (12.0 * p->dx);
 }
 
-/* mu = 4 a phi (phi^2 - 1) - kappa L_iso phi on interior nodes of padded arrays */
+/* Laplacian:
+ *   2D: [4 (sum of the 4 axis neighbours) + (sum of the 4 diagonal ones) - 20 f] / (6 dx^2)
+ *   3D: [2 (sum of the 6 face neighbours) + (sum of the 12 edge ones) - 24 f] / (6 dx^2) */
+static double liso(const orc_params* p, const double* f, long c, const long st[3])
+{
+    double ax = 0.0, ed = 0.0;
+    for (int a = 0; a < p->dim; ++a) {
+        ax += f[c + st[a]] + f[c - st[a]];
+        for (int b = a + 1; b < p->dim; ++b)
+            ed += (f[c + st[a] + st[b]] + f[c + st[a] - st[b]]) + (f[c - st[a] + st[b]] + f[c - st[a] - st[b]]);
+    }
+    double wa = (p->dim == 2) ? 4.0 : 2.0, w0 = (p->dim == 2) ? 20.0 : 24.0;
+    return (wa * ax + ed - w0 * f[c]) / (6.0 * p->dx * p->dx);
+}
+
+/* mu = 4 a phi (phi^2 - 1) - kappa L_iso phi on interior nodes of padded arrays,
+ * a = 3 sigma / (4 W), kappa = 3 sigma W / 8 (Sec. 2) */
 static void chem_pot(const orc_params* p, const pgrid* g, const double* phi, double* mu)
 {
     double a = 3.0 * p->sigma / (4.0 * p->width);
     double kappa = 3.0 * p->sigma * p->width / 8.0;
-    long sy = g->px;
-    for (int j = 0; j < g->ny; ++j)
-        for (int i = 0; i < g->nx; ++i) {
-            long c = P(g, i, j, 0);
-            double f = phi[c];
-            mu[c] = 4.0 * a * f * (f * f - 1.0) - kappa * liso(phi, c, sy, p->dx);
-        }
+    long st[3];
+    axis_strides(g, st);
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                long c = P(g, i, j, k);
+                double f = phi[c];
+                mu[c] = 4.0 * a * f * (f * f - 1.0) - kappa * liso(p, phi, c, st);
+            }
 }
 
-/* CHE right-hand side R = M L_iso mu - (u G_iso,x phi + v G_iso,y phi) */
+/* CHE right-hand side (2.14): R = M L_iso mu - u_a G_iso,a phi */
 static double che_rhs(const orc_params* p, const pgrid* g, const double* phi, const double* mu,
-                      const double* u, const double* v, long c)
+                      double* const uu[3], long c)
 {
-    long sy = g->px;
-    double diff = p->mobility * liso(mu, c, sy, p->dx);
-    double adv = u[c] * giso_x(phi, c, sy, p->dx) + v[c] * giso_y(phi, c, sy, p->dx);
+    long st[3];
+    axis_strides(g, st);
+    double diff = p->mobility * liso(p, mu, c, st);
+    double adv = 0.0;
+    for (int a = 0; a < p->dim; ++a) adv += uu[a][c] * giso(p, phi, c, st, a);
     return diff - adv;
 }
 
@@ -272,7 +328,7 @@ int orc_step(const orc_params* p, const double* force_x_row,
     }
     if (p->two_phase) {
         to_padded(&g, phi, ph);
-        fill_scalar(p, &g, ph);
+        fill_phi(p, &g, ph);
         chem_pot(p, &g, ph, mu);
         fill_scalar(p, &g, mu);
     }
@@ -327,11 +383,8 @@ int orc_step(const orc_params* p, const double* force_x_row,
                     if (a == 0 && force_x_row) ga += force_x_row[j];
                     mn[a] = m[a][c] - dt * flux + nu * dt * visc - p->sat_mom * sat + dt * rho_new * ga;
                 }
-                if (p->two_phase) {
-                    long sy = g.px;
-                    mn[0] -= dt * ph[c] * giso_x(mu, c, sy, dx);
-                    mn[1] -= dt * ph[c] * giso_y(mu, c, sy, dx);
-                }
+                if (p->two_phase)  /* surface tension -dt phi G_iso mu (Sec. 2) */
+                    for (int a = 0; a < nv; ++a) mn[a] -= dt * ph[c] * giso(p, mu, c, st, a);
                 out_drho[d] = rn[c];
                 out_u[d] = mn[0] / rho_new;
                 out_v[d] = mn[1] / rho_new;
@@ -340,20 +393,22 @@ int orc_step(const orc_params* p, const double* force_x_row,
 
     /* 6. Cahn-Hilliard (2.14) by Heun's method with u^n */
     if (p->two_phase) {
-        for (int j = 0; j < g.ny; ++j)
-            for (int i = 0; i < g.nx; ++i) {
-                long c = P(&g, i, j, 0);
-                phs[c] = ph[c] + dt * che_rhs(p, &g, ph, mu, uu[0], uu[1], c);
-            }
-        fill_scalar(p, &g, phs);
+        for (int k = 0; k < g.nz; ++k)
+            for (int j = 0; j < g.ny; ++j)
+                for (int i = 0; i < g.nx; ++i) {
+                    long c = P(&g, i, j, k);
+                    phs[c] = ph[c] + dt * che_rhs(p, &g, ph, mu, uu, c);
+                }
+        fill_phi(p, &g, phs);
         chem_pot(p, &g, phs, mus);
         fill_scalar(p, &g, mus);
-        for (int j = 0; j < g.ny; ++j)
-            for (int i = 0; i < g.nx; ++i) {
-                long c = P(&g, i, j, 0);
-                double r2 = che_rhs(p, &g, phs, mus, uu[0], uu[1], c);
-                out_phi[D(&g, i, j, 0)] = 0.5 * (ph[c] + phs[c] + dt * r2);
-            }
+        for (int k = 0; k < g.nz; ++k)
+            for (int j = 0; j < g.ny; ++j)
+                for (int i = 0; i < g.nx; ++i) {
+                    long c = P(&g, i, j, k);
+                    double r2 = che_rhs(p, &g, phs, mus, uu, c);
+                    out_phi[D(&g, i, j, k)] = 0.5 * (ph[c] + phs[c] + dt * r2);
+                }
     }
     free(buf);
     return 0;
@@ -397,17 +452,18 @@ int orc_run(const orc_params* p, const double* force_x_row, long nsteps,
 
 int orc_chemical_potential(const orc_params* p, const double* phi, double* out)
 {
-    if (check_params(p) || p->dim != 2) return -1;
+    if (check_params(p)) return -1;
     pgrid g = make_grid(p);
-    long np = (long)g.px * g.py;
+    long np = (long)g.px * g.py * g.pz;
     double* ph = (double*)calloc((size_t)np * 2, sizeof(double));
     if (!ph) return -2;
     double* mu = ph + np;
     to_padded(&g, phi, ph);
-    fill_scalar(p, &g, ph);
+    fill_phi(p, &g, ph);
     chem_pot(p, &g, ph, mu);
-    for (int j = 0; j < g.ny; ++j)
-        for (int i = 0; i < g.nx; ++i) out[D(&g, i, j, 0)] = mu[P(&g, i, j, 0)];
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) out[D(&g, i, j, k)] = mu[P(&g, i, j, k)];
     free(ph);
     return 0;
 }

@@ -28,8 +28,10 @@ typedef struct {
     double g[3];                /* uniform body force                        */
     int bc[6];
     double wall_u[6][3];        /* wall velocity of each face                */
-    int two_phase;              /* 2D only                                   */
+    int two_phase;              /* 2D or 3D                                  */
     double sigma, width, mobility;
+    double wet_cos[6];          /* cos(contact angle) of each wall face;
+                                   0 = 90 degrees (phi mirrored)             */
 } orc_params;
 
 /* One time step.  in_* are level n, out_* receive level n+1 (must not alias
@@ -64,8 +66,8 @@ int orc_diag(const orc_params* p, const double* drho, const double* u,
              const double* prev_u, const double* prev_v, const double* prev_w,
              double* out);
 
-/* Chemical potential mu = 4 a phi (phi^2-1) - kappa L_iso phi of a 2D
- * order-parameter field, with the ghost rules of the parameters. */
+/* Chemical potential mu = 4 a phi (phi^2-1) - kappa L_iso phi of a 2D or
+ * 3D order-parameter field, with the ghost rules of the parameters. */
 int orc_chemical_potential(const orc_params* p, const double* phi, double* mu);
 
 #ifdef __cplusplus

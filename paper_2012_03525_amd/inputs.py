@@ -220,6 +220,19 @@ def batch_cases(ncases: int = 512, seed: int = 4, sizes=tuple(range(32, 257, 16)
     return out
 
 
+def drop_on_wall_3d(nx: int, ny: int, nz: int, radius: float, width: float,
+                    center=(0.0, 0.0, 0.0)) -> Dict[str, np.ndarray]:
+    """Spherical drop (phi = +1 inside, tanh profile of width W) centred at
+    `center` in node coordinates where node (i, j, k) sits at (i + 1/2,
+    j + 1/2, k + 1/2); with the centre on the z = 0 wall it is the hemisphere
+    of the drop-spreading problem (Sec. 3.6).  Fluid at rest, drho = 0."""
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    r = np.sqrt((x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2)
+    phi = np.tanh(2.0 * (radius - r) / width)
+    zero = np.zeros_like(phi)
+    return {"drho": zero.copy(), "u": zero.copy(), "v": zero.copy(), "w": zero.copy(), "phi": phi}
+
+
 def seeded_state(shape, seed: int, scale_u: float = 0.02, scale_r: float = 1e-3,
                  two_phase: bool = False) -> Dict[str, np.ndarray]:
     """Smooth-plus-noise random state for parity tests (not a physical flow)."""

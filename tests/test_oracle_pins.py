@@ -385,6 +385,134 @@ def test_tanh_profile_is_near_equilibrium(orc):
         assert defects[i] / defects[i + 1] > 3.0
 
 
+def _l_iso_symbol(dim, k):
+    """Fourier symbol of the isotropic Laplacian (dx = 1) from the lattice
+    weights: 2D D2Q9 [8 (cos a + cos b) + 4 cos a cos b - 20] / 6,
+    3D D3Q19 [4 sum cos k_a + 4 sum_{a<b} cos k_a cos k_b - 24] / 6."""
+    c = [math.cos(x) for x in k]
+    if dim == 2:
+        return (8 * (c[0] + c[1]) + 4 * c[0] * c[1] - 20) / 6.0
+    return (4 * sum(c) + 4 * (c[0] * c[1] + c[0] * c[2] + c[1] * c[2]) - 24) / 6.0
+
+
+def _g_iso_symbol(dim, k, a):
+    """Imaginary part of the isotropic gradient's symbol along axis a:
+    2D sin k_a (2 + cos k_b) / 3, 3D sin k_a (1 + sum_{b != a} cos k_b) / 3."""
+    others = [math.cos(k[b]) for b in range(dim) if b != a]
+    base = 2.0 if dim == 2 else 1.0
+    return math.sin(k[a]) * (base + sum(others)) / 3.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_chemical_potential_of_a_plane_wave(orc, dim):
+    """mu = 4 a phi (phi^2 - 1) - kappa L_iso phi (Sec. 2) on a periodic box:
+    for a small plane wave the stencil part is the closed-form symbol of the
+    D2Q9 / D3Q19-weighted Laplacian times phi (to round-off)."""
+    n = 8
+    sigma, W = 0.02, 3.0
+    a, kappa = 3 * sigma / (4 * W), 3 * sigma * W / 8
+    kv = [2 * math.pi * m / n for m in ((1, 2, 3)[:dim])]
+    shape = (n,) * dim
+    grids = np.meshgrid(*[np.arange(n)] * dim, indexing="ij")[::-1]  # x fastest
+    theta = sum(kv[i] * grids[i] for i in range(dim))
+    phi = 0.3 * np.cos(theta)
+    p = orc.Params(dim=dim, nx=n, ny=n, nz=n, two_phase=True, sigma=sigma, width=W, mobility=0.1)
+    mu = orc.chemical_potential(p, phi)
+    ref = 4 * a * phi * (phi * phi - 1) - kappa * _l_iso_symbol(dim, kv) * phi
+    np.testing.assert_allclose(mu, ref.reshape(shape), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_heun_advection_of_a_plane_wave(orc, dim):
+    """sigma = 0 (no chemical potential, no surface-tension force) and a
+    uniform flow U: one step multiplies a Fourier mode of phi by
+    1 + z + z^2/2, z = -i dt U.G_iso(k), the amplification of Heun's method
+    with the isotropic gradient's symbol and u^n in both stages (Sec. 2)."""
+    n = 8
+    kv = [2 * math.pi * m / n for m in ((1, 2, 1)[:dim])]
+    U = [0.05, -0.03, 0.02][:dim]
+    grids = np.meshgrid(*[np.arange(n)] * dim, indexing="ij")[::-1]
+    theta = sum(kv[i] * grids[i] for i in range(dim))
+    shape = (n,) * dim
+    st = {"drho": np.zeros(shape), "phi": 0.2 * np.cos(theta)}
+    for i, key in enumerate(("u", "v", "w")[:dim]):
+        st[key] = np.full(shape, U[i])
+    p = orc.Params(dim=dim, nx=n, ny=n, nz=n, nu=0.05, two_phase=True, sigma=0.0, width=3.0, mobility=0.3)
+    out = orc.step(p, st)
+    z = -1j * sum(U[a] * _g_iso_symbol(dim, kv, a) for a in range(dim))
+    amp = 1 + z + z * z / 2
+    ref = 0.2 * np.real(amp * np.exp(1j * theta))
+    np.testing.assert_allclose(out["phi"], ref, rtol=0, atol=1e-15)
+    for i, key in enumerate(("u", "v", "w")[:dim]):  # uniform flow is a fixed point
+        np.testing.assert_array_equal(out[key], st[key])
+
+
+def test_3d_two_phase_reduces_to_2d_for_z_invariant_fields(orc):
+    """The D3Q19-weighted stencils reduce exactly to the D2Q9 ones on fields
+    that do not depend on z, and so does the 7-point flow update: a 3D run of
+    a z-invariant drop (w = 0, periodic in z) must reproduce the 2D run in
+    every z-plane to round-off."""
+    nx, ny, nz = 24, 20, 3
+    st2 = inputs.drop_in_shear(nx, ny, 6.0, 3.0, 0.01)
+    rng = np.random.Generator(np.random.PCG64(31))
+    st2["drho"] = 1e-4 * rng.uniform(-1, 1, size=(ny, nx))
+    wu = [[0.0] * 3 for _ in range(6)]
+    wu[2], wu[3] = [-0.01, 0, 0], [0.01, 0, 0]
+    cos60 = 0.5
+    p2 = orc.Params(dim=2, nx=nx, ny=ny, nu=0.1, bc=(0, 0, 1, 1, 0, 0), wall_u=wu, two_phase=True,
+                    sigma=0.01, width=3.0, mobility=0.05, wet_cos=(0, 0, cos60, -cos60, 0, 0))
+    p3 = orc.Params(dim=3, nx=nx, ny=ny, nz=nz, nu=0.1, bc=(0, 0, 1, 1, 0, 0), wall_u=wu, two_phase=True,
+                    sigma=0.01, width=3.0, mobility=0.05, wet_cos=(0, 0, cos60, -cos60, 0, 0))
+    st3 = {k: np.broadcast_to(v, (nz, ny, nx)).copy() for k, v in st2.items()}
+    st3["w"] = np.zeros((nz, ny, nx))
+    o2 = orc.run(p2, st2, 20)
+    o3 = orc.run(p3, st3, 20)
+    for k in ("drho", "u", "v", "phi"):
+        for kz in range(nz):
+            np.testing.assert_allclose(o3[k][kz], o2[k], rtol=0, atol=1e-13 * max(1.0, np.abs(o2[k]).max()))
+    assert np.abs(o3["w"]).max() < 1e-15
+
+
+def test_wetting_condition_keeps_a_wall_parallel_interface_in_equilibrium(orc):
+    """Sec. 2 wetting condition: d_n phi = -(2/W) cos(theta) (1 - phi_w^2).
+    phi = tanh(2 (z - z0)/W) (phase +1 away from the wall) satisfies it with
+    theta = 180 degrees and phi = -tanh(2 (z - z0)/W) with theta = 0, so the
+    chemical potential at the node next to the wall must be far below what a
+    mirrored phi (theta = 90 degrees) or the opposite angle leave there, and
+    must vanish as the interface is resolved (W/dx grows).  A sign or factor
+    error in the ghost rule fails this."""
+    n = 64
+    z = np.arange(n) + 0.5
+    for sign, cos_t in ((1.0, -1.0), (-1.0, 1.0)):
+        prev = None
+        for W in (4.0, 8.0, 16.0, 32.0):
+            phi1 = sign * np.tanh(2 * (z - 0.25 * W) / W)
+            phi = np.broadcast_to(phi1[:, None], (n, 4)).copy()
+            res = {}
+            for name, wc in (("wet", cos_t), ("mirror", 0.0), ("opposite", -cos_t)):
+                p = orc.Params(dim=2, nx=4, ny=n, two_phase=True, sigma=0.01, width=W, mobility=0.1,
+                               bc=(0, 0, 1, 1, 0, 0), wet_cos=(0, 0, wc, 0, 0, 0))
+                res[name] = abs(orc.chemical_potential(p, phi)[0, 0]) / (3 * 0.01 / W)  # relative to 4a
+            assert res["wet"] < 0.1 * res["mirror"] < 0.1 * res["opposite"], (sign, W, res)
+            if prev is not None:
+                assert prev / res["wet"] > 1.8, (sign, W, prev, res["wet"])  # converges with W/dx
+            prev = res["wet"]
+
+
+def test_phase_field_conserved_at_rest_3d_with_wetting(orc):
+    """u = 0: the CHE is diffusion of mu with no flux through walls and
+    symmetry planes (mu mirrored), whatever the contact angle; sum(phi) is
+    kept to round-off in 3D too."""
+    n = 12
+    st = inputs.drop_on_wall_3d(n, n, n, 5.0, 3.0, center=(0.0, 0.0, 0.0))
+    rng = np.random.Generator(np.random.PCG64(7))
+    st["phi"] = st["phi"] + 0.05 * rng.uniform(-1, 1, size=st["phi"].shape)
+    p = orc.Params(dim=3, nx=n, ny=n, nz=n, nu=0.1, bc=(2, 2, 2, 2, 1, 1), two_phase=True, sigma=0.01,
+                   width=3.0, mobility=0.05, wet_cos=(0, 0, 0, 0, math.cos(math.radians(60)), 0))
+    o = orc.step(p, st)
+    assert abs(o["phi"].sum() - st["phi"].sum()) < 1e-11
+
+
 def test_phase_field_conserved_at_rest(orc):
     """u = 0: the CHE is pure diffusion of mu through the isotropic Laplacian,
     whose sum over a periodic or mirrored grid vanishes; sum(phi) is kept."""
