@@ -75,7 +75,7 @@ typedef struct acm_config {
     double g[3];            /* uniform body force per unit mass               */
     int32_t bc[6];          /* acm_bc per face                                */
     double wall_u[6][3];    /* wall velocity per face (normal part must be 0) */
-    int32_t two_phase;      /* 1: Cahn-Hilliard coupling (2D only)            */
+    int32_t two_phase;      /* 1: Cahn-Hilliard coupling (2D or 3D)           */
     double sigma;           /* surface tension                                */
     double width;           /* interface width W                              */
     double mobility;        /* mobility M                                     */
@@ -90,6 +90,10 @@ typedef struct acm_config {
                                9 128x4, 12 128x8 (0: 64x8; FP64 accepts 3, 4,
                                else 32x8), bits 8+ = z chunk / 16 (0: 64
                                planes).  Results do not depend on the tile. */
+    double wet_cos[6];      /* two-phase: cos(contact angle) of each wall face
+                               for the wetting condition of Sec. 2,
+                               d_n phi = -(2/W) cos(theta) (1 - phi_w^2),
+                               in [-1, 1]; 0 (90 degrees) mirrors phi       */
 } acm_config;
 
 /* Device pointers of one complete state.  w is used in 3D only, phi in

@@ -34,7 +34,7 @@ class Config(ctypes.Structure):
         ("g", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 6), ("wall_u", (ctypes.c_double * 3) * 6),
         ("two_phase", ctypes.c_int32), ("sigma", ctypes.c_double), ("width", ctypes.c_double),
         ("mobility", ctypes.c_double), ("precision", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
-        ("graph_chunk", ctypes.c_int32), ("tile", ctypes.c_int32),
+        ("graph_chunk", ctypes.c_int32), ("tile", ctypes.c_int32), ("wet_cos", ctypes.c_double * 6),
     ]
 
 
@@ -165,7 +165,8 @@ def make_config(dim: int, nx: int, ny: int, nz: int = 1, *, dx: float = 1.0, dt:
                 sat_mom: float = 1.0, g: Sequence[float] = (0.0, 0.0, 0.0),
                 bc: Sequence[int] = (0, 0, 0, 0, 0, 0), wall_u=None, two_phase: bool = False,
                 sigma: float = 0.0, width: float = 4.0, mobility: float = 0.0, precision: str = "f32",
-                allow_unstable: bool = False, graph_chunk: int = 0, tile: int = 0) -> Config:
+                allow_unstable: bool = False, graph_chunk: int = 0, tile: int = 0,
+                wet_cos: Optional[Sequence[float]] = None) -> Config:
     c = Config()
     c.dim, c.nx, c.ny, c.nz = dim, nx, ny, (nz if dim == 3 else 1)
     c.dx, c.dt, c.nu, c.cs, c.rho0 = dx, dt, nu, cs, rho0
@@ -182,6 +183,8 @@ def make_config(dim: int, nx: int, ny: int, nz: int = 1, *, dx: float = 1.0, dt:
     c.allow_unstable = 1 if allow_unstable else 0
     c.graph_chunk = graph_chunk
     c.tile = tile
+    for f in range(6):
+        c.wet_cos[f] = float(wet_cos[f]) if wet_cos is not None else 0.0
     return c
 
 

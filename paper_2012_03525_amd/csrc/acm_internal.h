@@ -30,12 +30,15 @@ struct Coef {
     T fs[6][3];        // ghost velocity = fs * mirror + fo, per crossed face
     T fo[6][3];
     const T* fx;       // per-row x force (ny values) or null
-    // two-phase (2D)
+    // two-phase
     T a4;              // 4 a, a = 3 sigma / (4 W)
     T kap6;            // kappa / (6 dx^2)
     T mob;             // M
     T gi;              // 1 / (12 dx)   isotropic gradient
     T li;              // 1 / (6 dx^2)  isotropic Laplacian
+    T wb[6];           // wall faces: dx (2/W) cos(contact angle); 0 elsewhere
+    int wet;           // any nonzero wb
+    const T* fst[3];   // 3D two-phase: phi G_iso mu per node (subtracted times dt), or null
 };
 
 template <typename T>
@@ -96,6 +99,29 @@ __device__ __forceinline__ T fmaT(T a, T b, T c) { return fma(a, b, c); }
 __device__ __forceinline__ float recipT(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recipT(double x) { return 1.0 / x; }
 
+// Order parameter of a ghost node across a wall face with wetting (Sec. 2):
+// (phi_m - phi_g)/dx = -(2/W) cos(theta) (1 - phi_w^2), phi_w = (phi_g + phi_m)/2
+// the value at the halfway wall.  With b = dx (2/W) cos(theta) the wall value
+// solves b s^2 + 2 s - (2 phi_m + b) = 0; the root that tends to phi_m as
+// b -> 0 is taken in the cancellation-free form below; b = 0 gives phi_m.
+template <typename T>
+__device__ __forceinline__ T wet_ghost(T m, T b)
+{
+    const T q = fmaT(T(2), m, b);
+    const T s = q / (T(1) + sqrt(fmaT(b, q, T(1))));
+    return fmaT(T(2), s, -m);
+}
+
+// wb of the crossed face f (per-lane value: selected, not indexed)
+template <typename T>
+__device__ __forceinline__ T wet_b(const Coef<T>& c, int f)
+{
+    T b = c.wb[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) b = f == k ? c.wb[k] : b;
+    return b;
+}
+
 // Velocity of a ghost node from its mirror node across face f (0..5):
 // u_a = fs[f][a] u_a + fo[f][a].  f differs between lanes, so the six faces
 // are selected explicitly instead of indexing the coefficient arrays with a
@@ -130,6 +156,11 @@ hipError_t launch_step3d(const Coef<T>& c, const State<T>& in, const State<T>& o
                          hipStream_t s);
 template <typename T>
 hipError_t launch_twophase2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
+                             hipStream_t s);
+// 3D two-phase step: scratch holds 5 fields of nx*ny*nz values (mu / mu*,
+// phi*, and phi G_iso mu per axis), owned by the caller
+template <typename T>
+hipError_t launch_twophase3d(const Coef<T>& c, const State<T>& in, const State<T>& out, T* scratch, int tile,
                              hipStream_t s);
 
 // number of FP64 quantities reduced by the diagnostics kernel

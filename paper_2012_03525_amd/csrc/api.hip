@@ -95,9 +95,11 @@ acm_status validate(const acm_config* c)
     if (!(c->dx > 0) || !(c->dt > 0)) return fail(ACM_EINVAL, "dx and dt must be positive");
     if (!(c->nu >= 0)) return fail(ACM_EINVAL, "nu must be non-negative");
     if (!(c->rho0 > 0)) return fail(ACM_EINVAL, "rho0 must be positive");
-    if (c->two_phase && c->dim != 2) return fail(ACM_EINVAL, "two-phase runs are 2D");
     if (c->two_phase && (!(c->width > 0) || !(c->sigma >= 0) || !(c->mobility >= 0)))
         return fail(ACM_EINVAL, "two-phase needs width > 0, sigma >= 0, mobility >= 0");
+    for (int f = 0; f < 6; ++f)
+        if (!(c->wet_cos[f] >= -1.0 && c->wet_cos[f] <= 1.0))
+            return fail(ACM_EINVAL, "wet_cos must lie in [-1, 1]");
     if (c->precision != ACM_F64 && c->precision != ACM_F32) return fail(ACM_EINVAL, "unknown precision");
     const int nf = c->dim == 3 ? 6 : 4;
     for (int f = 0; f < nf; ++f) {
@@ -154,6 +156,11 @@ Coef<T> make_coef(const acm_config& c, const void* force_x)
         k.mob = T(c.mobility);
         k.gi = T(1.0 / (12.0 * dx));
         k.li = T(1.0 / (6.0 * dx * dx));
+        for (int f = 0; f < nf; ++f)
+            if (k.bc[f] == ACM_BC_WALL && c.wet_cos[f] != 0.0) {
+                k.wb[f] = T(dx * (2.0 / c.width) * c.wet_cos[f]);
+                k.wet = 1;
+            }
     }
     return k;
 }
@@ -195,6 +202,7 @@ struct acm_handle {
     int diag_blocks = 0;
     Coef<float> cf;
     Coef<double> cd;
+    void* scratch = nullptr;  // 3D two-phase intermediates (5 fields)
 };
 
 namespace {
@@ -211,6 +219,8 @@ hipError_t launch_typed(const acm_handle* h, const Coef<T>& c, int from, hipStre
 {
     const State<T> in = state_of<T>(h->set[from]);
     const State<T> out = state_of<T>(h->set[1 - from]);
+    if (h->cfg.two_phase && h->cfg.dim == 3)
+        return launch_twophase3d<T>(c, in, out, static_cast<T*>(h->scratch), h->cfg.tile, s);
     if (h->cfg.two_phase) return launch_twophase2d<T>(c, in, out, h->cfg.tile, s);
     if (h->cfg.dim == 3) return launch_step3d<T>(c, in, out, h->cfg.tile, s);
     return launch_step2d<T>(c, in, out, h->cfg.tile, s);
@@ -315,9 +325,11 @@ acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields
     e = hipMalloc(&h->partials, sizeof(double) * NDIAG * (size_t)h->diag_blocks);
     if (e == hipSuccess) e = hipMalloc(&h->result, sizeof(double) * NDIAG);
     if (e == hipSuccess) e = hipHostMalloc(&h->host, sizeof(double) * NDIAG, hipHostMallocDefault);
+    if (e == hipSuccess && cfg->two_phase && cfg->dim == 3)
+        e = hipMalloc(&h->scratch, (size_t)n * 5 * (cfg->precision == ACM_F64 ? sizeof(double) : sizeof(float)));
     if (e != hipSuccess) {
         acm_destroy(h);
-        return hip_fail(e, "allocating reduction buffers");
+        return hip_fail(e, "allocating reduction and scratch buffers");
     }
     *out = h;
     return ACM_OK;
@@ -424,6 +436,7 @@ void acm_destroy(acm_handle* h)
     if (h->partials) hipFree(h->partials);
     if (h->result) hipFree(h->result);
     if (h->host) hipHostFree(h->host);
+    if (h->scratch) hipFree(h->scratch);
     if (h->cap) hipStreamDestroy(h->cap);
     delete h;
 }

@@ -67,8 +67,8 @@ template hipError_t launch_step2d<double>(const Coef<double>&, const State<doubl
 // workgroup.  Plane k+3 is fetched into registers while plane k is computed.
 //
 // GEN = false is the fast path for fully periodic boxes with rho0 = 1: no
-// ghost transforms, m = u + drho u.  GEN = true handles every boundary type
-// and any rho0.  Both evaluate the same expressions, so a periodic rho0 = 1
+// ghost transforms, m = u + drho u.  GEN = true handles every boundary type,
+// any rho0 and the per-node surface-tension force of two-phase runs.  Both evaluate the same expressions, so a periodic rho0 = 1
 // case gives identical bits on either path.
 // ===========================================================================
 template <int TX, int TY, int RPT>
@@ -351,9 +351,17 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
                 const T rho_n = rho0 + rnC;
                 T gx_ = c.gdt[0];
                 if (c.fx) gx_ = fmaT(c.dt, c.fx[y0 + ty], gx_);
-                const T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lpx, -c.cg * fxx)));
-                const T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, lpy, -c.cg * fyy)));
-                const T dmz = fmaT(rho_n, c.gdt[2], fmaT(-c.ks, sz, fmaT(c.kv, lpz, -c.cg * fzz)));
+                T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lpx, -c.cg * fxx)));
+                T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, lpy, -c.cg * fyy)));
+                T dmz = fmaT(rho_n, c.gdt[2], fmaT(-c.ks, sz, fmaT(c.kv, lpz, -c.cg * fzz)));
+                if constexpr (GEN) {
+                    if (c.fst[0]) {  // two-phase: surface-tension force -dt phi G_iso mu
+                        const size_t q = ob + ooff[r] / sizeof(T);
+                        dmx = fmaT(-c.dt, c.fst[0][q], dmx);
+                        dmy = fmaT(-c.dt, c.fst[1][q], dmy);
+                        dmz = fmaT(-c.dt, c.fst[2][q], dmz);
+                    }
+                }
                 const T drn = rnC - rc;
                 const T inv = recipT(rho_n);
                 bstore(rnC, orr, ooff[r]);
@@ -385,7 +393,7 @@ static hipError_t launch3d_variant(const Coef<T>& c, const State<T>& in, const S
                                    hipStream_t s)
 {
     const int nbx = (c.nx + TX - 1) / TX, nby = (c.ny + TY - 1) / TY, nbz = (c.nz + zc - 1) / zc;
-    const bool fast = !c.nonperiodic && c.rho0 == T(1);
+    const bool fast = !c.nonperiodic && c.rho0 == T(1) && !c.fst[0];
     const dim3 grid(nbx * nby * nbz), block(TX * TY / RPT);
     if (fast)
         hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false>), grid, block, 0, s, c, in, out, zc, nbx, nby);

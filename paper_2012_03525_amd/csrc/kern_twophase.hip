@@ -14,7 +14,8 @@
 // Dependency radii: phi needs a 4-node halo (mu on tile+3, phi* on tile+2,
 // mu* on tile+1), the flow fields a 2-node halo.  Ghost positions of every
 // intermediate take the value at their mirror node for walls and symmetry
-// planes (contact angle 90 degrees), so they are computed there.
+// planes, so they are computed there; phi and phi* ghosts across a wall
+// then take the wetting rule of Sec. 2 (identity for a 90 degree angle).
 #include "acm_internal.h"
 #include "tile2d.h"
 
@@ -106,6 +107,10 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
             const int sx = map_coord(x0 + lx - 4, nx, c.bc[0], 0, fx);
             const int sy = map_coord(y0 + ly - 4, ny, c.bc[2], 2, fy);
             pv[i] = in.phi[(size_t)sy * nx + sx];
+            if (c.wet) {  // wetting rule across wall faces, x then y
+                if (fx >= 0) pv[i] = wet_ghost(pv[i], wet_b(c, fx));
+                if (fy >= 0) pv[i] = wet_ghost(pv[i], wet_b(c, fy));
+            }
         }
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
@@ -183,7 +188,15 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         const T gxp = gisox_num<T, PX>(sp, ep), gyp = gisoy_num<T, PX>(sp, ep);
         const T adv = fmaT(su[ef], gxp, sv[ef] * gyp) * c.gi;
         const T rhs = fmaT(c.mob * c.li, liso_num<T, MX>(smu, em), -adv);
-        sps[q] = fmaT(c.dt, rhs, sp[ep]);
+        T val = fmaT(c.dt, rhs, sp[ep]);
+        if (mirror && c.wet) {  // a ghost position takes the wetting rule of its wall faces
+            const int gx = x0 + lx - 2, gy = y0 + ly - 2;
+            if (gx < 0) val = wet_ghost(val, c.wb[0]);
+            if (gx >= nx) val = wet_ghost(val, c.wb[1]);
+            if (gy < 0) val = wet_ghost(val, c.wb[2]);
+            if (gy >= ny) val = wet_ghost(val, c.wb[3]);
+        }
+        sps[q] = val;
     }
     __syncthreads();
 

@@ -56,6 +56,8 @@ def _init(cfg, a=None, b=None):
     (lambda c: setattr(c, "graph_chunk", 3), acm.EINVAL),
     (lambda c: setattr(c, "nu", 0.3), acm.EUNSTABLE),         # above the 2D viscous bound
     (lambda c: setattr(c, "sat_mom", 0.0), acm.EUNSTABLE),    # continuity-only SAT
+    (lambda c: c.wet_cos.__setitem__(2, 1.5), acm.EINVAL),    # |cos(contact angle)| > 1
+    (lambda c: c.wet_cos.__setitem__(3, float("nan")), acm.EINVAL),
 ])
 def test_init_rejects_bad_arguments_without_touching_the_gpu(mutate, expect):
     cfg = acm.make_config(2, 16, 16, nu=0.05)

@@ -4,6 +4,8 @@ These CPU tests emulate FP32 *storage* with the FP64 oracle: every step is
 computed in FP64 and the state is then rounded to FP32, exactly what a
 kernel with FP32 fields and perfect arithmetic would keep.  They fix the
 tolerances the GPU parity tests use."""
+import math
+
 import numpy as np
 
 from paper_2012_03525_amd import inputs
@@ -67,3 +69,33 @@ def test_phase_field_storage_sets_two_phase_drho_bound(orc):
     den = np.sqrt(np.sum(ref["u"] ** 2 + ref["v"] ** 2))
     assert num / den < 2e-5
     assert rl2(a["phi"], ref["phi"]) < 1e-5
+
+
+def test_phase_field_storage_sets_3d_two_phase_velocity_bound(orc):
+    """3D drop spreading on a wetting wall (32^3, R = 12, W = 3.2, theta = 60
+    degrees), 200 steps.  The flow starts at rest and is driven only by
+    phi grad mu, so rounding only phi to FP32 after each step already moves
+    the velocity by ~1.4e-5 (relative L2) and drho by ~2.5e-5, while rounding
+    only the flow fields costs ~3e-8.  The GPU FP32 test of this case
+    therefore bounds the velocity at 1e-4 (FP32 arithmetic adds about as much
+    again) instead of the 2e-5 that holds for the Taylor-Green case."""
+    n = 32
+    p = orc.Params(dim=3, nx=n, ny=n, nz=n, nu=0.08, bc=(2, 2, 2, 2, 1, 1), two_phase=True, sigma=0.01,
+                   width=3.2, mobility=0.05, wet_cos=(0, 0, 0, 0, math.cos(math.radians(60)), 0))
+    st0 = {k: f32(v) for k, v in inputs.drop_on_wall_3d(n, n, n, 12.0, 3.2).items()}
+    ref = orc.run(p, st0, 200)
+    a = dict(st0)
+    b = dict(st0)
+    for _ in range(200):
+        a = orc.step(p, a)
+        a["phi"] = f32(a["phi"])
+        b = orc.step(p, b)
+        for k in ("drho", "u", "v", "w"):
+            b[k] = f32(b[k])
+
+    def vel(x, y):
+        num = np.sqrt(sum(np.sum((x[k] - y[k]) ** 2) for k in ("u", "v", "w")))
+        return num / np.sqrt(sum(np.sum(y[k] ** 2) for k in ("u", "v", "w")))
+    assert 5e-6 < vel(a, ref) < 5e-5
+    assert vel(b, ref) < 1e-6
+    assert rl2(a["phi"], ref["phi"]) < 1e-6
