@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="tgv3d_256",
-                    choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024", "batch512"])
+                    choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024", "drop_spreading_96", "batch512"])
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the closure step timing in the default workload's line")
     ap.add_argument("--tile", type=int, default=0)
@@ -83,6 +83,25 @@ def workload(name, tile):
         meta = {"workload": "2D periodic Taylor-Green vortex 64^2, FP64", "grid": [n, n], "u0": 0.01, "nu": 0.01}
         bytes_per_lup = 48
         kernel = "step2d_kernel"
+    elif name == "drop_spreading_96":
+        # drop spreading on a wall (Sec. 3.6): N_L = 32, c = 10, Re = 100 (Oh = 0.1), Cn = 0.1,
+        # Pe = 8000, theta = 60 degrees; [0,3]^3 with symmetry planes at the sides, walls at z = 0, 3
+        NL, c, Re, Cn, Pe, theta = 32, 10.0, 100.0, 0.1, 8000.0, 60.0
+        n = 3 * NL
+        nu = NL / (c * Re)
+        sigma = NL / (c * c * Re)
+        W = Cn * NL
+        M = NL * NL / (Pe * nu)
+        wet = [0.0] * 6
+        wet[4] = math.cos(math.radians(theta))
+        cfg = acm.make_config(3, n, n, n, nu=nu, precision="f32", bc=(2, 2, 2, 2, 1, 1), two_phase=True,
+                              sigma=sigma, width=W, mobility=M, tile=tile, graph_chunk=100, wet_cos=wet)
+        st = inputs.drop_on_wall_3d(n, n, n, float(NL), W, center=(0.0, 0.0, 0.0))
+        meta = {"workload": "3D drop spreading on a wall 96^3 (N_L = 32, theta = 60 deg), FP32", "grid": [n, n, n],
+                "N_L": NL, "c": c, "Re": Re, "Cn": Cn, "Pe": Pe, "theta_deg": theta, "nu": nu, "sigma": sigma,
+                "mobility": M}
+        bytes_per_lup = 40  # read drho,u,v,w,phi + write them (FP32), the fused minimum
+        kernel = "twophase3d step (5 launches)"
     else:
         n = 1024
         wu = [[0.0] * 3 for _ in range(6)]
@@ -181,7 +200,8 @@ def cpu_baseline(name, cfg, st, budget_s):
     p = oracle.Params(dim=cfg.dim, nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, dx=cfg.dx, dt=cfg.dt, nu=cfg.nu,
                       cs=(cfg.cs if cfg.cs > 0 else cfg.dx / (cfg.dt * math.sqrt(3))),
                       bc=list(cfg.bc), wall_u=[[cfg.wall_u[f][a] for a in range(3)] for f in range(6)],
-                      two_phase=bool(cfg.two_phase), sigma=cfg.sigma, width=cfg.width, mobility=cfg.mobility)
+                      two_phase=bool(cfg.two_phase), sigma=cfg.sigma, width=cfg.width, mobility=cfg.mobility,
+                      wet_cos=[cfg.wet_cos[f] for f in range(6)])
     nodes = cfg.nx * cfg.ny * (cfg.nz if cfg.dim == 3 else 1)
     t0 = time.perf_counter()
     steps = 0

@@ -402,10 +402,39 @@ static hipError_t launch3d_variant(const Coef<T>& c, const State<T>& in, const S
     return hipGetLastError();
 }
 
+// Default launch shape for small grids: the 2.5D march gives one workgroup
+// per (column, z chunk), so a 96^3 grid at 64 x 8 x 64 would keep only 48
+// workgroups busy.  Shorten the chunk, then the tile, until the launch has
+// at least two workgroups per CU (the choice never changes results).
+static int small_grid_tile(int nx, int ny, int nz, bool fp64)
+{
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+    }
+    struct Cand {
+        int code, tx, ty, zc;
+    };
+    static const Cand f32c[] = {{2, 64, 8, 64}, {2, 64, 8, 32}, {2, 64, 8, 16}, {1, 32, 8, 16}, {3, 32, 4, 16}};
+    static const Cand f64c[] = {{1, 32, 8, 64}, {1, 32, 8, 32}, {1, 32, 8, 16}, {3, 32, 4, 16}};
+    const Cand* cs = fp64 ? f64c : f32c;
+    const int nc = fp64 ? 4 : 5;
+    for (int i = 0; i < nc; ++i) {
+        const long nb = (long)((nx + cs[i].tx - 1) / cs[i].tx) * ((ny + cs[i].ty - 1) / cs[i].ty) *
+                        ((nz + cs[i].zc - 1) / cs[i].zc);
+        if (nb >= 2L * ncu || i == nc - 1) return cs[i].code | ((cs[i].zc / 16) << 8);
+    }
+    return 0;
+}
+
 // tile codes (3D): low byte = in-plane shape, upper bits = z chunk / 16
 template <typename T>
 hipError_t launch_step3d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile, hipStream_t s)
 {
+    if (tile == 0) tile = small_grid_tile(c.nx, c.ny, c.nz, sizeof(T) == 8);
     int zc = (tile >> 8) * 16;
     if (zc <= 0) zc = 64;
     if (zc > c.nz) zc = c.nz;

@@ -499,6 +499,40 @@ def test_wetting_condition_keeps_a_wall_parallel_interface_in_equilibrium(orc):
             prev = res["wet"]
 
 
+def _contact_angle_deg(phi):
+    """Contact angle of a 2D sessile drop on the y = 0 wall from a circle
+    fitted to its phi = 0 contour (rows interpolated linearly): the circle
+    meets the wall at theta with cos(theta) = -y_c / R."""
+    pts = []
+    for j in range(phi.shape[0]):
+        row = phi[j]
+        for i in range(len(row) - 1):
+            if row[i] * row[i + 1] < 0:
+                t = row[i] / (row[i] - row[i + 1])
+                pts.append((i + 0.5 + t, j + 0.5))
+    x, y = np.array(pts).T
+    (xc, yc, c), *_ = np.linalg.lstsq(np.c_[2 * x, 2 * y, np.ones_like(x)], x * x + y * y, rcond=None)
+    return math.degrees(math.acos(-yc / math.sqrt(c + xc * xc + yc * yc)))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_sessile_drop_relaxes_to_the_contact_angle(orc, theta):
+    """Sec. 2 wetting condition, physics check: a semicircular drop (R = 24,
+    W = 4) on a wall with contact angle theta relaxes to a circular cap that
+    meets the wall at theta (Young's angle): within 2.5 degrees after 20,000
+    steps (the fit gives 61.1 and 118.9 degrees)."""
+    nx, ny = 128, 64
+    X, Y = np.meshgrid(np.arange(nx) + 0.5, np.arange(ny) + 0.5)
+    z = np.zeros((ny, nx))
+    st = {"drho": z.copy(), "u": z.copy(), "v": z.copy(),
+          "phi": np.tanh(2 * (24.0 - np.sqrt((X - 64) ** 2 + Y ** 2)) / 4.0)}
+    p = orc.Params(dim=2, nx=nx, ny=ny, nu=0.1, bc=(0, 0, 1, 1, 0, 0), two_phase=True, sigma=0.01, width=4.0,
+                   mobility=0.2, wet_cos=(0, 0, math.cos(math.radians(theta)), 0, 0, 0))
+    st = orc.run(p, st, 20000)
+    assert abs(_contact_angle_deg(st["phi"]) - theta) < 2.5
+
+
 def test_phase_field_conserved_at_rest_3d_with_wetting(orc):
     """u = 0: the CHE is diffusion of mu with no flux through walls and
     symmetry planes (mu mirrored), whatever the contact angle; sum(phi) is
