@@ -11,17 +11,13 @@
 //   L_iso f   = [2 (sum of the 6 face neighbours) + (sum of the 12 edge neighbours) - 24 f] / (6 dx^2)
 // Ghosts: mu is mirrored across walls and symmetry planes (no flux); phi
 // and phi* are mirrored, then take the wetting rule of each crossed wall
-// face (x, y, z order).  One thread per node; neighbours are read from
-// global memory through the caches.
+// face (x, y, z order).  One thread per node; each stencil field is staged
+// per workgroup in LDS with its halo.
 #include "acm_internal.h"
 
 namespace acm {
 
 namespace {
-
-struct Dims {
-    int nx, ny, nz;
-};
 
 // value of a scalar field at node (i, j, k), which may lie one layer outside
 // the grid; WET applies the wetting rule across wall faces
@@ -41,23 +37,6 @@ __device__ __forceinline__ T at(const Coef<T>& c, const T* __restrict__ f, int i
         }
     }
     return v;
-}
-
-// The 19 values of the D3Q19 neighbourhood: n[1 + dx][1 + dy][1 + dz]
-// (only face and edge entries and the centre are filled).
-template <bool WET, typename T>
-__device__ __forceinline__ void gather19(const Coef<T>& c, const T* __restrict__ f, int i, int j, int k, T n[3][3][3])
-{
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int nz = (dx != 0) + (dy != 0) + (dz != 0);
-                if (nz == 3) continue;  // corners are not part of the stencil
-                n[1 + dx][1 + dy][1 + dz] = at<WET>(c, f, i + dx, j + dy, k + dz);
-            }
 }
 
 // numerators (the 1/(12 dx) and 1/(6 dx^2) factors are applied by the caller)
@@ -92,38 +71,92 @@ __device__ __forceinline__ T gz_num(const T n[3][3][3])
     return fmaT(T(2), n[1][1][2] - n[1][1][0], e);
 }
 
-__device__ __forceinline__ bool node(const Dims& d, int& i, int& j, int& k)
+// Workgroup tile BX x BY x BZ nodes; each field a kernel reads with its
+// 19-point stencil is staged once per workgroup in LDS with a one-node halo
+// (ghost rules applied while staging), so a node's neighbours come from LDS
+// instead of 19 separate global loads.
+constexpr int BX = 32, BY = 4, BZ = 4, NTH = BX * BY * BZ;
+constexpr int RX = BX + 2, RY = BY + 2, RZ = BZ + 2, RXYZ = RX * RY * RZ;
+
+template <bool WET, typename T>
+__device__ __forceinline__ void stage(const Coef<T>& c, const T* __restrict__ f, int i0, int j0, int k0, T* s)
 {
-    i = blockIdx.x * blockDim.x + threadIdx.x;
-    j = blockIdx.y * blockDim.y + threadIdx.y;
-    k = blockIdx.z;
-    return i < d.nx && j < d.ny && k < d.nz;
+    const int tid = threadIdx.x + BX * (threadIdx.y + BY * threadIdx.z);
+    constexpr int NIT = (RXYZ + NTH - 1) / NTH;
+    T v[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {  // every load before the first LDS store
+        const int q = min(tid + it * NTH, RXYZ - 1);
+        const int lz = q / (RX * RY), r = q - lz * (RX * RY), ly = r / RX, lx = r - ly * RX;
+        v[it] = at<WET>(c, f, i0 + lx - 1, j0 + ly - 1, k0 + lz - 1);
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it)
+        if (tid + it * NTH < RXYZ) s[tid + it * NTH] = v[it];
+}
+
+// the D3Q19 neighbourhood of the thread's node from a staged region
+template <typename T>
+__device__ __forceinline__ void nb19(const T* s, T n[3][3][3])
+{
+    const int e = (threadIdx.x + 1) + RX * ((threadIdx.y + 1) + RY * (threadIdx.z + 1));
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if ((dx != 0) + (dy != 0) + (dz != 0) == 3) continue;  // corners are not part of the stencil
+                n[1 + dx][1 + dy][1 + dz] = s[e + dx + RX * (dy + RY * dz)];
+            }
+}
+
+struct Node {
+    int i, j, k;
+    bool in;
+};
+template <typename T>
+__device__ __forceinline__ Node my_node(const Coef<T>& c)
+{
+    Node n;
+    n.i = blockIdx.x * BX + threadIdx.x;
+    n.j = blockIdx.y * BY + threadIdx.y;
+    n.k = blockIdx.z * BZ + threadIdx.z;
+    n.in = n.i < c.nx && n.j < c.ny && n.k < c.nz;
+    return n;
 }
 
 // mu = 4 a phi (phi^2 - 1) - kappa L_iso phi
 template <typename T>
-__global__ __launch_bounds__(256) void chem3_kernel(Coef<T> c, const T* __restrict__ phi, T* __restrict__ mu)
+__global__ __launch_bounds__(NTH) void chem3_kernel(Coef<T> c, const T* __restrict__ phi, T* __restrict__ mu)
 {
-    int i, j, k;
-    if (!node(Dims{c.nx, c.ny, c.nz}, i, j, k)) return;
+    __shared__ T sp[RXYZ];
+    stage<true>(c, phi, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * BZ, sp);
+    __syncthreads();
+    const Node d = my_node(c);
+    if (!d.in) return;
     T n[3][3][3];
-    gather19<true>(c, phi, i, j, k, n);
+    nb19(sp, n);
     const T p = n[1][1][1];
-    mu[((size_t)k * c.ny + j) * c.nx + i] = fmaT(c.a4 * p, fmaT(p, p, T(-1)), -c.kap6 * lap_num(n));
+    mu[((size_t)d.k * c.ny + d.j) * c.nx + d.i] = fmaT(c.a4 * p, fmaT(p, p, T(-1)), -c.kap6 * lap_num(n));
 }
 
 // F_a = phi G_iso,a mu and phi* = phi + dt (M L_iso mu - u_a G_iso,a phi)
 template <typename T>
-__global__ __launch_bounds__(256) void stage1_kernel(Coef<T> c, State<T> in, const T* __restrict__ mu,
+__global__ __launch_bounds__(NTH) void stage1_kernel(Coef<T> c, State<T> in, const T* __restrict__ mu,
                                                      T* __restrict__ fx, T* __restrict__ fy, T* __restrict__ fz,
                                                      T* __restrict__ phis)
 {
-    int i, j, k;
-    if (!node(Dims{c.nx, c.ny, c.nz}, i, j, k)) return;
-    const size_t o = ((size_t)k * c.ny + j) * c.nx + i;
+    __shared__ T sm[RXYZ], sp[RXYZ];
+    stage<false>(c, mu, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * BZ, sm);
+    stage<true>(c, in.phi, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * BZ, sp);
+    __syncthreads();
+    const Node d = my_node(c);
+    if (!d.in) return;
+    const size_t o = ((size_t)d.k * c.ny + d.j) * c.nx + d.i;
     T m[3][3][3], p[3][3][3];
-    gather19<false>(c, mu, i, j, k, m);
-    gather19<true>(c, in.phi, i, j, k, p);
+    nb19(sm, m);
+    nb19(sp, p);
     const T pc = p[1][1][1];
     fx[o] = pc * (gx_num(m) * c.gi);
     fy[o] = pc * (gy_num(m) * c.gi);
@@ -135,15 +168,19 @@ __global__ __launch_bounds__(256) void stage1_kernel(Coef<T> c, State<T> in, con
 
 // phi^{n+1} = (phi + phi* + dt (M L_iso mu* - u_a G_iso,a phi*)) / 2
 template <typename T>
-__global__ __launch_bounds__(256) void stage2_kernel(Coef<T> c, State<T> in, const T* __restrict__ phis,
+__global__ __launch_bounds__(NTH) void stage2_kernel(Coef<T> c, State<T> in, const T* __restrict__ phis,
                                                      const T* __restrict__ mus, T* __restrict__ phi_out)
 {
-    int i, j, k;
-    if (!node(Dims{c.nx, c.ny, c.nz}, i, j, k)) return;
-    const size_t o = ((size_t)k * c.ny + j) * c.nx + i;
+    __shared__ T sm[RXYZ], sp[RXYZ];
+    stage<false>(c, mus, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * BZ, sm);
+    stage<true>(c, phis, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * BZ, sp);
+    __syncthreads();
+    const Node d = my_node(c);
+    if (!d.in) return;
+    const size_t o = ((size_t)d.k * c.ny + d.j) * c.nx + d.i;
     T m[3][3][3], p[3][3][3];
-    gather19<false>(c, mus, i, j, k, m);
-    gather19<true>(c, phis, i, j, k, p);
+    nb19(sm, m);
+    nb19(sp, p);
     const T adv = fmaT(in.u[o], gx_num(p), fmaT(in.v[o], gy_num(p), in.w[o] * gz_num(p))) * c.gi;
     const T rhs = fmaT(c.mob * c.li, lap_num(m), -adv);
     phi_out[o] = T(0.5) * fmaT(c.dt, rhs, in.phi[o] + p[1][1][1]);
@@ -159,7 +196,7 @@ hipError_t launch_twophase3d(const Coef<T>& c, const State<T>& in, const State<T
     T* mu = scratch;
     T* phis = scratch + n;
     T* f[3] = {scratch + 2 * n, scratch + 3 * n, scratch + 4 * n};
-    const dim3 block(64, 4), grid((c.nx + 63) / 64, (c.ny + 3) / 4, c.nz);
+    const dim3 block(BX, BY, BZ), grid((c.nx + BX - 1) / BX, (c.ny + BY - 1) / BY, (c.nz + BZ - 1) / BZ);
     hipLaunchKernelGGL(chem3_kernel<T>, grid, block, 0, s, c, in.phi, mu);
     hipLaunchKernelGGL(stage1_kernel<T>, grid, block, 0, s, c, in, mu, f[0], f[1], f[2], phis);
     Coef<T> cf = c;
