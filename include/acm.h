@@ -65,7 +65,9 @@ typedef enum { ACM_F64 = 0, ACM_F32 = 1 } acm_precision;
 /* Problem statement (Sec. 2; Sec. 3 opening: dx = L/N_L, dt = T_c/N_t). */
 typedef struct acm_config {
     int32_t dim;            /* 2 or 3                                         */
-    int32_t nx, ny, nz;     /* nodes per axis (nz ignored in 2D); each >= 4   */
+    int32_t nx, ny, nz;     /* nodes per axis (nz ignored in 2D); each >= 4;
+                               at most 4e9 nodes; 3D: nx*ny values of one
+                               plane below 2 GiB                              */
     double dx, dt;          /* grid spacing and time step                     */
     double nu;              /* kinematic viscosity                            */
     double cs;              /* sound speed; <= 0 selects dx/(dt sqrt 3)       */

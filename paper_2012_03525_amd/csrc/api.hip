@@ -92,6 +92,8 @@ acm_status validate(const acm_config* c)
         return fail(ACM_EINVAL, "every axis needs at least " + std::to_string(minn) + " nodes");
     if ((double)c->nx * c->ny * (c->dim == 3 ? c->nz : 1) > 4.0e9)
         return fail(ACM_EINVAL, "grid larger than 4e9 nodes");
+    if (c->dim == 3 && (double)c->nx * c->ny * (c->precision == ACM_F64 ? 8 : 4) >= 2147483648.0)
+        return fail(ACM_EINVAL, "3D plane (nx * ny values) of 2 GiB or more");
     if (!(c->dx > 0) || !(c->dt > 0)) return fail(ACM_EINVAL, "dx and dt must be positive");
     if (!(c->nu >= 0)) return fail(ACM_EINVAL, "nu must be non-negative");
     if (!(c->rho0 > 0)) return fail(ACM_EINVAL, "rho0 must be positive");

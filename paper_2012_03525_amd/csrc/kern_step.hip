@@ -66,7 +66,7 @@ template hipError_t launch_step2d<double>(const Coef<double>&, const State<doubl
 // plus a one-node ring, so every node's drho' is formed exactly once per
 // workgroup.  Plane k+3 is fetched into registers while plane k is computed.
 //
-// GEN = false is the fast path for fully periodic boxes with rho0 = 1: no
+// GEN = false is the fast path for fully periodic boxes (nz >= 2) with rho0 = 1: no
 // ghost transforms, m = u + drho u.  GEN = true handles every boundary type,
 // any rho0 and the per-node surface-tension force of two-phase runs.  Both evaluate the same expressions, so a periodic rho0 = 1
 // case gives identical bits on either path.
@@ -104,33 +104,62 @@ __device__ __forceinline__ T rho_new_3d(const Coef<T>& c, const T* r0, const T* 
     return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
 }
 
-// Buffer-resource access for the z-march: one descriptor per field and plane
-// (scalar registers), 32-bit lane byte offsets fixed for the whole march.
-// The hardware range-checks every access against the plane size.
+// Buffer-resource access for the z-march: 32-bit lane byte offsets within a
+// plane, fixed for the whole march, plus a uniform plane offset.  A field
+// below 2 GiB gets one descriptor for the march and the plane's byte offset
+// in the scalar offset operand, so moving to the next plane costs one scalar
+// multiply; a larger field (WIDE) gets a descriptor per field and plane.
+// The hardware range-checks every access against the descriptor's size.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
-__device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, unsigned off)
+__device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
 }
-__device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, unsigned off)
+__device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff)
 {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
 }
 // streaming (non-temporal) store: the new state is not re-read in this step
-__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off)
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 2);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, 2);
 }
-__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned off)
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff)
 {
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 2);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, 2);
 }
 
-template <typename T, int TX, int TY, int RPT, bool GEN>
+// the four field descriptors of one plane (WIDE) or of the whole field, and
+// the scalar byte offset of plane z
+template <bool WIDE, typename T>
+struct PlaneAccess {
+    __amdgpu_buffer_rsrc_t r, u, v, w;
+    unsigned soff;
+    __device__ __forceinline__ PlaneAccess(const State<T>& f, int z, unsigned plane, unsigned pbytes,
+                                           unsigned fbytes)
+    {
+        if constexpr (WIDE) {
+            const size_t base = (size_t)z * plane;
+            r = plane_rsrc(f.r + base, pbytes);
+            u = plane_rsrc(f.u + base, pbytes);
+            v = plane_rsrc(f.v + base, pbytes);
+            w = plane_rsrc(f.w + base, pbytes);
+            soff = 0u;
+        } else {
+            r = plane_rsrc(f.r, fbytes);
+            u = plane_rsrc(f.u, fbytes);
+            v = plane_rsrc(f.v, fbytes);
+            w = plane_rsrc(f.w, fbytes);
+            soff = (unsigned)z * pbytes;
+        }
+    }
+};
+
+template <typename T, int TX, int TY, int RPT, bool GEN, bool WIDE>
 __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<T> in, State<T> out, int zc,
                                                                 int nbx, int nby)
 {
@@ -139,6 +168,9 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
     constexpr int YS = S::YS;
     __shared__ T sr[4][RXY], su[4][RXY], sv[4][RXY], sw[4][RXY];
     __shared__ T sd[2][DXY];
+    // ghost velocity rules u_a = gs[0][f][a] u_a + gs[1][f][a] per crossed
+    // face f, looked up per lane from LDS (GEN only)
+    __shared__ T gs[2][6][3];
 
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = lb % nbx;
@@ -150,6 +182,7 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const unsigned pbytes = plane * (unsigned)sizeof(T);
+    const unsigned fbytes = WIDE ? 0u : pbytes * (unsigned)nz;  // below 2^31 unless WIDE
     const int tid = threadIdx.x;
     const int tx = tid % TX, tyb = tid / TX;
     const int gx = x0 + tx;
@@ -188,56 +221,85 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
         }
         dsrc[i] = ey * RX + ex;
     }
-    // output byte offsets of the thread's nodes (same in every plane)
-    unsigned ooff[RPT];
-    bool oact[RPT];
+    // output byte offsets of the thread's nodes (same in every plane).  A
+    // lane outside the grid (ragged tile) computes like the others but gets
+    // the descriptor size as its offset, so the range check drops its stores
+    // (no branch around the stores: the memory-counter waits stay exact).
+    unsigned ooff[RPT], oidx[RPT];
+    T fxr[RPT];  // per-row x force, dt excluded
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int gy = y0 + tyb + r * YS;
-        oact[r] = (gx < nx) && (gy < ny);
-        ooff[r] = oact[r] ? ((unsigned)gy * (unsigned)nx + (unsigned)gx) * (unsigned)sizeof(T) : 0u;
+        const bool act = (gx < nx) && (gy < ny);
+        oidx[r] = act ? (unsigned)gy * (unsigned)nx + (unsigned)gx : 0u;
+        ooff[r] = act ? oidx[r] * (unsigned)sizeof(T) : (WIDE ? pbytes : fbytes);
+        fxr[r] = c.fx ? c.fx[min(gy, ny - 1)] : T(0);
     }
 
+    if constexpr (GEN) {
+        if (tid < 18) {
+            gs[0][tid / 3][tid % 3] = c.fs[tid / 3][tid % 3];
+            gs[1][tid / 3][tid % 3] = c.fo[tid / 3][tid % 3];
+        }
+        __syncthreads();
+    }
+    auto ghost = [&](int f, T& u, T& v, T& w) {
+        u = fmaT(gs[0][f][0], u, gs[1][f][0]);
+        v = fmaT(gs[0][f][1], v, gs[1][f][1]);
+        w = fmaT(gs[0][f][2], w, gs[1][f][2]);
+    };
+
     T pr[2][NL], pu[2][NL], pv[2][NL], pw[2][NL];
-    // fetch plane gz into register set b (ghost planes mapped, velocity rules applied)
+    int pfz0 = -1, pfz1 = -1;  // z face crossed by the plane in register set 0 / 1
+    // fetch plane gz into register set b (ghost planes mapped)
     auto fetch = [&](int gz, auto bset) {
         constexpr int b = decltype(bset)::value;
-        int fz;
-        const int sz = map_coord(gz, nz, c.bc[4], 4, fz);
-        const size_t base = (size_t)sz * plane;
-        const auto rr = plane_rsrc(in.r + base, pbytes), ru = plane_rsrc(in.u + base, pbytes);
-        const auto rv = plane_rsrc(in.v + base, pbytes), rw = plane_rsrc(in.w + base, pbytes);
+        int sz;
+        if constexpr (GEN) {
+            int fz;
+            sz = map_coord(gz, nz, c.bc[4], 4, fz);
+            if constexpr (b == 0) pfz0 = fz;
+            else pfz1 = fz;
+        } else {
+            sz = gz < 0 ? gz + nz : (gz >= nz ? gz - nz : gz);  // periodic z, nz >= 2
+        }
+        const PlaneAccess<WIDE, T> pa(in, sz, plane, pbytes, fbytes);
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
-            pr[b][i] = bload((T*)nullptr, rr, voff[i]);
-            pu[b][i] = bload((T*)nullptr, ru, voff[i]);
-            pv[b][i] = bload((T*)nullptr, rv, voff[i]);
-            pw[b][i] = bload((T*)nullptr, rw, voff[i]);
-        }
-        if constexpr (GEN) {
-            if (c.nonperiodic) {
-#pragma unroll
-                for (int i = 0; i < NL; ++i) {
-                    // faces crossed in x, then y, then z order
-                    if (sfx[i] >= 0) ghost_velocity(c, sfx[i], pu[b][i], pv[b][i], pw[b][i]);
-                    if (sfy[i] >= 0) ghost_velocity(c, sfy[i], pu[b][i], pv[b][i], pw[b][i]);
-                    if (fz >= 0) ghost_velocity(c, fz, pu[b][i], pv[b][i], pw[b][i]);
-                }
-            }
+            pr[b][i] = bload((T*)nullptr, pa.r, voff[i], pa.soff);
+            pu[b][i] = bload((T*)nullptr, pa.u, voff[i], pa.soff);
+            pv[b][i] = bload((T*)nullptr, pa.v, voff[i], pa.soff);
+            pw[b][i] = bload((T*)nullptr, pa.w, voff[i], pa.soff);
         }
     };
+    // register set b into LDS slot; the ghost velocity rules are applied here,
+    // when the loads have long arrived, rather than right after issuing them
     auto store = [&](auto slotc, auto bset) {
         constexpr int slot = decltype(slotc)::value;
         constexpr int b = decltype(bset)::value;
+        if constexpr (GEN) {
+            if (c.nonperiodic) {
+                const int fz = b == 0 ? pfz0 : pfz1;
+#pragma unroll
+                for (int i = 0; i < NL; ++i) {
+                    // faces crossed in x, then y, then z order
+                    if (sfx[i] >= 0) ghost(sfx[i], pu[b][i], pv[b][i], pw[b][i]);
+                    if (sfy[i] >= 0) ghost(sfy[i], pu[b][i], pv[b][i], pw[b][i]);
+                    if (fz >= 0) ghost(fz, pu[b][i], pv[b][i], pw[b][i]);
+                }
+            }
+        }
+        // A padding lane (q >= RXY) holds the value of position tid, which the
+        // same thread also writes as its element 0: it writes that value there
+        // again instead of branching around the store.
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
             const int q = tid + i * NT;
-            if ((i + 1) * NT <= RXY || q < RXY) {
-                sr[slot][q] = pr[b][i];
-                su[slot][q] = pu[b][i];
-                sv[slot][q] = pv[b][i];
-                sw[slot][q] = pw[b][i];
-            }
+            const int e = ((i + 1) * NT <= RXY || q < RXY) ? q : tid;
+            sr[slot][e] = pr[b][i];
+            su[slot][e] = pu[b][i];
+            sv[slot][e] = pv[b][i];
+            sw[slot][e] = pw[b][i];
         }
     };
     // drho' of the plane in slot S0 (below SD, above SU) on the tile + ring into sd[DS]
@@ -296,8 +358,20 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
         constexpr int J = decltype(jc)::value;
         constexpr int s0 = J, sU = (J + 1) & 3, s2 = (J + 2) & 3;
         using BS = std::integral_constant<int, J & 1>;
+        const size_t ob = (size_t)k * plane;
+        // two-phase: surface-tension force phi G_iso mu of this plane, loaded
+        // before the prefetch so that waiting for it leaves the prefetch in flight
+        T fst[3][RPT];
+        if constexpr (GEN) {
+            if (c.fst[0]) {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) fst[a][r] = c.fst[a][ob + oidx[r]];
+            }
+        }
         store(std::integral_constant<int, s2>{}, BS{});  // plane k+2 (its slot held plane k-2)
-        if (k + 4 <= z1 + 1) fetch(k + 4, BS{});
+        fetch(min(k + 4, z1 + 1), BS{});  // past the chunk: plane z1+1 again (cached)
         __syncthreads();
         const bool upper_ghost = (!zperiodic) && (k + 1 >= nz);
         if (!upper_ghost) ring(std::integral_constant<int, sU>{}, std::integral_constant<int, (J + 1) & 1>{});
@@ -309,9 +383,7 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
         const T* w0 = sw[s0];
         const T* dc = sd[J & 1];
         const T* dn = sd[(J + 1) & 1];
-        const size_t ob = (size_t)k * plane;
-        const auto orr = plane_rsrc(out.r + ob, pbytes), ou = plane_rsrc(out.u + ob, pbytes);
-        const auto ov = plane_rsrc(out.v + ob, pbytes), ow = plane_rsrc(out.w + ob, pbytes);
+        const PlaneAccess<WIDE, T> po(out, k, plane, pbytes, fbytes);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int ty = tyb + r * YS;
@@ -320,55 +392,52 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
             const T rc = r0[e], uc = u0[e], vc = v0[e], wc = w0[e];
             const T rnC = dc[dO];
             const T rn_next = upper_ghost ? rnC : dn[dO];
-            if (oact[r]) {
-                const T rE = r0[e + 1], rW = r0[e - 1], rN = r0[e + RX], rS = r0[e - RX];
-                const T rU = sr[sU][e], rD = r_prev[r];
-                const T uE = u0[e + 1], uW = u0[e - 1], uN = u0[e + RX], uS = u0[e - RX];
-                const T vE = v0[e + 1], vW = v0[e - 1], vN = v0[e + RX], vS = v0[e - RX];
-                const T wE = w0[e + 1], wW = w0[e - 1], wN = w0[e + RX], wS = w0[e - RX];
-                const T uU = su[sU][e], vU = sv[sU][e], wU = sw[sU][e];
-                const T uD = u_prev[r], vD = v_prev[r], wD = w_prev[r];
+            const T rE = r0[e + 1], rW = r0[e - 1], rN = r0[e + RX], rS = r0[e - RX];
+            const T rU = sr[sU][e], rD = r_prev[r];
+            const T uE = u0[e + 1], uW = u0[e - 1], uN = u0[e + RX], uS = u0[e - RX];
+            const T vE = v0[e + 1], vW = v0[e - 1], vN = v0[e + RX], vS = v0[e - RX];
+            const T wE = w0[e + 1], wW = w0[e - 1], wN = w0[e + RX], wS = w0[e - RX];
+            const T uU = su[sU][e], vU = sv[sU][e], wU = sw[sU][e];
+            const T uD = u_prev[r], vD = v_prev[r], wD = w_prev[r];
 
-                const T mxC = mom3<GEN>(rc, uc, rho0), myC = mom3<GEN>(rc, vc, rho0), mzC = mom3<GEN>(rc, wc, rho0);
-                const T mxE = mom3<GEN>(rE, uE, rho0), myE = mom3<GEN>(rE, vE, rho0), mzE = mom3<GEN>(rE, wE, rho0);
-                const T mxW = mom3<GEN>(rW, uW, rho0), myW = mom3<GEN>(rW, vW, rho0), mzW = mom3<GEN>(rW, wW, rho0);
-                const T mxN = mom3<GEN>(rN, uN, rho0), myN = mom3<GEN>(rN, vN, rho0), mzN = mom3<GEN>(rN, wN, rho0);
-                const T mxS = mom3<GEN>(rS, uS, rho0), myS = mom3<GEN>(rS, vS, rho0), mzS = mom3<GEN>(rS, wS, rho0);
-                const T mxU = mom3<GEN>(rU, uU, rho0), myU = mom3<GEN>(rU, vU, rho0), mzU = mom3<GEN>(rU, wU, rho0);
-                const T mxD = mom3<GEN>(rD, uD, rho0), myD = mom3<GEN>(rD, vD, rho0), mzD = mom3<GEN>(rD, wD, rho0);
+            const T mxC = mom3<GEN>(rc, uc, rho0), myC = mom3<GEN>(rc, vc, rho0), mzC = mom3<GEN>(rc, wc, rho0);
+            const T mxE = mom3<GEN>(rE, uE, rho0), myE = mom3<GEN>(rE, vE, rho0), mzE = mom3<GEN>(rE, wE, rho0);
+            const T mxW = mom3<GEN>(rW, uW, rho0), myW = mom3<GEN>(rW, vW, rho0), mzW = mom3<GEN>(rW, wW, rho0);
+            const T mxN = mom3<GEN>(rN, uN, rho0), myN = mom3<GEN>(rN, vN, rho0), mzN = mom3<GEN>(rN, wN, rho0);
+            const T mxS = mom3<GEN>(rS, uS, rho0), myS = mom3<GEN>(rS, vS, rho0), mzS = mom3<GEN>(rS, wS, rho0);
+            const T mxU = mom3<GEN>(rU, uU, rho0), myU = mom3<GEN>(rU, vU, rho0), mzU = mom3<GEN>(rU, wU, rho0);
+            const T mxD = mom3<GEN>(rD, uD, rho0), myD = mom3<GEN>(rD, vD, rho0), mzD = mom3<GEN>(rD, wD, rho0);
 
-                // centred differences of drho (pressure term and density SAT share them)
-                const T gxr = rE - rW, gyr = rN - rS, gzr = rU - rD;
-                const T fxx = fmaT(cs2, gxr, ((mxE * uE - mxW * uW) + (mxN * vN - mxS * vS)) + (mxU * wU - mxD * wD));
-                const T fyy = fmaT(cs2, gyr, ((myE * uE - myW * uW) + (myN * vN - myS * vS)) + (myU * wU - myD * wD));
-                const T fzz = fmaT(cs2, gzr, ((mzE * uE - mzW * uW) + (mzN * vN - mzS * vS)) + (mzU * wU - mzD * wD));
-                const T lpx = fmaT(T(-6), mxC, ((mxE + mxW) + (mxN + mxS)) + (mxU + mxD));
-                const T lpy = fmaT(T(-6), myC, ((myE + myW) + (myN + myS)) + (myU + myD));
-                const T lpz = fmaT(T(-6), mzC, ((mzE + mzW) + (mzN + mzS)) + (mzU + mzD));
-                const T sx = (dc[dO + 1] - dc[dO - 1]) - gxr;
-                const T sy = (dc[dO + DX] - dc[dO - DX]) - gyr;
-                const T sz = (rn_next - rn_prev[r]) - gzr;
-                const T rho_n = rho0 + rnC;
-                T gx_ = c.gdt[0];
-                if (c.fx) gx_ = fmaT(c.dt, c.fx[y0 + ty], gx_);
-                T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lpx, -c.cg * fxx)));
-                T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, lpy, -c.cg * fyy)));
-                T dmz = fmaT(rho_n, c.gdt[2], fmaT(-c.ks, sz, fmaT(c.kv, lpz, -c.cg * fzz)));
-                if constexpr (GEN) {
-                    if (c.fst[0]) {  // two-phase: surface-tension force -dt phi G_iso mu
-                        const size_t q = ob + ooff[r] / sizeof(T);
-                        dmx = fmaT(-c.dt, c.fst[0][q], dmx);
-                        dmy = fmaT(-c.dt, c.fst[1][q], dmy);
-                        dmz = fmaT(-c.dt, c.fst[2][q], dmz);
-                    }
+            // centred differences of drho (pressure term and density SAT share them)
+            const T gxr = rE - rW, gyr = rN - rS, gzr = rU - rD;
+            const T fxx = fmaT(cs2, gxr, ((mxE * uE - mxW * uW) + (mxN * vN - mxS * vS)) + (mxU * wU - mxD * wD));
+            const T fyy = fmaT(cs2, gyr, ((myE * uE - myW * uW) + (myN * vN - myS * vS)) + (myU * wU - myD * wD));
+            const T fzz = fmaT(cs2, gzr, ((mzE * uE - mzW * uW) + (mzN * vN - mzS * vS)) + (mzU * wU - mzD * wD));
+            const T lpx = fmaT(T(-6), mxC, ((mxE + mxW) + (mxN + mxS)) + (mxU + mxD));
+            const T lpy = fmaT(T(-6), myC, ((myE + myW) + (myN + myS)) + (myU + myD));
+            const T lpz = fmaT(T(-6), mzC, ((mzE + mzW) + (mzN + mzS)) + (mzU + mzD));
+            const T sx = (dc[dO + 1] - dc[dO - 1]) - gxr;
+            const T sy = (dc[dO + DX] - dc[dO - DX]) - gyr;
+            const T sz = (rn_next - rn_prev[r]) - gzr;
+            const T rho_n = rho0 + rnC;
+            T gx_ = c.gdt[0];
+            if (c.fx) gx_ = fmaT(c.dt, fxr[r], gx_);
+            T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lpx, -c.cg * fxx)));
+            T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, lpy, -c.cg * fyy)));
+            T dmz = fmaT(rho_n, c.gdt[2], fmaT(-c.ks, sz, fmaT(c.kv, lpz, -c.cg * fzz)));
+            if constexpr (GEN) {
+                if (c.fst[0]) {  // -dt phi G_iso mu
+                    dmx = fmaT(-c.dt, fst[0][r], dmx);
+                    dmy = fmaT(-c.dt, fst[1][r], dmy);
+                    dmz = fmaT(-c.dt, fst[2][r], dmz);
                 }
-                const T drn = rnC - rc;
-                const T inv = recipT(rho_n);
-                bstore(rnC, orr, ooff[r]);
-                bstore(fmaT(fmaT(-uc, drn, dmx), inv, uc), ou, ooff[r]);
-                bstore(fmaT(fmaT(-vc, drn, dmy), inv, vc), ov, ooff[r]);
-                bstore(fmaT(fmaT(-wc, drn, dmz), inv, wc), ow, ooff[r]);
             }
+            const T drn = rnC - rc;
+            const T inv = recipT(rho_n);
+            bstore(rnC, po.r, ooff[r], po.soff);
+            bstore(fmaT(fmaT(-uc, drn, dmx), inv, uc), po.u, ooff[r], po.soff);
+            bstore(fmaT(fmaT(-vc, drn, dmy), inv, vc), po.v, ooff[r], po.soff);
+            bstore(fmaT(fmaT(-wc, drn, dmz), inv, wc), po.w, ooff[r], po.soff);
             r_prev[r] = rc;
             u_prev[r] = uc;
             v_prev[r] = vc;
@@ -393,12 +462,17 @@ static hipError_t launch3d_variant(const Coef<T>& c, const State<T>& in, const S
                                    hipStream_t s)
 {
     const int nbx = (c.nx + TX - 1) / TX, nby = (c.ny + TY - 1) / TY, nbz = (c.nz + zc - 1) / zc;
-    const bool fast = !c.nonperiodic && c.rho0 == T(1) && !c.fst[0];
+    const bool fast = !c.nonperiodic && c.rho0 == T(1) && !c.fst[0] && c.nz >= 2;
+    const bool wide = (size_t)c.nx * c.ny * c.nz * sizeof(T) >= (size_t(1) << 31);
     const dim3 grid(nbx * nby * nbz), block(TX * TY / RPT);
-    if (fast)
-        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+    if (fast && !wide)
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false, false>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+    else if (fast)
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false, true>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+    else if (!wide)
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, false>), grid, block, 0, s, c, in, out, zc, nbx, nby);
     else
-        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, true>), grid, block, 0, s, c, in, out, zc, nbx, nby);
     return hipGetLastError();
 }
 

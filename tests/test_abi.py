@@ -66,6 +66,25 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu(mutate, expect):
     assert acm.lib().acm_last_error()
 
 
+@pytest.mark.parametrize("dims,precision,rejected", [
+    ((65536, 4096, 4), "f64", True),     # one z plane of 2 GiB
+    ((65536, 4096, 4), "f32", False),    # 1 GiB plane: passes validation
+    ((2048, 2048, 1024), "f32", True),   # 4.3e9 nodes
+])
+def test_init_grid_size_limits(dims, precision, rejected):
+    """Size limits are checked before anything touches the GPU; a grid that
+    passes them gets a handle (GPU present) or a HIP error (none), never
+    EINVAL.  acm_init launches nothing, so the placeholder field pointers are
+    never dereferenced."""
+    cfg = acm.make_config(3, *dims, nu=0.01, precision=precision, allow_unstable=True)
+    h = ctypes.c_void_p()
+    fa, fb = acm.Fields(1, 2, 3, 4, 5), acm.Fields(6, 7, 8, 9, 10)
+    st = acm.lib().acm_init(ctypes.byref(cfg), ctypes.byref(fa), ctypes.byref(fb), None, None, ctypes.byref(h))
+    if st == acm.OK:
+        acm.lib().acm_destroy(h)
+    assert (st == acm.EINVAL) == rejected, (st, acm.lib().acm_last_error())
+
+
 def test_init_rejects_missing_fields():
     cfg = acm.make_config(3, 8, 8, 8, nu=0.02)
     assert _init(cfg, a=acm.Fields(1, 2, 3, 0, 0)) == acm.EINVAL      # no w in 3D
