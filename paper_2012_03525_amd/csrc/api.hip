@@ -242,8 +242,8 @@ acm_status build_graph(acm_handle* h, int parity)
         e = launch_one(h, (parity + i) & 1, h->cap);
         if (e != hipSuccess) {
             hipGraph_t g = nullptr;
-            hipStreamEndCapture(h->cap, &g);
-            if (g) hipGraphDestroy(g);
+            (void)hipStreamEndCapture(h->cap, &g);
+            if (g) (void)hipGraphDestroy(g);
             return hip_fail(e, "kernel launch during capture");
         }
     }
@@ -251,7 +251,7 @@ acm_status build_graph(acm_handle* h, int parity)
     e = hipStreamEndCapture(h->cap, &g);
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&h->exec[parity], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         h->exec[parity] = nullptr;
         return hip_fail(e, "hipGraphInstantiate");
@@ -432,14 +432,14 @@ acm_status acm_set_current(acm_handle* h, int32_t which, int64_t step)
 void acm_destroy(acm_handle* h)
 {
     if (!h) return;
-    if (h->stream || h->cap) hipStreamSynchronize(h->stream);
+    if (h->stream || h->cap) (void)hipStreamSynchronize(h->stream);
     for (int p = 0; p < 2; ++p)
-        if (h->exec[p]) hipGraphExecDestroy(h->exec[p]);
-    if (h->partials) hipFree(h->partials);
-    if (h->result) hipFree(h->result);
-    if (h->host) hipHostFree(h->host);
-    if (h->scratch) hipFree(h->scratch);
-    if (h->cap) hipStreamDestroy(h->cap);
+        if (h->exec[p]) (void)hipGraphExecDestroy(h->exec[p]);
+    if (h->partials) (void)hipFree(h->partials);
+    if (h->result) (void)hipFree(h->result);
+    if (h->host) (void)hipHostFree(h->host);
+    if (h->scratch) (void)hipFree(h->scratch);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
 }
 

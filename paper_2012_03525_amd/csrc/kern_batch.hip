@@ -242,11 +242,11 @@ acm_status build_graph(acm_batch* b)
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return bfail(ACM_EHIP, std::string("batch capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
     }
     e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return bfail(ACM_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
     return ACM_OK;
 }
@@ -405,7 +405,8 @@ acm_status acm_batch_run(acm_batch* b, int32_t max_chunks, int32_t* active_left)
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) return bfail(ACM_EHIP, std::string("batch chunk: ") + hipGetErrorString(e));
         float ms = 0.f;
-        hipEventElapsedTime(&ms, b->ev_start, b->ev_chunk);
+        e = hipEventElapsedTime(&ms, b->ev_start, b->ev_chunk);
+        if (e != hipSuccess) return bfail(ACM_EHIP, std::string("batch timing: ") + hipGetErrorString(e));
         b->elapsed_ms = ms;
         b->lups += chunk_lups;
         for (int a = 0; a < nact; ++a) {
@@ -448,21 +449,21 @@ acm_status acm_batch_timing(const acm_batch* b, double* total_ms, int64_t* latti
 void acm_batch_destroy(acm_batch* b)
 {
     if (!b) return;
-    hipStreamSynchronize(b->stream);
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->cap) hipStreamDestroy(b->cap);
-    if (b->ev_start) hipEventDestroy(b->ev_start);
-    if (b->ev_chunk) hipEventDestroy(b->ev_chunk);
-    hipFree(b->dcases);
-    hipFree(b->ditems);
-    hipFree(b->dnitems);
-    hipFree(b->dqueue);
-    hipFree(b->dactive);
-    hipFree(b->dhealth);
-    if (b->hitems) hipHostFree(b->hitems);
-    if (b->hnitems) hipHostFree(b->hnitems);
-    if (b->hactive) hipHostFree(b->hactive);
-    if (b->hhealth) hipHostFree(b->hhealth);
+    (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+    if (b->ev_chunk) (void)hipEventDestroy(b->ev_chunk);
+    (void)hipFree(b->dcases);
+    (void)hipFree(b->ditems);
+    (void)hipFree(b->dnitems);
+    (void)hipFree(b->dqueue);
+    (void)hipFree(b->dactive);
+    (void)hipFree(b->dhealth);
+    if (b->hitems) (void)hipHostFree(b->hitems);
+    if (b->hnitems) (void)hipHostFree(b->hnitems);
+    if (b->hactive) (void)hipHostFree(b->hactive);
+    if (b->hhealth) (void)hipHostFree(b->hhealth);
     delete b;
 }
 
@@ -531,8 +532,8 @@ acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, 
             *best = t;
         }
     }
-    hipStreamSynchronize(s);
-    hipFree(mem);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(mem);
     return st;
 }
 }  // namespace

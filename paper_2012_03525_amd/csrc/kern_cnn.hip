@@ -1020,7 +1020,7 @@ acm_status acm_closure_set_network(acm_closure* h, int32_t enabled)
     if ((enabled != 0) != (h->use_net != 0)) {
         for (int p = 0; p < 2; ++p)
             if (h->exec[p]) {
-                hipGraphExecDestroy(h->exec[p]);
+                (void)hipGraphExecDestroy(h->exec[p]);
                 h->exec[p] = nullptr;
             }
     }
@@ -1040,11 +1040,11 @@ acm_status acm_closure_run(acm_closure* h, int64_t nsteps)
             hipGraph_t g = nullptr;
             const hipError_t e2 = hipStreamEndCapture(h->cap, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
-                if (g) hipGraphDestroy(g);
+                if (g) (void)hipGraphDestroy(g);
                 return chip(e != hipSuccess ? e : e2, "closure capture");
             }
             e = hipGraphInstantiate(&h->exec[p], g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             if (e != hipSuccess) return chip(e, "closure instantiate");
         }
         acm_status st = chip(hipGraphLaunch(h->exec[p], h->stream), "closure graph launch");
@@ -1072,10 +1072,10 @@ acm_status acm_closure_current(const acm_closure* h, int32_t* which, int64_t* st
 void acm_closure_destroy(acm_closure* h)
 {
     if (!h) return;
-    hipStreamSynchronize(h->stream);
+    (void)hipStreamSynchronize(h->stream);
     for (int p = 0; p < 2; ++p)
-        if (h->exec[p]) hipGraphExecDestroy(h->exec[p]);
-    if (h->cap) hipStreamDestroy(h->cap);
+        if (h->exec[p]) (void)hipGraphExecDestroy(h->exec[p]);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
 }
 
