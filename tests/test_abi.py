@@ -207,3 +207,24 @@ def test_loss_rejects_bad_output_scales_without_touching_the_gpu():
     for sc in ((0.0, 0.0, 0.0), (1.0, -1.0, 1.0), (1.0, float("nan"), 1.0), (float("inf"), 1.0, 1.0)):
         s = (ctypes.c_float * 3)(*sc)
         assert L.acm_cnn_loss(64, 64, 7 << 20, base, tgt, s, 8 << 20, 9 << 20, 10 << 20, None) == acm.EINVAL, sc
+
+
+def test_calibration_refinement_is_exact_on_band_limited_fields():
+    """The grid-convergence check of the closure experiment starts the finer
+    run from the Fourier interpolation of the fine initial field; the field
+    is band-limited (|k| <= 16), so the even nodes must reproduce it and the
+    odd nodes must match the analytic field between them."""
+    from paper_2012_03525_amd import inputs
+    from paper_2012_03525_amd.closure_experiment import _refine2
+    n = 64
+    st = inputs.random_spectrum_field(n, 5, 0.03, kmax=8)
+    r = _refine2(st, n)
+    for k in ("u", "v"):
+        assert r[k].shape == (2 * n, 2 * n)
+        assert np.abs(r[k][::2, ::2] - st[k]).max() < 1e-15
+    # a single mode sampled on both grids
+    x = 2 * math.pi * np.arange(n) / n
+    x2 = 2 * math.pi * np.arange(2 * n) / (2 * n)
+    f = {"u": np.sin(3 * x)[None, :] * np.cos(2 * x)[:, None]}
+    g = _refine2(f, n)["u"]
+    assert np.abs(g - np.sin(3 * x2)[None, :] * np.cos(2 * x2)[:, None]).max() < 1e-13
