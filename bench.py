@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the closure step timing in the default workload's line")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--batch-mode", type=int, default=0, choices=(0, 1),
+                    help="batch512: 0 one workgroup per item, 1 persistent work queue")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-only", action="store_true",
@@ -136,7 +138,7 @@ def measured_traffic(name):
 
 
 def run_batch(a, copy):
-    """The 512-case sweep in one batched persistent launch (FP32, autotuned
+    """The 512-case sweep, one batched launch per step (FP32, autotuned
     tiles, 500-step graph chunks): aggregate MLUPS over the whole job and the
     p50 / p99 case completion times."""
     import numpy as np
@@ -152,7 +154,7 @@ def run_batch(a, copy):
         cfgs.append(acm.make_config(2, c.n, c.n, nu=c.nu, precision="f32", bc=bc, wall_u=wu))
         states.append(c.state)
     print(f"[bench] batch: {len(cases)} cases, {sum(c.n * c.n for c in cases)} nodes", file=sys.stderr, flush=True)
-    b = acm.Batch(cfgs, states, [c.nsteps for c in cases], chunk=500)
+    b = acm.Batch(cfgs, states, [c.nsteps for c in cases], chunk=500, mode=a.batch_mode)
     b.run()
     ms, lups = b.timing()
     st = [b.status(i) for i in range(len(cases))]
@@ -167,13 +169,15 @@ def run_batch(a, copy):
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched sweep: 512 2D cases n in {32..256}, half periodic TGV / half lid-driven "
-                               "cavity, Re log-uniform [100, 5000], FP32, one persistent launch per 500-step chunk",
+                               "cavity, Re log-uniform [100, 5000], FP32, one launch per step, 500-step graph chunks",
+                   "launch": ["one workgroup per item", "persistent work queue"][a.batch_mode],
                    "cases": len(cases), "lattice_updates": int(lups), "parallelism": "single GPU"},
         "wall_ms": round(ms, 2),
         "case_completion_ms": {"p50": round(float(np.percentile(done, 50)), 2),
                                "p99": round(float(np.percentile(done, 99)), 2),
                                "finished": int(done.size), "diverged": diverged},
-        "roofline": {"bound": "hbm", "kernel": "batch_step_kernel", "achieved": round(gbs, 1),
+        "roofline": {"bound": "hbm", "kernel": ["batch_grid_kernel", "batch_step_kernel"][a.batch_mode],
+                     "achieved": round(gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_lup": 24, "copy_kernel_gbs": copy["gbs"]},
     }

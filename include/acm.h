@@ -173,8 +173,9 @@ const char* acm_last_error(void);
 /* Batched independent 2D cases (serving-style sweeps)                       */
 /* ------------------------------------------------------------------------ */
 /* Hundreds of independent single-phase 2D cases of uneven size advance
- * together: each step is ONE persistent launch whose workgroups pop
- * (case, tile) items from an atomic work queue and apply the same per-node
+ * together: each step is ONE launch over the active (case, tile) items,
+ * either persistent workgroups popping them from an atomic work queue or one
+ * workgroup per item (acm_batch_opts.mode), applying the same per-node
  * arithmetic as acm_step (results are bitwise equal to running each case
  * alone).  Steps are captured in HIP graphs of `chunk` steps; after every
  * chunk a health check retires cases that finished or diverged. */
@@ -192,9 +193,14 @@ typedef struct acm_batch_case {
 
 typedef struct acm_batch_opts {
     int32_t chunk;         /* steps per captured graph, even; 0 = 500        */
-    int32_t blocks;        /* persistent workgroups; 0 = CUs x occupancy     */
-    int32_t grab;          /* queue items taken per atomic; 0 = 4            */
+    int32_t blocks;        /* mode 1: persistent workgroups; 0 = CUs x
+                              occupancy                                      */
+    int32_t grab;          /* mode 1: queue items taken per atomic; 0 = 4    */
     double umax_limit;     /* max |u| above this marks divergence; 0 = 0.3   */
+    int32_t mode;          /* 0: one workgroup per (case, tile) item,
+                              launched over the item capacity; 1: persistent
+                              workgroups popping the work queue (blocks,
+                              grab).  Results do not depend on the mode.     */
 } acm_batch_opts;
 
 typedef struct acm_batch_case_status {
@@ -226,7 +232,8 @@ acm_status acm_batch_timing(const acm_batch* b, double* total_ms, int64_t* latti
 void acm_batch_destroy(acm_batch* b);
 
 /* Tile autotuner: time `copies` periodic n x n cases for `steps` steps with
- * every 2D tile variant (0..5) through the batched kernel; ms_per_tile[6]
+ * every 2D tile variant (0..5) through the batched kernel (mode 0; batches
+ * in mode 1 tune through their own mode); ms_per_tile[6]
  * receives ms per step, *best the fastest variant.  Allocates and frees its
  * own scratch fields.  The choice changes only speed, never results. */
 acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int32_t steps, void* stream,

@@ -60,7 +60,7 @@ class BatchCase(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("blocks", ctypes.c_int32), ("grab", ctypes.c_int32),
-                ("umax_limit", ctypes.c_double)]
+                ("umax_limit", ctypes.c_double), ("mode", ctypes.c_int32)]
 
 
 class BatchCaseStatus(ctypes.Structure):
@@ -299,11 +299,12 @@ BATCH_RUNNING, BATCH_FINISHED, BATCH_DIVERGED = 0, 1, 2
 
 class Batch:
     """Independent 2D single-phase cases advanced together by the batched
-    persistent kernel.  All states live in one arena tensor (6 fields per
-    case: set a then set b), sliced into per-case views."""
+    kernel (mode 0: one workgroup per item; 1: persistent work queue).  All
+    states live in one arena tensor (6 fields per case: set a then set b),
+    sliced into per-case views."""
 
     def __init__(self, cfgs, states, nsteps, tiles=None, chunk: int = 500, device: str = "cuda:0",
-                 umax_limit: float = 0.3, grab: int = 0, blocks: int = 0):
+                 umax_limit: float = 0.3, grab: int = 0, blocks: int = 0, mode: int = 0):
         import torch
         self.torch = torch
         n = len(cfgs)
@@ -328,7 +329,7 @@ class Batch:
             bc.nsteps = int(nsteps[i])
             bc.tile = -1 if tiles is None else int(tiles[i])
         self._cases = arr
-        opts = BatchOpts(chunk, blocks, grab, umax_limit)
+        opts = BatchOpts(chunk, blocks, grab, umax_limit, mode)
         self.stream = torch.cuda.current_stream()
         h = ctypes.c_void_p()
         check(lib().acm_batch_init(arr, n, ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),

@@ -1,10 +1,15 @@
-// Batched independent 2D cases in one persistent launch per step.
+// Batched independent 2D cases in one launch per step.
 //
-// Every active (case, tile) pair is an item of a device table; a persistent
-// grid (CUs x occupancy workgroups) pops items `grab` at a time from an
-// atomic counter and runs the same tile function as the single-case kernel
-// (tile2d.h), so each case's result is bitwise equal to running it alone.
-// The last workgroup to finish resets the counter for the next launch.  A
+// Every active (case, tile) pair is an item of a device table.  Mode 0
+// (default): one workgroup per item slot (the item capacity), slots past the
+// active count exit at once, and the hardware dispatcher keeps as many items
+// in flight as occupancy allows.  Mode 1: a persistent grid (CUs x occupancy
+// workgroups) pops items `grab` at a time from an atomic counter; the last
+// workgroup to finish resets the counter for the next launch.  A persistent
+// workgroup waits out each item's load latency in turn, which the dispatcher
+// hides in mode 0 (1.5x faster on the 512-case sweep).  Both run
+// the same tile function as the single-case kernel (tile2d.h), so each
+// case's result is bitwise equal to running it alone.  A
 // chunk of steps is captured once as a HIP graph (the item table and its
 // length live in device memory, so the graph survives changes of the active
 // set); after each chunk a health kernel reduces max|u| and a non-finite
@@ -52,6 +57,21 @@ constexpr size_t batch_lds_bytes()
     return m;
 }
 
+// the tile function of one item (the case's tile variant)
+template <typename T>
+__device__ __forceinline__ void batch_item(const BatchCaseDev<T>& bc, int4 it, int parity, char* smem)
+{
+    const State<T> in = bc.s[parity], out = bc.s[parity ^ 1];
+    switch (bc.tile) {
+        case 1: tile2d<T, 32, 8, 256>(bc.c, in, out, it.y * 32, it.z * 8, smem); break;
+        case 2: tile2d<T, 64, 8, 256>(bc.c, in, out, it.y * 64, it.z * 8, smem); break;
+        case 3: tile2d<T, 16, 16, 256>(bc.c, in, out, it.y * 16, it.z * 16, smem); break;
+        case 4: tile2d<T, 128, 4, 256>(bc.c, in, out, it.y * 128, it.z * 4, smem); break;
+        case 5: tile2d<T, 32, 16, 256>(bc.c, in, out, it.y * 32, it.z * 16, smem); break;
+        default: tile2d<T, 64, 4, 256>(bc.c, in, out, it.y * 64, it.z * 4, smem); break;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void batch_step_kernel(const BatchCaseDev<T>* __restrict__ cases,
                                                           const int4* __restrict__ items,
@@ -70,16 +90,7 @@ __global__ __launch_bounds__(256) void batch_step_kernel(const BatchCaseDev<T>* 
         const int last = min(first + grab, n);
         for (int t = first; t < last; ++t) {
             const int4 it = items[t];
-            const BatchCaseDev<T>& bc = cases[it.x];
-            const State<T> in = bc.s[parity], out = bc.s[parity ^ 1];
-            switch (bc.tile) {
-                case 1: tile2d<T, 32, 8, 256>(bc.c, in, out, it.y * 32, it.z * 8, smem); break;
-                case 2: tile2d<T, 64, 8, 256>(bc.c, in, out, it.y * 64, it.z * 8, smem); break;
-                case 3: tile2d<T, 16, 16, 256>(bc.c, in, out, it.y * 16, it.z * 16, smem); break;
-                case 4: tile2d<T, 128, 4, 256>(bc.c, in, out, it.y * 128, it.z * 4, smem); break;
-                case 5: tile2d<T, 32, 16, 256>(bc.c, in, out, it.y * 32, it.z * 16, smem); break;
-                default: tile2d<T, 64, 4, 256>(bc.c, in, out, it.y * 64, it.z * 4, smem); break;
-            }
+            batch_item<T>(cases[it.x], it, parity, smem);
             __syncthreads();  // the next item reuses the LDS tile
         }
     }
@@ -90,6 +101,19 @@ __global__ __launch_bounds__(256) void batch_step_kernel(const BatchCaseDev<T>* 
             queue[1] = 0;
         }
     }
+}
+
+// Mode 0: workgroup b runs item b; slots past the active count exit.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_grid_kernel(const BatchCaseDev<T>* __restrict__ cases,
+                                                          const int4* __restrict__ items,
+                                                          const int* __restrict__ nitems, int parity)
+{
+    __shared__ __align__(16) char smem[batch_lds_bytes<T>()];
+    const int t = blockIdx.x;
+    if (t >= *nitems) return;
+    const int4 it = items[t];
+    batch_item<T>(cases[it.x], it, parity, smem);
 }
 
 // One workgroup per active case: max |u| and a non-finite flag.
@@ -155,6 +179,7 @@ struct acm_batch {
     int chunk = 500;
     int blocks = 0;
     int grab = 4;
+    int mode = 0;   // 0 one workgroup per item, 1 persistent work queue
     double umax_limit = 0.3;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
@@ -201,9 +226,13 @@ hipError_t upload_cases(acm_batch* b, const acm_batch_case* cases)
 template <typename T>
 hipError_t launch_batch_step(acm_batch* b, int parity, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_step_kernel<T>), dim3(b->blocks), dim3(256), 0, s,
-                       static_cast<const BatchCaseDev<T>*>(b->dcases), b->ditems, b->dnitems, b->dqueue, parity,
-                       b->grab);
+    if (b->mode == 0)
+        hipLaunchKernelGGL((batch_grid_kernel<T>), dim3((unsigned)std::max<size_t>(1, b->max_items)), dim3(256), 0,
+                           s, static_cast<const BatchCaseDev<T>*>(b->dcases), b->ditems, b->dnitems, parity);
+    else
+        hipLaunchKernelGGL((batch_step_kernel<T>), dim3(b->blocks), dim3(256), 0, s,
+                           static_cast<const BatchCaseDev<T>*>(b->dcases), b->ditems, b->dnitems, b->dqueue,
+                           parity, b->grab);
     return hipGetLastError();
 }
 
@@ -228,7 +257,7 @@ int occupancy_blocks()
 // Tile variants chosen by the autotuner, per (nx, ny, precision), for the
 // life of the process.
 std::mutex g_tune_mutex;
-std::map<std::tuple<int, int, int>, int> g_tune_cache;
+std::map<std::tuple<int, int, int, int>, int> g_tune_cache;  // (nx, ny, precision, mode) -> tile
 
 acm_status build_graph(acm_batch* b)
 {
@@ -255,7 +284,7 @@ acm_status build_graph(acm_batch* b)
 
 namespace {
 acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, void* stream, double* ms_per_tile,
-                          int32_t* best);
+                          int32_t* best, int mode);
 }
 
 extern "C" {
@@ -269,6 +298,8 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
     const int prec = cases[0].cfg.precision;
     const int chunk = (opts && opts->chunk > 0) ? opts->chunk : 500;
     if (chunk % 2) return bfail(ACM_EINVAL, "chunk must be even");
+    if (opts && opts->mode != 0 && opts->mode != 1) return bfail(ACM_EINVAL, "mode must be 0 or 1");
+    const int mode = opts ? opts->mode : 0;
     for (int i = 0; i < ncases; ++i) {
         const acm_batch_case& k = cases[i];
         std::string err;
@@ -287,7 +318,7 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
     for (int i = 0; i < ncases; ++i) {
         tiles[i] = cases[i].tile;
         if (tiles[i] >= 0) continue;
-        const auto key = std::make_tuple((int)cases[i].cfg.nx, (int)cases[i].cfg.ny, (int)prec);
+        const auto key = std::make_tuple((int)cases[i].cfg.nx, (int)cases[i].cfg.ny, (int)prec, mode);
         {
             std::lock_guard<std::mutex> lock(g_tune_mutex);
             const auto it = g_tune_cache.find(key);
@@ -300,7 +331,8 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
         int32_t best = 0;
         const int nxy = cases[i].cfg.nx * cases[i].cfg.ny;
         const int copies = std::min(1024, std::max(1, (1 << 22) / nxy));  // about 4 M nodes
-        const acm_status st = autotune_shape(cases[i].cfg.nx, cases[i].cfg.ny, prec, copies, 20, stream, ms, &best);
+        const acm_status st =
+            autotune_shape(cases[i].cfg.nx, cases[i].cfg.ny, prec, copies, 20, stream, ms, &best, mode);
         if (st != ACM_OK) return st;
         std::lock_guard<std::mutex> lock(g_tune_mutex);
         g_tune_cache[key] = best;
@@ -312,6 +344,7 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
     b->precision = prec;
     b->chunk = chunk;
     b->grab = (opts && opts->grab > 0) ? opts->grab : 4;
+    b->mode = mode;
     b->umax_limit = (opts && opts->umax_limit > 0) ? opts->umax_limit : 0.3;
     b->stream = static_cast<hipStream_t>(stream);
     b->tile.resize(ncases);
@@ -473,14 +506,14 @@ acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int3
     if (n < 4 || copies <= 0 || steps <= 0 || steps % 2 || !ms_per_tile || !best)
         return bfail(ACM_EINVAL, "autotune: bad arguments");
     if (precision != ACM_F32 && precision != ACM_F64) return bfail(ACM_EINVAL, "autotune: precision");
-    return autotune_shape(n, n, precision, copies, steps, stream, ms_per_tile, best);
+    return autotune_shape(n, n, precision, copies, steps, stream, ms_per_tile, best, 0);
 }
 
 }  // extern "C"
 
 namespace {
 acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, void* stream, double* ms_per_tile,
-                          int32_t* best)
+                          int32_t* best, int mode)
 {
     const size_t es = precision == ACM_F64 ? 8 : 4;
     const size_t field = (size_t)nx * ny * es;
@@ -515,6 +548,7 @@ acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, 
         for (auto& k : cs) k.tile = t;
         acm_batch_opts o{};
         o.chunk = steps;
+        o.mode = mode;
         acm_batch* b = nullptr;
         st = acm_batch_init(cs.data(), copies, &o, stream, &b);
         if (st != ACM_OK) break;

@@ -177,6 +177,8 @@ def test_batch_init_rejects_bad_cases_without_touching_the_gpu():
     bad = acm.BatchOpts(21, 0, 0, 0.0)
     arr[1].tile = 0
     assert acm.lib().acm_batch_init(arr, n, ctypes.byref(bad), None, ctypes.byref(h)) == acm.EINVAL
+    bad_mode = acm.BatchOpts(20, 0, 0, 0.0, 2)                   # launch mode must be 0 or 1
+    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(bad_mode), None, ctypes.byref(h)) == acm.EINVAL
 
 
 def test_fused_correction_rejects_bad_arguments_without_touching_the_gpu():

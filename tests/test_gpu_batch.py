@@ -1,4 +1,4 @@
-"""Batched persistent launch: every case must be bitwise equal to the same
+"""Batched launch (both modes): every case must be bitwise equal to the same
 case run alone through acm_run, divergence must be isolated to its case,
 and sampled cases of the 512-case sweep must match the CPU oracle."""
 import math
@@ -55,10 +55,11 @@ def spec_state(nx, ny, seed):
     return f32(inputs.seeded_state((ny, nx), seed=seed, scale_u=0.03, scale_r=1e-3))
 
 
-def test_batch_bitwise_equals_single_runs(acm_mod):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_bitwise_equals_single_runs(acm_mod, mode):
     cfgs = [case_cfg(acm_mod, nx, ny, kind, 0.04) for nx, ny, kind, _, _ in SPECS]
     states = [spec_state(nx, ny, 100 + i) for i, (nx, ny, _, _, _) in enumerate(SPECS)]
-    b = acm_mod.Batch(cfgs, states, [s[4] for s in SPECS], tiles=[s[3] for s in SPECS], chunk=20)
+    b = acm_mod.Batch(cfgs, states, [s[4] for s in SPECS], tiles=[s[3] for s in SPECS], chunk=20, mode=mode)
     left = b.run()
     assert left == 0
     for i, (nx, ny, kind, tile, nsteps) in enumerate(SPECS):
@@ -77,14 +78,15 @@ def test_batch_bitwise_equals_single_runs(acm_mod):
     b.close()
 
 
-def test_batch_divergence_is_isolated(acm_mod):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_divergence_is_isolated(acm_mod, mode):
     """A linearly unstable case (nu above the viscous bound, allowed
     explicitly) is retired as diverged; the others finish bitwise equal to
     their single runs."""
     cfgs = [case_cfg(acm_mod, 40, 40, "tgv", 0.04), case_cfg(acm_mod, 40, 40, "tgv", 0.45, allow_unstable=True),
             case_cfg(acm_mod, 48, 32, "cavity", 0.04)]
     states = [spec_state(40, 40, 1), spec_state(40, 40, 2), spec_state(48, 32, 3)]
-    b = acm_mod.Batch(cfgs, states, [400, 400, 400], chunk=20, umax_limit=0.3)
+    b = acm_mod.Batch(cfgs, states, [400, 400, 400], chunk=20, umax_limit=0.3, mode=mode)
     assert b.run() == 0
     assert b.status(1)["state"] == acm_mod.BATCH_DIVERGED
     assert b.status(1)["steps_done"] < 400
