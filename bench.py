@@ -193,6 +193,7 @@ def closure_timing(steps: int = 2000):
     return {"fine_1024_x4_us": round(t["fine_steps_per_coarse_step_us"], 2),
             "closure_256_step_us": round(t["closure_step_us"], 2),
             "plain_coarse_256_step_us": round(t["plain_coarse_step_us"], 2),
+            "closure_256_two_launch_step_us": round(t["closure_separate_launch_step_us"], 2),
             "speedup_vs_fine": round(t["fine_steps_per_coarse_step_us"] / t["closure_step_us"], 3)}
 
 

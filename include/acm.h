@@ -323,18 +323,22 @@ acm_status acm_cnn_correct(int32_t nx, int32_t ny, const acm_fields* in, const a
                            const void* const* weights, const float* const* biases, const float* in_scale,
                            const float* out_scale, void* stream);
 
-/* Closure inference: every coarse step runs the SMAME step into the
- * workspace, then acm_cnn_correct into the other buffer set, captured in HIP
- * graphs of `chunk` steps (even; 0 = 100).  weights/biases as for
- * acm_cnn_correct.  workspace: acm_closure_workspace bytes of device memory
- * (the uncorrected state).  Grids need nx, ny multiples of 16. */
+/* Closure inference: every coarse step is the SMAME step followed by the
+ * network correction into the other buffer set, captured in HIP graphs of
+ * `chunk` steps (even; 0 = 100).  On fully periodic grids both run in one
+ * launch (the correction kernel performs the step on its tiles); otherwise
+ * the step writes the workspace and acm_cnn_correct follows.  weights/biases
+ * as for acm_cnn_correct.  workspace: acm_closure_workspace bytes of device
+ * memory (the uncorrected state).  Grids need nx, ny multiples of 16. */
 typedef struct acm_closure acm_closure;
 size_t acm_closure_workspace(int32_t nx, int32_t ny);
 acm_status acm_closure_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b, const void* force_x,
                             const void* const* weights, const float* const* biases, const float* in_scale,
                             const float* out_scale, void* workspace, int32_t chunk, void* stream,
                             acm_closure** out);
-/* 0: plain coarse steps (the network is skipped), 1: corrected steps. */
+/* 0: plain coarse steps (the network is skipped), 1: corrected steps,
+ * 2: corrected steps with the SMAME step always launched on its own
+ * (identical results; for checking and timing).  Other values: ACM_EINVAL. */
 acm_status acm_closure_set_network(acm_closure* h, int32_t enabled);
 acm_status acm_closure_run(acm_closure* h, int64_t nsteps);
 acm_status acm_closure_current(const acm_closure* h, int32_t* which, int64_t* step);

@@ -338,7 +338,8 @@ class ClosureRun:
     of state buffers, with a monitor handle on the same buffers for the
     gate diagnostics."""
 
-    def __init__(self, spec: FlowSpec, net: Optional[Network], state_coarse: Dict[str, "object"], chunk: int = 100):
+    def __init__(self, spec: FlowSpec, net: Optional[Network], state_coarse: Dict[str, "object"], chunk: int = 100,
+                 separate_step: bool = False):
         import torch
         self.torch = torch
         self.spec = spec
@@ -363,6 +364,8 @@ class ClosureRun:
         self.h = h
         if net is None:
             acm.check(acm.lib().acm_closure_set_network(self.h, 0))
+        elif separate_step:  # step kernel, then correction kernel (same results)
+            acm.check(acm.lib().acm_closure_set_network(self.h, 2))
         self.mon = acm.Solver(cfg, None, tensors=self.sets, force_x=spec.coarse_force())
 
     def current(self):

@@ -92,8 +92,9 @@ def run_experiment(preset: str = "full", log=print, train_seeds=None, eval_seeds
 
 def step_timing(preset: str = "full", steps: int = 2000, log=print):
     """Per-step wall time of plain fine steps and of closure steps (SMAME
-    step + fused network correction, graph-launched) on the preset's grids;
-    the network weights do not change the cost, so they are untrained."""
+    step + fused network correction, graph-launched; in one launch and as two
+    launches) on the preset's grids; the network weights do not change the
+    cost, so they are untrained."""
     import ctypes
     import torch
     spec = closure.FlowSpec(**PRESETS[preset]["spec"])
@@ -109,9 +110,10 @@ def step_timing(preset: str = "full", steps: int = 2000, log=print):
     closure.filter_to(f.tensors(), c0, spec, ctypes.c_void_p(f.stream.cuda_stream))
     f.close()
     out = {"fine_step_us": t_fine * 1e6, "fine_steps_per_coarse_step_us": spec.ratio * t_fine * 1e6}
-    for name, net in (("closure_step_us", closure.Network(*shape, seed=0, out_scale=[0.0, 1e-6, 1e-6])),
-                      ("plain_coarse_step_us", None)):
-        run = closure.ClosureRun(spec, net, c0)
+    net = closure.Network(*shape, seed=0, out_scale=[0.0, 1e-6, 1e-6])
+    for name, n_, sep in (("closure_step_us", net, False), ("closure_separate_launch_step_us", net, True),
+                          ("plain_coarse_step_us", None, False)):
+        run = closure.ClosureRun(spec, n_, c0, separate_step=sep)
         run.run(200)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -24,6 +24,7 @@
 
 #include "../../include/acm.h"
 #include "acm_internal.h"
+#include "tile2d.h"
 
 namespace acm {
 
@@ -480,7 +481,7 @@ __device__ __forceinline__ uint2 pack4(float a, float b, float c, float d)
 template <int SO, int NH, bool LAST>
 __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const float* __restrict__ bias,
                                         const bf16_t* __restrict__ in, bf16_t* __restrict__ out, const Args& a,
-                                        int gx0, int gy0, int H, int W)
+                                        int gx0, int gy0, int H, int W, const float* sq = nullptr)
 {
     constexpr int SN = SO + 2, NP = SO * SO, NG = (NP + 15) / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -510,8 +511,11 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
                 const int py = p / SO, px = p - py * SO;
                 const size_t o = (size_t)(gy0 + py) * W + (gx0 + px);
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    a.qo[c][o] = a.d[c] != 0.f ? fmaf(a.d[c], acc[0][c] + bb[0][c], a.qi[c][o]) : a.qi[c][o];
+                for (int c = 0; c < 3; ++c) {
+                    // the uncorrected state: from LDS when the kernel ran the step itself
+                    const float q = sq ? sq[c * T * T + p] : a.qi[c][o];
+                    a.qo[c][o] = a.d[c] != 0.f ? fmaf(a.d[c], acc[0][c] + bb[0][c], q) : q;
+                }
             }
         }
     };
@@ -557,9 +561,22 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
     }
 }
 
-__global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a)
+// STEP: the kernel first runs the SMAME step itself (fully periodic grids):
+// it stages the state before the step on the (SI + 4)^2 region in the space
+// of buffer A, forms drho' on the (SI + 2)^2 ring, and the momentum update on
+// the SI^2 input region of layer 0, with the same per-node functions as the
+// step kernels (tile2d.h), so the result equals a step launch followed by
+// the correction launch bit for bit.  The tile's own uncorrected values stay
+// in LDS for the epilogue.
+constexpr int RS = SI + 4, NRS = RS * RS;  // staged state region (30^2)
+constexpr int DS = SI + 2, NDS = DS * DS;  // drho' region (28^2)
+static_assert((3 * NRS + NDS) * 4 <= BA * 2, "step staging fits in buffer A");
+constexpr int SQ_HALF = 3 * T * T * 2;     // centre values, FP32, in halfwords
+
+template <bool STEP>
+__global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a, Coef<float> cf, State<float> qs)
 {
-    __shared__ __align__(16) bf16_t lds[LDS_HALF];
+    __shared__ __align__(16) bf16_t lds[LDS_HALF + (STEP ? SQ_HALF : 0)];
     bf16_t* const sw = lds;
     bf16_t* const sa = lds + WTOT;
     bf16_t* const sb = sa + BA;
@@ -589,15 +606,20 @@ __global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a)
         w0v[i] = k < 27 ? a.w[0][((k / 3) * 32 + o) * 16 + (k % 3)] : bf16_t(0);
     }
     constexpr int NI = SI * SI, II = (NI + NT - 1) / NT;
-    float q0[II], q1[II], q2[II];
+    constexpr int NQ = STEP ? NRS : NI, IQ = (NQ + NT - 1) / NT;
+    constexpr int QS = STEP ? RS : SI, QH = STEP ? 7 : 5;  // staged side and halo
+    const float* const q0p = STEP ? qs.r : a.qi[0];
+    const float* const q1p = STEP ? qs.u : a.qi[1];
+    const float* const q2p = STEP ? qs.v : a.qi[2];
+    float q0[IQ], q1[IQ], q2[IQ];
 #pragma unroll
-    for (int i = 0; i < II; ++i) {
-        const int e = min(tid + i * NT, NI - 1);
-        const int r = e / SI, c = e - r * SI;
-        const size_t src = (size_t)wrap(gy0 - 5 + r, H) * W + wrap(gx0 - 5 + c, W);
-        q0[i] = a.qi[0][src];
-        q1[i] = a.qi[1][src];
-        q2[i] = a.qi[2][src];
+    for (int i = 0; i < IQ; ++i) {
+        const int e = min(tid + i * NT, NQ - 1);
+        const int r = e / QS, c = e - r * QS;
+        const size_t src = (size_t)wrap(gy0 - QH + r, H) * W + wrap(gx0 - QH + c, W);
+        q0[i] = q0p[src];
+        q1[i] = q1p[src];
+        q2[i] = q2p[src];
     }
 #pragma unroll
     for (int l = 0; l < 3; ++l)
@@ -609,11 +631,47 @@ __global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a)
         if (tid + i * NT < NV4) reinterpret_cast<uint4*>(sw + OW4)[tid + i * NT] = wv4[i];
 #pragma unroll
     for (int i = 0; i < I0; ++i) sw[tid + i * NT] = w0v[i];
+    if constexpr (STEP) {
+        float* const sr = reinterpret_cast<float*>(sa);
+        float* const su = sr + NRS;
+        float* const sv = su + NRS;
+        float* const srn = sv + NRS;
+        float* const sq = reinterpret_cast<float*>(lds + LDS_HALF);
 #pragma unroll
-    for (int i = 0; i < II; ++i) {
-        const int e = tid + i * NT;
-        if (e < NI)
-            *reinterpret_cast<uint2*>(sb + 4 * e) = pack4(q0[i] * a.s[0], q1[i] * a.s[1], q2[i] * a.s[2], 0.f);
+        for (int i = 0; i < IQ; ++i) {
+            const int e = tid + i * NT;
+            if (e < NRS) {
+                sr[e] = q0[i];
+                su[e] = q1[i];
+                sv[e] = q2[i];
+            }
+        }
+        __syncthreads();
+        for (int q = tid; q < NDS; q += NT) {
+            const int ly = q / DS, lx = q - ly * DS;
+            srn[q] = rho_new_2d<float, RS>(cf, sr, su, sv, (ly + 1) * RS + (lx + 1));
+        }
+        __syncthreads();
+        for (int q = tid; q < NI; q += NT) {
+            const int ly = q / SI, lx = q - ly * SI;
+            float rn, un, vn;
+            momentum_node2d<float, RS, DS>(cf, sr, su, sv, srn, (ly + 2) * RS + (lx + 2), (ly + 1) * DS + (lx + 1),
+                                           wrap(gy0 - 5 + ly, H), rn, un, vn);
+            *reinterpret_cast<uint2*>(sb + 4 * q) = pack4(rn * a.s[0], un * a.s[1], vn * a.s[2], 0.f);
+            const int cy = ly - 5, cx = lx - 5;
+            if (cy >= 0 && cy < T && cx >= 0 && cx < T) {
+                sq[cy * T + cx] = rn;
+                sq[T * T + cy * T + cx] = un;
+                sq[2 * T * T + cy * T + cx] = vn;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < IQ; ++i) {
+            const int e = tid + i * NT;
+            if (e < NI)
+                *reinterpret_cast<uint2*>(sb + 4 * e) = pack4(q0[i] * a.s[0], q1[i] * a.s[1], q2[i] * a.s[2], 0.f);
+        }
     }
     __syncthreads();
 
@@ -660,15 +718,27 @@ __global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a)
     layer32<S1 - 4, 2, false>(sw + OW3, a.b[3], sa, sb, a, gx0, gy0, H, W);
     __syncthreads();
     // last layer: output side 16 = the tile; (gx0, gy0) is its origin
-    layer32<T, 1, true>(sw + OW4, a.b[4], sb, nullptr, a, gx0, gy0, H, W);
+    layer32<T, 1, true>(sw + OW4, a.b[4], sb, nullptr, a, gx0, gy0, H, W,
+                        STEP ? reinterpret_cast<const float*>(lds + LDS_HALF) : nullptr);
 }
 }  // namespace fused
 
 hipError_t launch_fused(int H, int W, const fused::Args& a, hipStream_t s)
 {
     if (H % fused::T || W % fused::T) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fused::cnn_fused_kernel, dim3((W / fused::T) * (H / fused::T)), dim3(fused::NT), 0, s, H, W,
-                       a);
+    hipLaunchKernelGGL(fused::cnn_fused_kernel<false>, dim3((W / fused::T) * (H / fused::T)), dim3(fused::NT), 0, s,
+                       H, W, a, Coef<float>{}, State<float>{});
+    return hipGetLastError();
+}
+
+// SMAME step of the state qs and the correction in one launch (fully
+// periodic grids); a.qi is not read.
+hipError_t launch_fused_step(int H, int W, const fused::Args& a, const Coef<float>& c, const State<float>& qs,
+                             hipStream_t s)
+{
+    if (H % fused::T || W % fused::T || c.nonperiodic) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fused::cnn_fused_kernel<true>, dim3((W / fused::T) * (H / fused::T)), dim3(fused::NT), 0, s,
+                       H, W, a, c, qs);
     return hipGetLastError();
 }
 
@@ -887,6 +957,7 @@ struct acm_closure {
     int which = 0;
     int64_t step = 0;
     int use_net = 1;
+    int two_launch = 0;  // 1: step kernel then correction kernel even on periodic grids
     Coef<float> coef;
 };
 
@@ -920,10 +991,12 @@ hipError_t closure_step(acm_closure* h, int from, hipStream_t s)
     const State<float> so{static_cast<float*>(out.drho), static_cast<float*>(out.u), static_cast<float*>(out.v),
                           nullptr, nullptr};
     if (!h->use_net) return launch_step2d<float>(h->coef, si, so, h->cfg.tile, s);
+    float* const qo[3] = {so.r, so.u, so.v};
+    if (!h->coef.nonperiodic && !h->two_launch)  // step and correction in one launch
+        return launch_fused_step(h->cfg.ny, h->cfg.nx, fused_args(h, h->tmp, qo), h->coef, si, s);
     const State<float> st{h->tmp[0], h->tmp[1], h->tmp[2], nullptr, nullptr};
     hipError_t e = launch_step2d<float>(h->coef, si, st, h->cfg.tile, s);
     if (e != hipSuccess) return e;
-    float* const qo[3] = {so.r, so.u, so.v};
     return launch_fused(h->cfg.ny, h->cfg.nx, fused_args(h, h->tmp, qo), s);
 }
 
@@ -1017,14 +1090,17 @@ acm_status acm_closure_init(const acm_config* cfg, const acm_fields* a, const ac
 acm_status acm_closure_set_network(acm_closure* h, int32_t enabled)
 {
     if (!h) return cfail(ACM_EINVAL, "closure is NULL");
-    if ((enabled != 0) != (h->use_net != 0)) {
+    if (enabled < 0 || enabled > 2) return cfail(ACM_EINVAL, "enabled must be 0, 1 or 2");
+    const int use_net = enabled ? 1 : 0, two_launch = enabled == 2 ? 1 : 0;
+    if (use_net != h->use_net || two_launch != h->two_launch) {  // the captured graphs are stale
         for (int p = 0; p < 2; ++p)
             if (h->exec[p]) {
                 (void)hipGraphExecDestroy(h->exec[p]);
                 h->exec[p] = nullptr;
             }
     }
-    h->use_net = enabled ? 1 : 0;
+    h->use_net = use_net;
+    h->two_launch = two_launch;
     return ACM_OK;
 }
 

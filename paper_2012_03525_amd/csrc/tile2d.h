@@ -120,49 +120,61 @@ __device__ __forceinline__ void rho_ring2d(const Coef<T>& c, int x0, int y0, boo
     }
 }
 
+// Momentum update of one node: R-region index e, drho'-region index d, grid
+// row gy (for the per-row force).  Returns drho', u', v'.  Shared by the tile
+// kernels and by the fused closure kernel, so all give identical bits.
+template <typename T, int RX, int DX>
+__device__ __forceinline__ void momentum_node2d(const Coef<T>& c, const T* sr, const T* su, const T* sv,
+                                                const T* srn, int e, int d, int gy, T& rn_out, T& u_out, T& v_out)
+{
+    const T rc = sr[e], uc = su[e], vc = sv[e];
+    const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
+    const T uE = su[e + 1], uW = su[e - 1], uN = su[e + RX], uS = su[e - RX];
+    const T vE = sv[e + 1], vW = sv[e - 1], vN = sv[e + RX], vS = sv[e - RX];
+    const T rho0 = c.rho0, cs2 = c.cs2;
+    const T mxC = momc(rc, uc, rho0), myC = momc(rc, vc, rho0);
+    const T mxE = momc(rE, uE, rho0), mxW = momc(rW, uW, rho0);
+    const T mxN = momc(rN, uN, rho0), mxS = momc(rS, uS, rho0);
+    const T myE = momc(rE, vE, rho0), myW = momc(rW, vW, rho0);
+    const T myN = momc(rN, vN, rho0), myS = momc(rS, vS, rho0);
+    const T rnC = srn[d];
+    const T rnE = srn[d + 1], rnW = srn[d - 1], rnN = srn[d + DX], rnS = srn[d - DX];
+    // fluxes of Pi_ab = m_a u_b + cs^2 drho delta_ab
+    const T fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + (mxN * vN - mxS * vS);
+    const T fyy = (myE * uE - myW * uW) + (fmaT(myN, vN, cs2 * rN) - fmaT(myS, vS, cs2 * rS));
+    const T lx_ = ((mxE + mxW) + (mxN + mxS)) - T(4) * mxC;
+    const T ly_ = ((myE + myW) + (myN + myS)) - T(4) * myC;
+    const T sx = (rnE - rnW) - (rE - rW);
+    const T sy = (rnN - rnS) - (rN - rS);
+    const T rho_n = rho0 + rnC;
+    T gx_ = c.gdt[0];
+    if (c.fx) gx_ = fmaT(c.dt, c.fx[gy], gx_);
+    const T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lx_, -c.cg * fxx)));
+    const T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, ly_, -c.cg * fyy)));
+    const T drn = rnC - rc;
+    const T inv = recipT(rho_n);
+    rn_out = rnC;
+    u_out = fmaT(fmaT(-uc, drn, dmx), inv, uc);
+    v_out = fmaT(fmaT(-vc, drn, dmy), inv, vc);
+}
+
 // Momentum update and store for the nodes of the tile.
 template <typename T, int TX, int TY, int NT>
 __device__ __forceinline__ void momentum2d(const Coef<T>& c, const State<T>& out, int x0, int y0,
                                            const T* sr, const T* su, const T* sv, const T* srn)
 {
     using S = Shape2<TX, TY>;
-    constexpr int RX = S::RX, DX = S::DX;
     for (int q = threadIdx.x; q < TX * TY; q += NT) {
         const int ly = q / TX, lx = q - ly * TX;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= c.nx || gy >= c.ny) continue;
-        const int e = (ly + 2) * RX + (lx + 2);
-        const int d = (ly + 1) * DX + (lx + 1);
-        const T rc = sr[e], uc = su[e], vc = sv[e];
-        const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
-        const T uE = su[e + 1], uW = su[e - 1], uN = su[e + RX], uS = su[e - RX];
-        const T vE = sv[e + 1], vW = sv[e - 1], vN = sv[e + RX], vS = sv[e - RX];
-        const T rho0 = c.rho0, cs2 = c.cs2;
-        const T mxC = momc(rc, uc, rho0), myC = momc(rc, vc, rho0);
-        const T mxE = momc(rE, uE, rho0), mxW = momc(rW, uW, rho0);
-        const T mxN = momc(rN, uN, rho0), mxS = momc(rS, uS, rho0);
-        const T myE = momc(rE, vE, rho0), myW = momc(rW, vW, rho0);
-        const T myN = momc(rN, vN, rho0), myS = momc(rS, vS, rho0);
-        const T rnC = srn[d];
-        const T rnE = srn[d + 1], rnW = srn[d - 1], rnN = srn[d + DX], rnS = srn[d - DX];
-        // fluxes of Pi_ab = m_a u_b + cs^2 drho delta_ab
-        const T fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + (mxN * vN - mxS * vS);
-        const T fyy = (myE * uE - myW * uW) + (fmaT(myN, vN, cs2 * rN) - fmaT(myS, vS, cs2 * rS));
-        const T lx_ = ((mxE + mxW) + (mxN + mxS)) - T(4) * mxC;
-        const T ly_ = ((myE + myW) + (myN + myS)) - T(4) * myC;
-        const T sx = (rnE - rnW) - (rE - rW);
-        const T sy = (rnN - rnS) - (rN - rS);
-        const T rho_n = rho0 + rnC;
-        T gx_ = c.gdt[0];
-        if (c.fx) gx_ = fmaT(c.dt, c.fx[gy], gx_);
-        const T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lx_, -c.cg * fxx)));
-        const T dmy = fmaT(rho_n, c.gdt[1], fmaT(-c.ks, sy, fmaT(c.kv, ly_, -c.cg * fyy)));
-        const T drn = rnC - rc;
-        const T inv = recipT(rho_n);
+        T rn, un, vn;
+        momentum_node2d<T, S::RX, S::DX>(c, sr, su, sv, srn, (ly + 2) * S::RX + (lx + 2), (ly + 1) * S::DX + (lx + 1),
+                                         gy, rn, un, vn);
         const size_t o = (size_t)gy * c.nx + gx;
-        out.r[o] = rnC;
-        out.u[o] = fmaT(fmaT(-uc, drn, dmx), inv, uc);
-        out.v[o] = fmaT(fmaT(-vc, drn, dmy), inv, vc);
+        out.r[o] = rn;
+        out.u[o] = un;
+        out.v[o] = vn;
     }
 }
 

@@ -242,10 +242,12 @@ def test_training_overfits_one_pair(mods):
     assert last < first / 10, (first, last)
 
 
-def test_closure_handle_equals_manual_sequence(mods):
-    """The closure handle (graph-captured) is bitwise equal to acm steps
-    followed by the fused network correction issued call by call, and with
-    the network switched off to plain acm_run."""
+@pytest.mark.parametrize("separate_step", [False, True])
+def test_closure_handle_equals_manual_sequence(mods, separate_step):
+    """The closure handle (graph-captured; the step run inside the correction
+    kernel, or as its own launch) is bitwise equal to acm steps followed by
+    the fused network correction issued call by call, and with the network
+    switched off to plain acm_run."""
     torch, acm, closure, cnn = mods
     from paper_2012_03525_amd import inputs
     spec = closure.FlowSpec(n_fine=256, nu_fine=0.02)
@@ -253,9 +255,10 @@ def test_closure_handle_equals_manual_sequence(mods):
     dev = "cuda:0"
     c0 = {k: torch.from_numpy(v.astype(np.float32)).to(dev) for k, v in st.items()}
     net = closure.Network(64, 64, seed=2, in_scale=[1e3, 30.0, 30.0], out_scale=[1e-6, 1e-5, 1e-5])
-    run = closure.ClosureRun(spec, net, c0, chunk=2)
+    run = closure.ClosureRun(spec, net, c0, chunk=2, separate_step=separate_step)
     run.run(4)
     got = {k: t.clone() for k, t in run.state().items()}
+    assert acm.lib().acm_closure_set_network(run.h, 3) == acm.EINVAL
     run.close()
     s = acm.Solver(spec.coarse_config(), {k: v.astype(np.float32).astype(np.float64) for k, v in st.items()},
                    force_x=spec.coarse_force())
