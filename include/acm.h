@@ -139,7 +139,9 @@ acm_status acm_stability(const acm_config* cfg, double* max_amplification, doubl
  * The initial state must already be in a.  force_x: NULL or a device array
  * of ny elements (precision type) added to g[0] on row j (e.g. Kolmogorov
  * forcing).  stream: hipStream_t or NULL.  The handle owns only host data,
- * graph executables and a small reduction buffer it allocates here. */
+ * graph executables and a small reduction buffer it allocates here, plus,
+ * for 3D two-phase runs, 4 fields of intermediates (phi* and the surface-
+ * tension force per axis). */
 acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b,
                     const void* force_x, void* stream, acm_handle** out);
 

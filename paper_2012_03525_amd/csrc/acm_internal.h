@@ -157,8 +157,8 @@ hipError_t launch_step3d(const Coef<T>& c, const State<T>& in, const State<T>& o
 template <typename T>
 hipError_t launch_twophase2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
                              hipStream_t s);
-// 3D two-phase step: scratch holds 5 fields of nx*ny*nz values (mu / mu*,
-// phi*, and phi G_iso mu per axis), owned by the caller
+// 3D two-phase step: scratch holds 4 fields of nx*ny*nz values (phi* and
+// phi G_iso mu per axis), owned by the caller
 template <typename T>
 hipError_t launch_twophase3d(const Coef<T>& c, const State<T>& in, const State<T>& out, T* scratch, int tile,
                              hipStream_t s);

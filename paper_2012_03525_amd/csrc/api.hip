@@ -204,7 +204,7 @@ struct acm_handle {
     int diag_blocks = 0;
     Coef<float> cf;
     Coef<double> cd;
-    void* scratch = nullptr;  // 3D two-phase intermediates (5 fields)
+    void* scratch = nullptr;  // 3D two-phase intermediates (4 fields)
 };
 
 namespace {
@@ -328,7 +328,7 @@ acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields
     if (e == hipSuccess) e = hipMalloc(&h->result, sizeof(double) * NDIAG);
     if (e == hipSuccess) e = hipHostMalloc(&h->host, sizeof(double) * NDIAG, hipHostMallocDefault);
     if (e == hipSuccess && cfg->two_phase && cfg->dim == 3)
-        e = hipMalloc(&h->scratch, (size_t)n * 5 * (cfg->precision == ACM_F64 ? sizeof(double) : sizeof(float)));
+        e = hipMalloc(&h->scratch, (size_t)n * 4 * (cfg->precision == ACM_F64 ? sizeof(double) : sizeof(float)));
     if (e != hipSuccess) {
         acm_destroy(h);
         return hip_fail(e, "allocating reduction and scratch buffers");
