@@ -88,10 +88,14 @@ typedef struct acm_config {
                                phase: 1 32x8, 2 64x8, 3 16x16, 4 128x4,
                                5 32x16 (0: 64x4).  2D two-phase: 1 32x8,
                                2 64x8, 3 16x16 (0: 32x16).  3D: low byte
-                               1 32x8, 3 32x4, 4 64x4, 5 64x16, 7 32x16,
-                               9 128x4, 12 128x8 (0: 64x8; FP64 accepts 3, 4,
-                               else 32x8), bits 8+ = z chunk / 16 (0: 64
-                               planes).  Results do not depend on the tile. */
+                               1 32x8, 2 64x8, 3 32x4, 4 64x4, 5 64x16,
+                               7 32x16, 9 128x4, 12 128x8, 13 64x8 with two
+                               rows per thread; 0: 13 with 64-plane chunks,
+                               or a smaller shape and chunk when that gives
+                               fewer than two workgroups per CU (FP64 accepts
+                               3, 4, else 32x8); bits 8+ = z chunk / 16 (0:
+                               64 planes).  Results do not depend on the
+                               tile. */
     double wet_cos[6];      /* two-phase: cos(contact angle) of each wall face
                                for the wetting condition of Sec. 2,
                                d_n phi = -(2/W) cos(theta) (1 - phi_w^2),
