@@ -90,7 +90,8 @@ typedef struct acm_config {
                                2 64x8, 3 16x16 (0: 32x16).  3D: low byte
                                1 32x8, 2 64x8, 3 32x4, 4 64x4, 5 64x16,
                                7 32x16, 9 128x4, 12 128x8, 13 64x8 with two
-                               rows per thread; 0: 13 with 64-plane chunks,
+                               rows per thread on fully periodic grids
+                               (else as 2); 0: 13 with 64-plane chunks,
                                or a smaller shape and chunk when that gives
                                fewer than two workgroups per CU (FP64 accepts
                                3, 4, else 32x8); bits 8+ = z chunk / 16 (0:

@@ -61,10 +61,13 @@ template hipError_t launch_step2d<double>(const Coef<double>&, const State<doubl
 
 // ===========================================================================
 // 3D: 2.5D march along z.  A workgroup owns a TX x TY column of nodes and a
-// chunk of ZC planes.  Four input planes (with a two-node in-plane halo) are
+// chunk of ZC planes.  NS input planes (with a two-node in-plane halo) are
 // resident in LDS as a ring; drho' is computed one plane ahead on the tile
 // plus a one-node ring, so every node's drho' is formed exactly once per
-// workgroup.  Plane k+3 is fetched into registers while plane k is computed.
+// workgroup.  Plane k+4 is fetched into registers while plane k is computed.
+// NS = 4 keeps the plane being written clear of the planes being read (two
+// barriers per plane); NS = 3 takes 3/4 of the LDS and a third barrier
+// before a slot is overwritten.
 //
 // GEN = false is the fast path for fully periodic boxes (nz >= 2) with rho0 = 1: no
 // ghost transforms, m = u + drho u.  GEN = true handles every boundary type,
@@ -159,14 +162,19 @@ struct PlaneAccess {
     }
 };
 
-template <typename T, int TX, int TY, int RPT, bool GEN, bool WIDE>
+template <typename T, int TX, int TY, int RPT, bool GEN, bool WIDE, int NS>
 __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<T> in, State<T> out, int zc,
                                                                 int nbx, int nby)
 {
     using S = Shape3<TX, TY, RPT>;
     constexpr int RX = S::RX, RXY = S::RXY, DX = S::DX, DXY = S::DXY, NT = S::NT, NL = S::NL, ND = S::ND;
     constexpr int YS = S::YS;
-    __shared__ T sr[4][RXY], su[4][RXY], sv[4][RXY], sw[4][RXY];
+    static_assert(NS == 3 || NS == 4, "three or four resident planes");
+    // plane p lives in slot (p - z0) mod NS; the loop body is unrolled over P
+    // planes so that every slot, register set and drho' buffer is fixed at
+    // compile time
+    constexpr int P = NS == 4 ? 4 : 6;
+    __shared__ T sr[NS][RXY], su[NS][RXY], sv[NS][RXY], sw[NS][RXY];
     __shared__ T sd[2][DXY];
     // ghost velocity rules u_a = gs[0][f][a] u_a + gs[1][f][a] per crossed
     // face f, looked up per lane from LDS (GEN only)
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
     const int t1 = lb / nbx;
     const int by = t1 % nby, bz = t1 / nby;
     const int x0 = bx * TX, y0 = by * TY;
-    const int z0 = bz * zc;  // zc is a multiple of 16, so z0 % 4 == 0
+    const int z0 = bz * zc;
     const int z1 = min(z0 + zc, c.nz);
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     const unsigned plane = (unsigned)nx * (unsigned)ny;
@@ -302,9 +310,9 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
             sw[slot][e] = pw[b][i];
         }
     };
-    // drho' of the plane in slot S0 (below SD, above SU) on the tile + ring into sd[DS]
-    auto ring = [&](auto s0c, auto dsc) {
-        constexpr int s0 = decltype(s0c)::value, sD = (s0 + 3) & 3, sU = (s0 + 1) & 3;
+    // drho' of the plane in slot s0 (below sD, above sU) on the tile + ring into sd[ds]
+    auto ring = [&](auto s0c, auto sDc, auto sUc, auto dsc) {
+        constexpr int s0 = decltype(s0c)::value, sD = decltype(sDc)::value, sU = decltype(sUc)::value;
         constexpr int ds = decltype(dsc)::value;
 #pragma unroll
         for (int i = 0; i < ND; ++i) {
@@ -319,45 +327,66 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
 
-    // ---- prologue (z0 % 4 == 0): planes z0-2 .. z0+1 resident, z0+2 and z0+3 in flight
+    // ---- prologue: planes z0-1 .. z0+1 resident and drho'(z0) on the ring,
+    // planes z0+2 and z0+3 in flight in register sets 0 and 1
+    T rn_prev[RPT], r_prev[RPT], u_prev[RPT], v_prev[RPT], w_prev[RPT];
+    // drho'(z0-1) at the own nodes and the level-n values of plane z0-1
+    auto own_below = [&](auto sMc, auto sDc, auto sUc) {
+        constexpr int sM = decltype(sMc)::value, sD = decltype(sDc)::value, sU = decltype(sUc)::value;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int eo = (tyb + r * YS + 2) * RX + (tx + 2);
+            rn_prev[r] = T(0);
+            if (zperiodic || z0 > 0)  // planes z0-2, z0-1, z0 are resident
+                rn_prev[r] = rho_new_3d<GEN, T, RX>(c, sr[sM], su[sM], sv[sM], sr[sD], sw[sD], sr[sU], sw[sU], eo);
+            r_prev[r] = sr[sM][eo];
+            u_prev[r] = su[sM][eo];
+            v_prev[r] = sv[sM][eo];
+            w_prev[r] = sw[sM][eo];
+        }
+    };
     fetch(z0 - 2, I0{});
     fetch(z0 - 1, I1{});
-    store(I2{}, I0{});
-    store(I3{}, I1{});
-    fetch(z0, I0{});
-    fetch(z0 + 1, I1{});
-    store(I0{}, I0{});
-    store(I1{}, I1{});
-    fetch(z0 + 2, I0{});
-    fetch(z0 + 3, I1{});
-    __syncthreads();
-    ring(I0{}, I0{});
-    T rn_prev[RPT], r_prev[RPT], u_prev[RPT], v_prev[RPT], w_prev[RPT];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const int eo = (tyb + r * YS + 2) * RX + (tx + 2);
-        rn_prev[r] = T(0);
-        if (zperiodic || z0 > 0)  // drho'(z0-1) at the own node: planes z0-2, z0-1, z0 are resident
-            rn_prev[r] = rho_new_3d<GEN, T, RX>(c, sr[3], su[3], sv[3], sr[2], sw[2], sr[0], sw[0], eo);
+    if constexpr (NS == 4) {
+        store(I2{}, I0{});
+        store(I3{}, I1{});
+        fetch(z0, I0{});
+        fetch(z0 + 1, I1{});
+        store(I0{}, I0{});
+        store(I1{}, I1{});
+        fetch(z0 + 2, I0{});
+        fetch(z0 + 3, I1{});
+        __syncthreads();
+        ring(I0{}, I3{}, I1{}, I0{});
+        own_below(I3{}, I2{}, I0{});
+    } else {
+        store(I1{}, I0{});
+        store(I2{}, I1{});
+        fetch(z0, I0{});
+        fetch(z0 + 1, I1{});
+        store(I0{}, I0{});
+        fetch(z0 + 2, I0{});
+        __syncthreads();
+        own_below(I2{}, I1{}, I0{});
+        __syncthreads();  // plane z0+1 replaces plane z0-2
+        store(I1{}, I1{});
+        fetch(z0 + 3, I1{});
+        __syncthreads();
+        ring(I0{}, I2{}, I1{}, I0{});
     }
     __syncthreads();
+    if (!(zperiodic || z0 > 0)) {  // wall / symmetry at z = 0: drho'(-1) is the mirror value
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const int eo = (tyb + r * YS + 2) * RX + (tx + 2);
-        const int dO = (tyb + r * YS + 1) * DX + (tx + 1);
-        if (!(zperiodic || z0 > 0)) rn_prev[r] = sd[0][dO];  // wall / symmetry at z = 0: mirror
-        r_prev[r] = sr[3][eo];
-        u_prev[r] = su[3][eo];
-        v_prev[r] = sv[3][eo];
-        w_prev[r] = sw[3][eo];
+        for (int r = 0; r < RPT; ++r) rn_prev[r] = sd[0][(tyb + r * YS + 1) * DX + (tx + 1)];
     }
 
     const T rho0 = c.rho0, cs2 = c.cs2;
     // one plane; J = k mod 4 fixes every LDS slot and register set at compile time
     auto iterate = [&](int k, auto jc) {
         constexpr int J = decltype(jc)::value;
-        constexpr int s0 = J, sU = (J + 1) & 3, s2 = (J + 2) & 3;
+        constexpr int s0 = J % NS, sU = (J + 1) % NS, s2 = (J + 2) % NS;
         using BS = std::integral_constant<int, J & 1>;
+        if constexpr (NS == 3) __syncthreads();  // slot s2 held plane k-1, read by the previous plane
         const size_t ob = (size_t)k * plane;
         // two-phase: surface-tension force phi G_iso mu of this plane, loaded
         // before the prefetch so that waiting for it leaves the prefetch in flight
@@ -374,7 +403,9 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
         fetch(min(k + 4, z1 + 1), BS{});  // past the chunk: plane z1+1 again (cached)
         __syncthreads();
         const bool upper_ghost = (!zperiodic) && (k + 1 >= nz);
-        if (!upper_ghost) ring(std::integral_constant<int, sU>{}, std::integral_constant<int, (J + 1) & 1>{});
+        if (!upper_ghost)
+            ring(std::integral_constant<int, sU>{}, std::integral_constant<int, s0>{},
+                 std::integral_constant<int, s2>{}, std::integral_constant<int, (J + 1) & 1>{});
         __syncthreads();
 
         const T* r0 = sr[s0];
@@ -445,34 +476,66 @@ __global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<
             rn_prev[r] = rnC;
         }
     };
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
     int k = z0;
-    for (; k + 3 < z1; k += 4) {
+    for (; k + P - 1 < z1; k += P) {
         iterate(k, I0{});
         iterate(k + 1, I1{});
         iterate(k + 2, I2{});
         iterate(k + 3, I3{});
+        if constexpr (P == 6) {
+            iterate(k + 4, I4{});
+            iterate(k + 5, I5{});
+        }
     }
     if (k < z1) iterate(k, I0{});
     if (k + 1 < z1) iterate(k + 1, I1{});
     if (k + 2 < z1) iterate(k + 2, I2{});
+    if constexpr (P == 6) {
+        if (k + 3 < z1) iterate(k + 3, I3{});
+        if (k + 4 < z1) iterate(k + 4, I4{});
+    }
 }
 
-template <typename T, int TX, int TY, int RPT>
+// the fully periodic fast path applies (rho0 = 1, no per-node force)
+template <typename T>
+static bool fast3d(const Coef<T>& c)
+{
+    return !c.nonperiodic && c.rho0 == T(1) && !c.fst[0] && c.nz >= 2;
+}
+
+// a shape that only the fast path uses (its wall path would not fit the
+// register file at two waves per SIMD)
+template <typename T, int TX, int TY, int RPT, int NS>
+static hipError_t launch3d_fast(const Coef<T>& c, const State<T>& in, const State<T>& out, int zc, hipStream_t s)
+{
+    const int nbx = (c.nx + TX - 1) / TX, nby = (c.ny + TY - 1) / TY, nbz = (c.nz + zc - 1) / zc;
+    const bool wide = (size_t)c.nx * c.ny * c.nz * sizeof(T) >= (size_t(1) << 31);
+    const dim3 grid(nbx * nby * nbz), block(TX * TY / RPT);
+    if (!wide)
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false, false, NS>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+    else
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false, true, NS>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+    return hipGetLastError();
+}
+
+template <typename T, int TX, int TY, int RPT, int NS = 4>
 static hipError_t launch3d_variant(const Coef<T>& c, const State<T>& in, const State<T>& out, int zc,
                                    hipStream_t s)
 {
     const int nbx = (c.nx + TX - 1) / TX, nby = (c.ny + TY - 1) / TY, nbz = (c.nz + zc - 1) / zc;
-    const bool fast = !c.nonperiodic && c.rho0 == T(1) && !c.fst[0] && c.nz >= 2;
+    const bool fast = fast3d(c);
     const bool wide = (size_t)c.nx * c.ny * c.nz * sizeof(T) >= (size_t(1) << 31);
     const dim3 grid(nbx * nby * nbz), block(TX * TY / RPT);
     if (fast && !wide)
-        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false, false>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false, false, NS>), grid, block, 0, s, c, in, out, zc, nbx, nby);
     else if (fast)
-        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false, true>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false, true, NS>), grid, block, 0, s, c, in, out, zc, nbx, nby);
     else if (!wide)
-        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, false>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, false, NS>), grid, block, 0, s, c, in, out, zc, nbx, nby);
     else
-        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, true>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, true, NS>), grid, block, 0, s, c, in, out, zc, nbx, nby);
     return hipGetLastError();
 }
 
@@ -531,8 +594,12 @@ hipError_t launch_step3d(const Coef<T>& c, const State<T>& in, const State<T>& o
             case 7: return launch3d_variant<T, 32, 16, 2>(c, in, out, zc, s);
             case 9: return launch3d_variant<T, 128, 4, 1>(c, in, out, zc, s);
             case 12: return launch3d_variant<T, 128, 8, 1>(c, in, out, zc, s);
-            // two rows per thread (256 threads): 3 % faster than one row at 256^3
-            case 13: return launch3d_variant<T, 64, 8, 2>(c, in, out, zc, s);
+            // periodic fast path: two rows per thread (256 threads) and a
+            // three-plane ring (44 KB of LDS, 197 VGPRs), 5 % faster than one
+            // row per thread at 256^3; other grids: 64 x 8, one row per thread
+            case 13:
+                if (fast3d(c)) return launch3d_fast<T, 64, 8, 2, 3>(c, in, out, zc, s);
+                return launch3d_variant<T, 64, 8, 1>(c, in, out, zc, s);
             default: return launch3d_variant<T, 64, 8, 1>(c, in, out, zc, s);
         }
     }
