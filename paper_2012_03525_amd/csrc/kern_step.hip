@@ -162,8 +162,10 @@ struct PlaneAccess {
     }
 };
 
-template <typename T, int TX, int TY, int RPT, bool GEN, bool WIDE, int NS>
-__global__ __launch_bounds__(TX * TY / RPT) void step3d_kernel(Coef<T> c, State<T> in, State<T> out, int zc,
+// WPE > 0 asks the compiler for at least WPE waves per SIMD (a register
+// budget of 512 / WPE VGPRs); 0 leaves the budget to the compiler.
+template <typename T, int TX, int TY, int RPT, bool GEN, bool WIDE, int NS, int WPE = 0>
+__global__ __launch_bounds__(TX * TY / RPT) __attribute__((amdgpu_waves_per_eu(WPE))) void step3d_kernel(Coef<T> c, State<T> in, State<T> out, int zc,
                                                                 int nbx, int nby)
 {
     using S = Shape3<TX, TY, RPT>;
@@ -520,10 +522,16 @@ static hipError_t launch3d_fast(const Coef<T>& c, const State<T>& in, const Stat
     return hipGetLastError();
 }
 
+// The FP32 wall path of the 8-row, one-row-per-thread shapes asks for four
+// waves per SIMD (128 VGPRs, two 8-wave workgroups per CU): at 64 x 8 it
+// would otherwise take 144 VGPRs and one workgroup per CU, 20 % slower on a
+// walled 256^3 grid, for an 8-byte spill.  (The 4-row shapes would spill
+// over 100 bytes per lane under the same cap and keep their budget.)
 template <typename T, int TX, int TY, int RPT, int NS = 4>
 static hipError_t launch3d_variant(const Coef<T>& c, const State<T>& in, const State<T>& out, int zc,
                                    hipStream_t s)
 {
+    constexpr int WG = (sizeof(T) == 4 && RPT == 1 && TY == 8) ? 4 : 0;
     const int nbx = (c.nx + TX - 1) / TX, nby = (c.ny + TY - 1) / TY, nbz = (c.nz + zc - 1) / zc;
     const bool fast = fast3d(c);
     const bool wide = (size_t)c.nx * c.ny * c.nz * sizeof(T) >= (size_t(1) << 31);
@@ -533,9 +541,11 @@ static hipError_t launch3d_variant(const Coef<T>& c, const State<T>& in, const S
     else if (fast)
         hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, false, true, NS>), grid, block, 0, s, c, in, out, zc, nbx, nby);
     else if (!wide)
-        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, false, NS>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, false, NS, WG>), grid, block, 0, s, c, in, out, zc, nbx,
+                           nby);
     else
-        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, true, NS>), grid, block, 0, s, c, in, out, zc, nbx, nby);
+        hipLaunchKernelGGL((step3d_kernel<T, TX, TY, RPT, true, true, NS, WG>), grid, block, 0, s, c, in, out, zc, nbx,
+                           nby);
     return hipGetLastError();
 }
 
