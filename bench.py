@@ -225,7 +225,7 @@ def cpu_baseline(name, cfg, st, budget_s):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2012_03525_amd import acm
