@@ -103,15 +103,18 @@ __global__ __launch_bounds__(256) void batch_step_kernel(const BatchCaseDev<T>* 
     }
 }
 
-// Mode 0: workgroup b runs item b; slots past the active count exit.
+// Mode 0: one workgroup per active item; slots past the active count exit.
 template <typename T>
 __global__ __launch_bounds__(256) void batch_grid_kernel(const BatchCaseDev<T>* __restrict__ cases,
                                                           const int4* __restrict__ items,
                                                           const int* __restrict__ nitems, int parity)
 {
     __shared__ __align__(16) char smem[batch_lds_bytes<T>()];
-    const int t = blockIdx.x;
-    if (t >= *nitems) return;
+    const int n = *nitems;
+    if ((int)blockIdx.x >= n) return;
+    // a bijection of the active slots that gives each XCD a contiguous run of
+    // items (neighbouring tiles of a case), so their halos meet in its L2
+    const int t = xcd_remap(blockIdx.x, n);
     const int4 it = items[t];
     batch_item<T>(cases[it.x], it, parity, smem);
 }
