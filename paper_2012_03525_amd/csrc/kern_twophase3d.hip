@@ -80,7 +80,9 @@ __device__ __forceinline__ T gz_num(const T n[3][3][3])
 // ring (mu), P region = the tile plus two nodes (phi, ghost rules applied
 // while staging), so a node's neighbours come from LDS instead of 19
 // separate global loads.
-constexpr int BX = 32, BY = 4, BZ = 4, NTH = BX * BY * BZ;
+// Threads BX x BY x TZ; each owns ZR nodes of its column, TZ planes apart,
+// so the staged halo is shared by twice the nodes (the tile is BZ = TZ ZR deep).
+constexpr int BX = 32, BY = 4, TZ = 4, ZR = 2, BZ = TZ * ZR, NTH = BX * BY * TZ;
 constexpr int RX = BX + 2, RY = BY + 2, RZ = BZ + 2, RXYZ = RX * RY * RZ;
 
 // halo-2 region of a staged phi field and the D3Q19 neighbourhood of LDS
@@ -162,13 +164,14 @@ struct Node {
     int i, j, k;
     bool in;
 };
+// the thread's r-th node (r < ZR) and its local z in the tile
 template <typename T>
-__device__ __forceinline__ Node my_node(const Coef<T>& c)
+__device__ __forceinline__ Node my_node(const Coef<T>& c, int r)
 {
     Node n;
     n.i = blockIdx.x * BX + threadIdx.x;
     n.j = blockIdx.y * BY + threadIdx.y;
-    n.k = blockIdx.z * BZ + threadIdx.z;
+    n.k = blockIdx.z * BZ + threadIdx.z + TZ * r;
     n.in = n.i < c.nx && n.j < c.ny && n.k < c.nz;
     return n;
 }
@@ -186,19 +189,23 @@ __global__ __launch_bounds__(NTH) void stage1_kernel(Coef<T> c, State<T> in, T* 
     __syncthreads();
     mu_ring(c, i0, j0, k0, sp, sm);
     __syncthreads();
-    const Node d = my_node(c);
-    if (!d.in) return;
-    const size_t o = ((size_t)d.k * c.ny + d.j) * c.nx + d.i;
-    T m[3][3][3], p[3][3][3];
-    nb19at<RX, RY>(sm, (threadIdx.x + 1) + RX * ((threadIdx.y + 1) + RY * (threadIdx.z + 1)), m);
-    nb19at<PX, PY>(sp, (threadIdx.x + 2) + PX * ((threadIdx.y + 2) + PY * (threadIdx.z + 2)), p);
-    const T pc = p[1][1][1];
-    fx[o] = pc * (gx_num(m) * c.gi);
-    fy[o] = pc * (gy_num(m) * c.gi);
-    fz[o] = pc * (gz_num(m) * c.gi);
-    const T adv = fmaT(in.u[o], gx_num(p), fmaT(in.v[o], gy_num(p), in.w[o] * gz_num(p))) * c.gi;
-    const T rhs = fmaT(c.mob * c.li, lap_num(m), -adv);
-    phis[o] = fmaT(c.dt, rhs, pc);
+#pragma unroll
+    for (int r = 0; r < ZR; ++r) {
+        const Node d = my_node(c, r);
+        if (!d.in) continue;
+        const int lz = threadIdx.z + TZ * r;
+        const size_t o = ((size_t)d.k * c.ny + d.j) * c.nx + d.i;
+        T m[3][3][3], p[3][3][3];
+        nb19at<RX, RY>(sm, (threadIdx.x + 1) + RX * ((threadIdx.y + 1) + RY * (lz + 1)), m);
+        nb19at<PX, PY>(sp, (threadIdx.x + 2) + PX * ((threadIdx.y + 2) + PY * (lz + 2)), p);
+        const T pc = p[1][1][1];
+        fx[o] = pc * (gx_num(m) * c.gi);
+        fy[o] = pc * (gy_num(m) * c.gi);
+        fz[o] = pc * (gz_num(m) * c.gi);
+        const T adv = fmaT(in.u[o], gx_num(p), fmaT(in.v[o], gy_num(p), in.w[o] * gz_num(p))) * c.gi;
+        const T rhs = fmaT(c.mob * c.li, lap_num(m), -adv);
+        phis[o] = fmaT(c.dt, rhs, pc);
+    }
 }
 
 // mu* of phi* on the tile and its ring, then
@@ -214,15 +221,19 @@ __global__ __launch_bounds__(NTH) void stage2_kernel(Coef<T> c, State<T> in, con
     __syncthreads();
     mu_ring(c, i0, j0, k0, sp, sm);
     __syncthreads();
-    const Node d = my_node(c);
-    if (!d.in) return;
-    const size_t o = ((size_t)d.k * c.ny + d.j) * c.nx + d.i;
-    T m[3][3][3], p[3][3][3];
-    nb19at<RX, RY>(sm, (threadIdx.x + 1) + RX * ((threadIdx.y + 1) + RY * (threadIdx.z + 1)), m);
-    nb19at<PX, PY>(sp, (threadIdx.x + 2) + PX * ((threadIdx.y + 2) + PY * (threadIdx.z + 2)), p);
-    const T adv = fmaT(in.u[o], gx_num(p), fmaT(in.v[o], gy_num(p), in.w[o] * gz_num(p))) * c.gi;
-    const T rhs = fmaT(c.mob * c.li, lap_num(m), -adv);
-    phi_out[o] = T(0.5) * fmaT(c.dt, rhs, in.phi[o] + p[1][1][1]);
+#pragma unroll
+    for (int r = 0; r < ZR; ++r) {
+        const Node d = my_node(c, r);
+        if (!d.in) continue;
+        const int lz = threadIdx.z + TZ * r;
+        const size_t o = ((size_t)d.k * c.ny + d.j) * c.nx + d.i;
+        T m[3][3][3], p[3][3][3];
+        nb19at<RX, RY>(sm, (threadIdx.x + 1) + RX * ((threadIdx.y + 1) + RY * (lz + 1)), m);
+        nb19at<PX, PY>(sp, (threadIdx.x + 2) + PX * ((threadIdx.y + 2) + PY * (lz + 2)), p);
+        const T adv = fmaT(in.u[o], gx_num(p), fmaT(in.v[o], gy_num(p), in.w[o] * gz_num(p))) * c.gi;
+        const T rhs = fmaT(c.mob * c.li, lap_num(m), -adv);
+        phi_out[o] = T(0.5) * fmaT(c.dt, rhs, in.phi[o] + p[1][1][1]);
+    }
 }
 
 }  // namespace
@@ -234,7 +245,7 @@ hipError_t launch_twophase3d(const Coef<T>& c, const State<T>& in, const State<T
     const size_t n = (size_t)c.nx * c.ny * c.nz;
     T* phis = scratch;
     T* f[3] = {scratch + n, scratch + 2 * n, scratch + 3 * n};
-    const dim3 block(BX, BY, BZ), grid((c.nx + BX - 1) / BX, (c.ny + BY - 1) / BY, (c.nz + BZ - 1) / BZ);
+    const dim3 block(BX, BY, TZ), grid((c.nx + BX - 1) / BX, (c.ny + BY - 1) / BY, (c.nz + BZ - 1) / BZ);
     hipLaunchKernelGGL(stage1_kernel<T>, grid, block, 0, s, c, in, f[0], f[1], f[2], phis);
     Coef<T> cf = c;
     for (int a = 0; a < 3; ++a) cf.fst[a] = f[a];
