@@ -170,6 +170,18 @@ acm_status acm_current(const acm_handle* h, int32_t* which, int64_t* step);
  * complete checkpoint. */
 acm_status acm_set_current(acm_handle* h, int32_t which, int64_t step);
 
+/* Adjoint of one step (for training through the solver; not part of the
+ * paper's method): with s = S(q) the step (2.10)-(2.13) with the body force
+ * and the handle's forcing row, taken from state q, writes the
+ * vector-Jacobian product adj_q = (dS/dq)^T adj_s.  q, s, adj_s, adj_q: device
+ * fields drho, u, v of the handle's grid and precision, caller-owned; s must
+ * hold S(q) (its density and velocity enter the derivative of u' = m'/rho').
+ * adj_q must not alias the other three (ACM_EINVAL).  Covers 2D single-phase
+ * handles on fully periodic grids (ACM_EINVAL otherwise).  Asynchronous on
+ * the handle's stream; the handle's own sets are not touched. */
+acm_status acm_step_adjoint(acm_handle* h, const acm_fields* q, const acm_fields* s, const acm_fields* adj_s,
+                            const acm_fields* adj_q);
+
 /* Release the handle (not the caller's fields).  Synchronises the stream. */
 void acm_destroy(acm_handle* h);
 
@@ -282,6 +294,11 @@ size_t acm_cnn_wgrad_workspace(int32_t nx, int32_t ny, int32_t cin, int32_t cout
 acm_status acm_cnn_wgrad(int32_t nx, int32_t ny, int32_t cin, int32_t cout, const void* x, const void* g,
                          float* workspace, float* dw, float* db, void* stream);
 
+/* As acm_cnn_wgrad, but adds the gradients to dw and db (for sums over the
+ * steps of an unrolled trajectory). */
+acm_status acm_cnn_wgrad_add(int32_t nx, int32_t ny, int32_t cin, int32_t cout, const void* x, const void* g,
+                             float* workspace, float* dw, float* db, void* stream);
+
 /* Network input a0 (bf16, 16 channels) = in_scale[c] * (drho, u, v)[c]. */
 acm_status acm_cnn_pack(int32_t nx, int32_t ny, const float* drho, const float* u, const float* v,
                         const float* in_scale, void* a0, void* stream);
@@ -300,6 +317,16 @@ size_t acm_cnn_loss_workspace(int32_t nx, int32_t ny);
 acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* const* base,
                         const float* const* target, const float* out_scale, void* grad, double* workspace,
                         double* loss, void* stream);
+
+/* Loss of a state against a target for training through several steps:
+ * e_c = (q[c] - target[c]) / out_scale[c] on the channels with
+ * out_scale[c] > 0; *loss (device double) += weight * mean(e^2) over pixels
+ * and those channels; adj[c] (fp32, in place) += weight * d mean(e^2) / d q[c].
+ * workspace: acm_cnn_loss_workspace bytes.  ACM_EINVAL for NULL pointers, a
+ * negative or non-finite scale, all scales zero, or a non-finite weight. */
+acm_status acm_cnn_state_loss(int32_t nx, int32_t ny, const float* const* q, const float* const* target,
+                              const float* out_scale, float weight, float* const* adj, double* workspace,
+                              double* loss, void* stream);
 
 /* Adam update of n fp32 parameters (bias-corrected, step t >= 1); p16
  * (optional) receives the bf16 copy used by the convolutions. */

@@ -82,6 +82,7 @@ SIGNATURES = {
     "acm_current": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int64)]),
     "acm_set_current": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
+    "acm_step_adjoint": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(Fields)] * 4),
     "acm_destroy": (None, [ctypes.c_void_p]),
     "acm_last_error": (ctypes.c_char_p, []),
     "acm_version": (ctypes.c_char_p, []),
@@ -103,6 +104,7 @@ SIGNATURES = {
                                          ctypes.c_void_p]),
     "acm_cnn_wgrad_workspace": (ctypes.c_size_t, [ctypes.c_int32] * 4),
     "acm_cnn_wgrad": (ctypes.c_int, [ctypes.c_int32] * 4 + [ctypes.c_void_p] * 6),
+    "acm_cnn_wgrad_add": (ctypes.c_int, [ctypes.c_int32] * 4 + [ctypes.c_void_p] * 6),
     "acm_cnn_pack": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32] + [ctypes.c_void_p] * 3 +
                      [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]),
     "acm_cnn_apply": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]
@@ -111,6 +113,10 @@ SIGNATURES = {
     "acm_cnn_loss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                     ctypes.POINTER(ctypes.c_float)] + [ctypes.c_void_p] * 4),
+    "acm_cnn_state_loss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_float),
+                                          ctypes.c_float, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "acm_cnn_adam": (ctypes.c_int, [ctypes.c_int64] + [ctypes.c_void_p] * 5 + [ctypes.c_float] * 4 +
                      [ctypes.c_int64, ctypes.c_void_p]),
     "acm_cnn_to_bf16": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -254,6 +260,13 @@ class Solver:
 
     def run(self, nsteps: int):
         check(lib().acm_run(self.h, int(nsteps)))
+
+    def adjoint(self, q: Dict[str, "object"], s: Dict[str, "object"], adj_s: Dict[str, "object"],
+                adj_q: Dict[str, "object"]):
+        """adj_q = (dS/dq)^T adj_s for s = S(q) (device tensor dicts drho, u,
+        v of this grid and precision; 2D periodic single-phase).  Async."""
+        f = [self._fields(d) for d in (q, s, adj_s, adj_q)]
+        check(lib().acm_step_adjoint(self.h, *[ctypes.byref(x) for x in f]))
 
     def current(self):
         w, s = ctypes.c_int32(), ctypes.c_int64()

@@ -325,6 +325,182 @@ def train(net: Network, pairs, epochs: int, lr: float, seed: int = 0, lr_decay: 
     return losses
 
 
+def generate_windows(spec: FlowSpec, seeds: Sequence[int], warmup: int, windows_per_seed: int, stride: int,
+                     k: int):
+    """Trajectory windows for training through the solver: for each snapshot
+    time t, the box-filtered fine states F(fine_t), F(fine_{t + r}), ...,
+    F(fine_{t + k r}) one coarse step apart.  Returns a list of lists of
+    k + 1 state dicts (device tensors)."""
+    import torch
+    dev = torch.device("cuda:0")
+    shape_c = (spec.n_coarse, spec.n_coarse)
+    out = []
+    for seed in seeds:
+        fine = acm.Solver(spec.fine_config(), spec.initial_state(seed), force_x=spec.fine_force())
+        stream = ctypes.c_void_p(fine.stream.cuda_stream)
+        fine.run(warmup)
+        for _ in range(windows_per_seed):
+            win = []
+            for j in range(k + 1):
+                if j:
+                    fine.run(spec.ratio)
+                f = {kk: torch.empty(shape_c, dtype=torch.float32, device=dev) for kk in ("drho", "u", "v")}
+                filter_to(fine.tensors(), f, spec, stream)
+                win.append(f)
+            out.append(win)
+            fine.run(stride - k * spec.ratio)
+        fine.close()
+    torch.cuda.synchronize()
+    return out
+
+
+def pairs_from_windows(spec: FlowSpec, windows):
+    """One-step training pairs (S_c(F_0), F_1) of each window."""
+    import torch
+    shape_c = (spec.n_coarse, spec.n_coarse)
+    coarse = acm.Solver(spec.coarse_config(), {k: np.zeros(shape_c) for k in ("drho", "u", "v")},
+                        force_x=spec.coarse_force())
+    out = []
+    for win in windows:
+        for k in win[0]:
+            coarse.sets[0][k].copy_(win[0][k])
+        coarse.set_current(0, 0)
+        coarse.step()
+        out.append(({k: coarse.sets[1][k].clone() for k in ("drho", "u", "v")}, win[1]))
+    coarse.close()
+    torch.cuda.synchronize()
+    return out
+
+
+class Unroll:
+    """Training through k corrected coarse steps (solver in the loop):
+    q_j = S(q_{j-1}) + D f(N S(q_{j-1})), loss (1/k) sum_j mean((q_j - F_j)/D)^2
+    over the corrected channels.  The backward pass runs, for j = k .. 1, the
+    state loss of step j, the network backward (weight gradients summed over
+    the steps, and the gradient with respect to the network input) and the
+    adjoint of the SMAME step, all in libacm; the network activations of
+    each step are recomputed from the stored uncorrected state."""
+
+    def __init__(self, spec: FlowSpec, net: Network, k: int):
+        import torch
+        self.torch = torch
+        self.spec, self.net, self.k = spec, net, k
+        dev = net.dev
+        shape = (spec.n_coarse, spec.n_coarse)
+        assert (net.ny, net.nx) == shape
+
+        def state():
+            return {kk: torch.zeros(shape, dtype=torch.float32, device=dev) for kk in ("drho", "u", "v")}
+        self.q = [state() for _ in range(k + 1)]   # q_0 .. q_k
+        self.s = [None] + [state() for _ in range(k)]   # s_1 .. s_k (uncorrected)
+        self.lam = [state(), state()]
+        self.gin = torch.zeros((shape[0], shape[1], 16), dtype=torch.float32, device=dev)
+        self.zero16 = torch.zeros(16, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.solver = acm.Solver(spec.coarse_config(), None, tensors=[state(), state()],
+                                 force_x=spec.coarse_force())
+
+    def close(self):
+        self.solver.close()
+
+    def _step(self, src, dst):
+        for kk in src:
+            self.solver.sets[0][kk].copy_(src[kk])
+        self.solver.set_current(0, 0)
+        self.solver.step()
+        for kk in dst:
+            dst[kk].copy_(self.solver.sets[1][kk])
+
+    def forward(self, q0):
+        net = self.net
+        for kk in q0:
+            self.q[0][kk].copy_(q0[kk])
+        for j in range(1, self.k + 1):
+            self._step(self.q[j - 1], self.s[j])
+            net.forward(self.s[j]["drho"], self.s[j]["u"], self.s[j]["v"])
+            for kk in self.s[j]:
+                self.q[j][kk].copy_(self.s[j][kk])
+            net.apply(self.q[j]["drho"], self.q[j]["u"], self.q[j]["v"])
+
+    def loss_and_grads(self, q0, targets, adj_q0: bool = False):
+        """Loss of the window and its gradients in net.gw / net.gb (and, with
+        adj_q0, dL/dq_0 in self.adj_q0).  Returns the device loss tensor."""
+        L = acm.lib()
+        net, k = self.net, self.k
+        assert len(targets) == k
+        nx, ny = net.nx, net.ny
+        self.forward(q0)
+        self.loss.zero_()
+        lam, lam_next = self.lam
+        for kk in lam:
+            lam[kk].zero_()
+        first = True
+        for j in range(k, 0, -1):
+            qj = (ctypes.c_void_p * 3)(*[self.q[j][kk].data_ptr() for kk in ("drho", "u", "v")])
+            tj = (ctypes.c_void_p * 3)(*[targets[j - 1][kk].data_ptr() for kk in ("drho", "u", "v")])
+            aj = (ctypes.c_void_p * 3)(*[lam[kk].data_ptr() for kk in ("drho", "u", "v")])
+            acm.check(L.acm_cnn_state_loss(nx, ny, qj, tj, _f3(net.out_scale), 1.0 / k, aj, _vp(net.loss_ws),
+                                           _vp(self.loss), net.stream))
+            # lam = dL/dq_j; the correction adds D raw, so dL/draw = D lam
+            sj = self.s[j]
+            net.forward(sj["drho"], sj["u"], sj["v"])
+            acm.check(L.acm_cnn_pack(nx, ny, _vp(lam["drho"]), _vp(lam["u"]), _vp(lam["v"]), _f3(net.out_scale),
+                                     _vp(net.gout), net.stream))
+            g = net.gout
+            wg = L.acm_cnn_wgrad if first else L.acm_cnn_wgrad_add
+            for l in range(LAYERS - 1, -1, -1):
+                ci, co = net.shapes[l]
+                acm.check(wg(nx, ny, ci, co, _vp(net.acts[l]), _vp(g), _vp(net.wg_ws), _vp(net.gw[l]),
+                             _vp(net.gb[l]), net.stream))
+                if l > 0:
+                    gx = net.gacts[l - 1]
+                    acm.check(L.acm_cnn_conv(nx, ny, co, ci, CONV_MASK, _vp(g), _vp(net.wt16[l]), None,
+                                             _vp(net.acts[l]), _vp(gx), net.stream))
+                    g = gx
+            first = False
+            # gradient with respect to the network input, then through N
+            ci0, co0 = net.shapes[0]
+            acm.check(L.acm_cnn_conv(nx, ny, co0, ci0, CONV_RAW, _vp(g), _vp(net.wt16[0]), _vp(self.zero16), None,
+                                     _vp(self.gin), net.stream))
+            acm.check(L.acm_cnn_apply(nx, ny, _vp(self.gin), _f3(net.in_scale), _vp(lam["drho"]), _vp(lam["u"]),
+                                      _vp(lam["v"]), net.stream))
+            # lam = dL/ds_j; through the step to dL/dq_{j-1}
+            if j > 1 or adj_q0:
+                self.solver.adjoint(self.q[j - 1], sj, lam, lam_next)
+                lam, lam_next = lam_next, lam
+        self.adj_q0 = lam if adj_q0 else None
+        return self.loss
+
+    def train_step(self, q0, targets, lr: float):
+        loss = self.loss_and_grads(q0, targets)
+        self.net.adam(lr)
+        return loss
+
+
+def train_unrolled(net: Network, spec: FlowSpec, windows, k: int, epochs: int, lr: float, seed: int = 0,
+                   lr_decay: float = 1.0, log=None):
+    """Adam epochs of training through k steps over every window (the first
+    k + 1 states of each are used)."""
+    un = Unroll(spec, net, k)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    losses = []
+    try:
+        for ep in range(epochs):
+            order = rng.permutation(len(windows))
+            tot = 0.0
+            for i in order:
+                win = windows[i]
+                loss = un.train_step(win[0], win[1:k + 1], lr)
+                tot += float(loss.item()) if log is not None else 0.0
+            losses.append(tot / len(windows))
+            if log is not None:
+                log(f"unrolled epoch {ep} (k = {k}): mean loss {losses[-1]:.4e} lr {lr:.2e}")
+            lr *= lr_decay
+    finally:
+        un.close()
+    return losses
+
+
 @dataclass
 class GateResult:
     tripped: bool

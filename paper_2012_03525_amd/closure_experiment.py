@@ -45,9 +45,18 @@ def run_experiment(preset: str = "full", log=print, train_seeds=None, eval_seeds
     spec = closure.FlowSpec(**p["spec"])
     tr = range(*(train_seeds or p["train_seeds"]))
     ev = range(*(eval_seeds or p["eval_seeds"]))
+    k_unroll = int(p.get("unroll", 0))
     t0 = time.perf_counter()
-    pairs = closure.generate_pairs(spec, tr, warmup=p["warmup"], pairs_per_seed=p["pairs_per_seed"],
-                                   stride=p["stride"])
+    windows = None
+    if k_unroll:
+        # one set of trajectory windows serves both training stages: the
+        # one-step pairs are (S_c(F_0), F_1) of each window
+        windows = closure.generate_windows(spec, tr, warmup=p["warmup"], windows_per_seed=p["pairs_per_seed"],
+                                           stride=p["stride"], k=k_unroll)
+        pairs = closure.pairs_from_windows(spec, windows)
+    else:
+        pairs = closure.generate_pairs(spec, tr, warmup=p["warmup"], pairs_per_seed=p["pairs_per_seed"],
+                                       stride=p["stride"])
     t_gen = time.perf_counter() - t0
     n_in, d_out = closure.channel_scales(pairs)
     log(f"{len(pairs)} pairs from {len(tr)} seeds in {t_gen:.1f} s; N = {n_in}, D = {d_out}")
@@ -56,9 +65,14 @@ def run_experiment(preset: str = "full", log=print, train_seeds=None, eval_seeds
     # plain coarse step's residual in units of D
     t0 = time.perf_counter()
     losses = closure.train(net, pairs, epochs or p["epochs"], p["lr"], seed=0, lr_decay=p["lr_decay"], log=log)
+    del pairs
+    unroll_losses = []
+    if k_unroll:
+        unroll_losses = closure.train_unrolled(net, spec, windows, k_unroll, p["unroll_epochs"], p["unroll_lr"],
+                                               seed=1, lr_decay=p.get("unroll_lr_decay", 1.0), log=log)
+        del windows
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    del pairs
     results = []
     for seed in ev:
         r = closure.evaluate_seed(spec, net, seed, warmup=p["warmup"], coarse_steps=p["coarse_steps"])
@@ -77,6 +91,7 @@ def run_experiment(preset: str = "full", log=print, train_seeds=None, eval_seeds
         "preset": preset, "spec": asdict(spec), "train_seeds": [tr.start, tr.stop], "eval_seeds": [ev.start, ev.stop],
         "coarse_steps": p["coarse_steps"], "fine_steps": p["coarse_steps"] * spec.ratio,
         "t_generate_s": t_gen, "t_train_s": t_train, "epoch_loss": losses,
+        "unroll": k_unroll, "unroll_epoch_loss": unroll_losses,
         "mean_err_plain_end": mean("err_plain_end"), "mean_err_plain_max": mean("err_plain_max"),
         "mean_err_closure_end": mean("err_cnn_end"), "mean_err_closure_max": mean("err_cnn_max"),
         "max_err_closure_max": float(max(r["err_cnn_max"] for r in results)),

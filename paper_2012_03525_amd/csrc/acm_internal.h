@@ -163,6 +163,12 @@ template <typename T>
 hipError_t launch_twophase3d(const Coef<T>& c, const State<T>& in, const State<T>& out, T* scratch, int tile,
                              hipStream_t s);
 
+// adjoint of one 2D single-phase step on a fully periodic grid (kern_adjoint.hip):
+// aq = (dS/dq)^T as at state q, with s = S(q)
+template <typename T>
+hipError_t launch_adjoint2d(const Coef<T>& c, const State<T>& q, const State<T>& s, const State<T>& as,
+                            const State<T>& aq, hipStream_t st);
+
 // number of FP64 quantities reduced by the diagnostics kernel
 constexpr int NDIAG = 14;
 template <typename T>

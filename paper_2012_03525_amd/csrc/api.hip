@@ -429,6 +429,32 @@ acm_status acm_set_current(acm_handle* h, int32_t which, int64_t step)
     return ACM_OK;
 }
 
+acm_status acm_step_adjoint(acm_handle* h, const acm_fields* q, const acm_fields* s, const acm_fields* adj_s,
+                            const acm_fields* adj_q)
+{
+    if (!h || !q || !s || !adj_s || !adj_q) return fail(ACM_EINVAL, "NULL argument");
+    if (h->cfg.dim != 2 || h->cfg.two_phase || h->cf.nonperiodic)
+        return fail(ACM_EINVAL, "the adjoint step covers 2D single-phase runs on fully periodic grids");
+    const acm_fields* all[4] = {q, s, adj_s, adj_q};
+    for (const acm_fields* f : all)
+        if (!f->drho || !f->u || !f->v) return fail(ACM_EINVAL, "NULL field");
+    const void* outs[3] = {adj_q->drho, adj_q->u, adj_q->v};
+    for (const void* o : outs)
+        for (int k = 0; k < 3; ++k) {
+            const void* ins[3] = {all[k]->drho, all[k]->u, all[k]->v};
+            for (const void* in : ins)
+                if (o == in) return fail(ACM_EINVAL, "adj_q must not alias q, s or adj_s");
+        }
+    hipError_t e;
+    if (h->cfg.precision == ACM_F64)
+        e = launch_adjoint2d<double>(h->cd, state_of<double>(*q), state_of<double>(*s), state_of<double>(*adj_s),
+                                     state_of<double>(*adj_q), h->stream);
+    else
+        e = launch_adjoint2d<float>(h->cf, state_of<float>(*q), state_of<float>(*s), state_of<float>(*adj_s),
+                                    state_of<float>(*adj_q), h->stream);
+    return e == hipSuccess ? ACM_OK : hip_fail(e, "adjoint launch");
+}
+
 void acm_destroy(acm_handle* h)
 {
     if (!h) return;

@@ -239,15 +239,17 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(int H, int W, const bf1
 }
 
 // fixed-order sum of the per-workgroup partials: out[e] = sum_b partial[b][e]
+// (acc: out[e] += that sum)
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ partial, int nblk, int n,
-                                                              float* __restrict__ dw, float* __restrict__ db, int nw)
+                                                              float* __restrict__ dw, float* __restrict__ db, int nw,
+                                                              int acc)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
     float s = 0.f;
     for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * n + e];
-    if (e < nw) dw[e] = s;
-    else db[e - nw] = s;
+    float* dst = e < nw ? &dw[e] : &db[e - nw];
+    *dst = acc ? *dst + s : s;
 }
 
 // wt[t][i][o] = w[8 - t][o][i]: weights of the transposed convolution
@@ -339,6 +341,47 @@ __global__ void loss_final_kernel(const double* __restrict__ partial, int nblk, 
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += partial[b];
     out[0] = s / count;
+}
+
+// loss of a state against its target, for training through several steps:
+// e_c = (q_c - t_c) / d_c on the active channels; adj_c += k e_c / d_c with
+// k = 2 weight / (n_active n); per-block sum of e^2
+__global__ __launch_bounds__(256) void state_loss_kernel(int n, const float* __restrict__ q0,
+                                                         const float* __restrict__ q1, const float* __restrict__ q2,
+                                                         const float* __restrict__ t0, const float* __restrict__ t1,
+                                                         const float* __restrict__ t2, LossChannels lc, float k,
+                                                         float* __restrict__ a0, float* __restrict__ a1,
+                                                         float* __restrict__ a2, double* __restrict__ partial)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    double se = 0.0;
+    if (p < n) {
+        const float e0 = lc.w[0] * (q0[p] - t0[p]) * lc.id[0];
+        const float e1 = lc.w[1] * (q1[p] - t1[p]) * lc.id[1];
+        const float e2 = lc.w[2] * (q2[p] - t2[p]) * lc.id[2];
+        se = (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
+        a0[p] = fmaf(k * e0, lc.id[0], a0[p]);
+        a1[p] = fmaf(k * e1, lc.id[1], a1[p]);
+        a2[p] = fmaf(k * e2, lc.id[2], a2[p]);
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = se;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// out += scale * (fixed-order sum of the partials)
+__global__ void loss_accumulate_kernel(const double* __restrict__ partial, int nblk, double scale,
+                                       double* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[b];
+    out[0] += s * scale;
 }
 
 // Adam (Kingma & Ba) with bias correction; p16 (optional) receives bf16(p)
@@ -799,8 +842,8 @@ size_t acm_cnn_wgrad_workspace(int32_t nx, int32_t ny, int32_t cin, int32_t cout
     return nblk * (size_t)(9 * cout * cin + cout) * sizeof(float);
 }
 
-acm_status acm_cnn_wgrad(int32_t nx, int32_t ny, int32_t cin, int32_t cout, const void* x, const void* g,
-                         float* workspace, float* dw, float* db, void* stream)
+static acm_status wgrad_impl(int32_t nx, int32_t ny, int32_t cin, int32_t cout, const void* x, const void* g,
+                             float* workspace, float* dw, float* db, void* stream, int acc)
 {
     if (!grid_ok(nx, ny)) return cfail(ACM_EINVAL, "network grids need nx % 64 == 0 and ny % 8 == 0");
     if (!x || !g || !workspace || !dw || !db) return cfail(ACM_EINVAL, "NULL pointer");
@@ -820,8 +863,20 @@ acm_status acm_cnn_wgrad(int32_t nx, int32_t ny, int32_t cin, int32_t cout, cons
     if (st != ACM_OK) return st;
     const int n = 9 * cout * cin + cout;
     hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(n)), dim3(256), 0, s, workspace, nblk, n, dw, db,
-                       9 * cout * cin);
+                       9 * cout * cin, acc);
     return chip(hipGetLastError(), "reduce launch");
+}
+
+acm_status acm_cnn_wgrad(int32_t nx, int32_t ny, int32_t cin, int32_t cout, const void* x, const void* g,
+                         float* workspace, float* dw, float* db, void* stream)
+{
+    return wgrad_impl(nx, ny, cin, cout, x, g, workspace, dw, db, stream, 0);
+}
+
+acm_status acm_cnn_wgrad_add(int32_t nx, int32_t ny, int32_t cin, int32_t cout, const void* x, const void* g,
+                             float* workspace, float* dw, float* db, void* stream)
+{
+    return wgrad_impl(nx, ny, cin, cout, x, g, workspace, dw, db, stream, 1);
 }
 
 acm_status acm_cnn_transpose(int32_t cin, int32_t cout, const void* w, void* wt, void* stream)
@@ -876,6 +931,36 @@ acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* c
     if (st != ACM_OK) return st;
     hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, workspace, nb, (double)lc.nact * n, loss);
     return chip(hipGetLastError(), "loss final launch");
+}
+
+acm_status acm_cnn_state_loss(int32_t nx, int32_t ny, const float* const* q, const float* const* target,
+                              const float* out_scale, float weight, float* const* adj, double* workspace,
+                              double* loss, void* stream)
+{
+    if (!q || !target || !out_scale || !adj || !workspace || !loss) return cfail(ACM_EINVAL, "NULL pointer");
+    if (nx <= 0 || ny <= 0) return cfail(ACM_EINVAL, "bad grid");
+    for (int c = 0; c < 3; ++c)
+        if (!q[c] || !target[c] || !adj[c]) return cfail(ACM_EINVAL, "NULL field");
+    if (!std::isfinite(weight)) return cfail(ACM_EINVAL, "weight must be finite");
+    LossChannels lc{};
+    for (int c = 0; c < 3; ++c) {
+        if (!(out_scale[c] >= 0.f) || !std::isfinite(out_scale[c])) return cfail(ACM_EINVAL, "out_scale must be >= 0");
+        lc.w[c] = out_scale[c] > 0.f ? 1.f : 0.f;
+        lc.id[c] = out_scale[c] > 0.f ? 1.f / out_scale[c] : 0.f;
+        lc.nact += out_scale[c] > 0.f;
+    }
+    if (lc.nact == 0) return cfail(ACM_EINVAL, "every output channel is excluded");
+    const int n = nx * ny;
+    const int nb = blocks_for(n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const float k = 2.f * weight / ((float)lc.nact * (float)n);
+    hipLaunchKernelGGL(state_loss_kernel, dim3(nb), dim3(256), 0, s, n, q[0], q[1], q[2], target[0], target[1],
+                       target[2], lc, k, adj[0], adj[1], adj[2], workspace);
+    acm_status st = chip(hipGetLastError(), "state loss launch");
+    if (st != ACM_OK) return st;
+    hipLaunchKernelGGL(loss_accumulate_kernel, dim3(1), dim3(64), 0, s, workspace, nb,
+                       (double)weight / ((double)lc.nact * n), loss);
+    return chip(hipGetLastError(), "state loss final launch");
 }
 
 acm_status acm_cnn_adam(int64_t n, float* p, const float* g, float* m, float* v, void* p16, float lr, float b1,

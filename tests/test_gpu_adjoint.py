@@ -1,0 +1,186 @@
+"""GPU parity of training through the solver: the adjoint step kernel
+against the FP64 oracle's vector-Jacobian product (FP64 and FP32, ragged
+and multi-tile grids, the 256^2 closure grid), its argument checks, the
+state loss, the accumulating weight gradient, and the whole k-step
+unrolled gradient against the oracle's autograd of the same composition."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2012_03525_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("drho", "u", "v")
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import oracle
+    from oracle import adjoint
+    from paper_2012_03525_amd import acm, closure
+    acm.lib()
+    oracle.lib()
+    return torch, acm, closure, oracle, adjoint
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_adjoint(env, nx, ny, precision, seed, nu=0.04, g=(2e-5, -1e-5), force=True):
+    torch, acm, _, oracle, adjoint = env
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    fx = 3e-5 * np.sin(2 * np.pi * 3 * np.arange(ny) / ny + 0.2) if force else None
+    cfg = acm.make_config(2, nx, ny, nu=nu, precision=precision, g=(g[0], g[1], 0.0))
+    q = inputs.seeded_state((ny, nx), seed=seed, scale_u=0.05, scale_r=2e-3)
+    if precision == "f32":
+        q = {k: v.astype(np.float32).astype(np.float64) for k, v in q.items()}
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    a = {k: rng.standard_normal((ny, nx)) for k in KEYS}
+    if precision == "f32":
+        a = {k: v.astype(np.float32).astype(np.float64) for k, v in a.items()}
+    sol = acm.Solver(cfg, q, force_x=fx)
+    print(f"adjoint {precision} {nx}x{ny} seed {seed}", flush=True)
+    qd = {k: sol.sets[0][k].clone() for k in KEYS}
+    sol.step()
+    sd = sol.tensors()
+    ad = {k: torch.from_numpy(a[k]).to(device=dev, dtype=dtype) for k in KEYS}
+    out = {k: torch.full((ny, nx), float("nan"), dtype=dtype, device=dev) for k in KEYS}
+    sol.adjoint(qd, sd, ad, out)
+    torch.cuda.synchronize()
+    got = {k: out[k].double().cpu().numpy() for k in KEYS}
+    p = oracle.Params(dim=2, nx=nx, ny=ny, nu=nu, g=(g[0], g[1], 0.0))
+    ref = adjoint.step2d_vjp(p, q, a, force_x_row=fx)
+    sol.close()
+    return got, ref
+
+
+@pytest.mark.parametrize("nx,ny", [(100, 37), (64, 8), (20, 12), (192, 96)])
+def test_adjoint_f64_matches_oracle(env, nx, ny):
+    got, ref = run_adjoint(env, nx, ny, "f64", seed=nx + ny)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) <= 1e-12, k
+
+
+@pytest.mark.parametrize("nx,ny", [(100, 37), (256, 256)])
+def test_adjoint_f32_matches_oracle(env, nx, ny):
+    got, ref = run_adjoint(env, nx, ny, "f32", seed=3 * nx + ny)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) <= 1e-5, k
+
+
+def test_adjoint_without_force_or_body_force(env):
+    got, ref = run_adjoint(env, 64, 16, "f64", seed=7, g=(0.0, 0.0), force=False)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) <= 1e-12, k
+
+
+def test_adjoint_rejects_unsupported(env):
+    torch, acm, _, _, _ = env
+    dev = torch.device("cuda:0")
+    st = inputs.seeded_state((16, 16), seed=1)
+    walls = acm.Solver(acm.make_config(2, 16, 16, nu=0.05, precision="f64", bc=(0, 0, 1, 1, 0, 0)), st)
+    t = [{k: torch.zeros((16, 16), dtype=torch.float64, device=dev) for k in KEYS} for _ in range(4)]
+    with pytest.raises(acm.AcmError):
+        walls.adjoint(*t)
+    walls.close()
+    per = acm.Solver(acm.make_config(2, 16, 16, nu=0.05, precision="f64"), st)
+    with pytest.raises(acm.AcmError):   # output aliases the cotangent
+        per.adjoint(t[0], t[1], t[2], t[2])
+    per.adjoint(*t)  # valid call: zero cotangent gives zero adjoint
+    torch.cuda.synchronize()
+    assert all(float(t[3][k].abs().max()) == 0.0 for k in KEYS)
+    per.close()
+
+
+def test_state_loss_accumulates(env):
+    torch, acm, closure, _, _ = env
+    dev = torch.device("cuda:0")
+    nx, ny = 64, 24
+    rng = np.random.Generator(np.random.PCG64(5))
+    q = {k: rng.standard_normal((ny, nx)).astype(np.float32) for k in KEYS}
+    t = {k: rng.standard_normal((ny, nx)).astype(np.float32) for k in KEYS}
+    a0 = {k: rng.standard_normal((ny, nx)).astype(np.float32) for k in KEYS}
+    D = [0.0, 0.5, 2.0]
+    w = 0.25
+    dq = {k: torch.from_numpy(v).to(dev) for k, v in q.items()}
+    dt_ = {k: torch.from_numpy(v).to(dev) for k, v in t.items()}
+    da = {k: torch.from_numpy(v).to(dev) for k, v in a0.items()}
+    L = acm.lib()
+    ws = torch.zeros(L.acm_cnn_loss_workspace(nx, ny) // 8 + 1, dtype=torch.float64, device=dev)
+    loss = torch.full((1,), 3.0, dtype=torch.float64, device=dev)
+    arr = lambda d: (ctypes.c_void_p * 3)(*[d[k].data_ptr() for k in KEYS])
+    acm.check(L.acm_cnn_state_loss(nx, ny, arr(dq), arr(dt_), closure._f3(D), w, arr(da), ctypes.c_void_p(ws.data_ptr()),
+                                   ctypes.c_void_p(loss.data_ptr()), None))
+    torch.cuda.synchronize()
+    e = {c: (q[KEYS[c]].astype(np.float64) - t[KEYS[c]]) / D[c] for c in (1, 2)}
+    ref_loss = 3.0 + w * sum(float((e[c] ** 2).sum()) for c in (1, 2)) / (2 * nx * ny)
+    assert abs(float(loss.item()) - ref_loss) <= 1e-6 * ref_loss
+    np.testing.assert_array_equal(da["drho"].cpu().numpy(), a0["drho"])
+    for c in (1, 2):
+        ref = a0[KEYS[c]] + w * 2.0 * e[c] / (D[c] * 2 * nx * ny)
+        np.testing.assert_allclose(da[KEYS[c]].cpu().numpy(), ref, rtol=1e-5, atol=1e-7)
+    with pytest.raises(acm.AcmError):
+        acm.check(L.acm_cnn_state_loss(nx, ny, arr(dq), arr(dt_), closure._f3([0.0, 0.0, 0.0]), w, arr(da),
+                                       ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(loss.data_ptr()), None))
+
+
+def test_wgrad_add_accumulates(env):
+    torch, acm, closure, _, _ = env
+    dev = torch.device("cuda:0")
+    nx, ny = 64, 16
+    rng = np.random.Generator(np.random.PCG64(6))
+    x = torch.from_numpy(rng.standard_normal((ny, nx, 32)).astype(np.float32)).to(dev).to(torch.bfloat16)
+    g = torch.from_numpy(rng.standard_normal((ny, nx, 32)).astype(np.float32)).to(dev).to(torch.bfloat16)
+    L = acm.lib()
+    ws = torch.zeros(L.acm_cnn_wgrad_workspace(nx, ny, 32, 32) // 4 + 1, dtype=torch.float32, device=dev)
+    dw1, db1 = torch.zeros((9, 32, 32), device=dev), torch.zeros(32, device=dev)
+    dw2, db2 = torch.full((9, 32, 32), 1.5, device=dev), torch.full((32,), -2.0, device=dev)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    acm.check(L.acm_cnn_wgrad(nx, ny, 32, 32, vp(x), vp(g), vp(ws), vp(dw1), vp(db1), None))
+    acm.check(L.acm_cnn_wgrad_add(nx, ny, 32, 32, vp(x), vp(g), vp(ws), vp(dw2), vp(db2), None))
+    torch.cuda.synchronize()
+    assert torch.equal(dw2, dw1 + 1.5)
+    assert torch.equal(db2, db1 - 2.0)
+
+
+def test_unrolled_gradient_matches_oracle(env):
+    """k = 3 corrected steps on a 64^2 coarse grid of the forced flow: loss,
+    every layer's weight gradient and dL/dq0 from the library (bf16 network)
+    against the FP64 oracle with the same bf16-rounded weights."""
+    torch, acm, closure, oracle, adjoint = env
+    spec = closure.FlowSpec(n_fine=256)
+    n = spec.n_coarse
+    k = 3
+    print(f"unrolled gradient k={k} n={n}", flush=True)
+    net = closure.Network(n, n, seed=3, in_scale=[300.0, 25.0, 25.0], out_scale=[0.0, 2e-3, 2e-3])
+    params = closure.he_init(3, last_scale=0.5)
+    net.load(params)
+    p16 = [[torch.from_numpy(w).to(torch.bfloat16).double().numpy(), b] for w, b in params]
+    q0 = inputs.seeded_state((n, n), seed=21, scale_u=0.04, scale_r=1e-3)
+    tg = [inputs.seeded_state((n, n), seed=22 + j, scale_u=0.04, scale_r=1e-3) for j in range(k)]
+    q0 = {kk: v.astype(np.float32).astype(np.float64) for kk, v in q0.items()}
+    tg = [{kk: v.astype(np.float32).astype(np.float64) for kk, v in t.items()} for t in tg]
+    dev = net.dev
+    td = lambda d: {kk: torch.from_numpy(v).to(device=dev, dtype=torch.float32) for kk, v in d.items()}
+    un = closure.Unroll(spec, net, k)
+    loss = un.loss_and_grads(td(q0), [td(t) for t in tg], adj_q0=True)
+    torch.cuda.synchronize()
+    p = oracle.Params(dim=2, nx=n, ny=n, nu=spec.nu_fine / spec.ratio)
+    ref_loss, ref_g, ref_q, _ = adjoint.unrolled_loss(p, p16, net.in_scale, net.out_scale, q0, tg,
+                                                      force_x_row=spec.coarse_force())
+    assert abs(float(loss.item()) - ref_loss) <= 0.02 * ref_loss
+    for l in range(closure.LAYERS):
+        ci, co = closure.REAL_CHANNELS[l], closure.REAL_CHANNELS[l + 1]
+        gw = net.gw[l][:, :co, :ci].double().cpu().numpy()
+        gb = net.gb[l][:co].double().cpu().numpy()
+        assert rel(gw, ref_g[l][0]) <= 5e-2, l
+        assert rel(gb, ref_g[l][1]) <= 5e-2, l
+    for kk in ("u", "v"):
+        assert rel(un.adj_q0[kk].double().cpu().numpy(), ref_q[kk]) <= 5e-2, kk
+    un.close()
