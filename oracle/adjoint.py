@@ -22,7 +22,9 @@ The unrolled closure loss composes k corrected coarse steps,
 q_j = S(q_{j-1}) + D f(N S(q_{j-1})), with the five-layer network of
 `cnn.py` (written here with torch's conv2d on circularly padded input), and
 averages the normalised squared error of q_j against the targets F_j over
-the steps, pixels and the channels with D_c > 0.
+the steps, pixels and the channels with D_c > 0.  An optional term
+div_weight * mean(div(q_j - S(q_{j-1}))^2), with div the centred divergence
+(2.12) of the velocity, penalises the compressive part of each correction.
 """
 from __future__ import annotations
 
@@ -133,13 +135,30 @@ def network(params_t, x: torch.Tensor) -> torch.Tensor:
     return h
 
 
+def divergence(p: Params, u: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
+    """Centred divergence G_x u + G_y v (2.12) on a periodic grid."""
+    return (_E(u) - _W(u) + _N(v) - _S(v)) / (2.0 * p.dx)
+
+
+def div_penalty(p: Params, a: Dict[str, np.ndarray], b: Dict[str, np.ndarray], weight: float):
+    """weight * mean(div(a - b)^2) and its gradients with respect to the
+    velocity of a and of b (numpy dicts u, v)."""
+    xs = [_t(a[k]).requires_grad_(True) for k in ("u", "v")] + [_t(b[k]).requires_grad_(True) for k in ("u", "v")]
+    d = divergence(p, xs[0] - xs[2], xs[1] - xs[3])
+    val = weight * (d * d).mean()
+    g = torch.autograd.grad(val, xs)
+    return (float(val.detach()), {"u": g[0].numpy(), "v": g[1].numpy()},
+            {"u": g[2].numpy(), "v": g[3].numpy()})
+
+
 def unrolled_loss(p: Params, params, in_scale: Sequence[float], out_scale: Sequence[float],
                   q0: Dict[str, np.ndarray], targets: Sequence[Dict[str, np.ndarray]], force_x_row=None,
-                  grads: bool = True):
-    """Loss (1/k) sum_j mean_{pixels, c: D_c > 0} ((q_j - F_j)_c / D_c)^2 of k
-    corrected steps from q0, with its gradients with respect to every layer's
-    (w, b) [numpy, real channels] and to q0.  Returns (loss, grads, adj_q0,
-    states) where states are q_1..q_k."""
+                  grads: bool = True, div_weight: float = 0.0):
+    """Loss (1/k) sum_j [mean_{pixels, c: D_c > 0} ((q_j - F_j)_c / D_c)^2
+    + div_weight mean(div(q_j - s_j)^2)] of k corrected steps from q0
+    (s_j = S(q_{j-1}), the uncorrected step), with its gradients with respect
+    to every layer's (w, b) [numpy, real channels] and to q0.  Returns (loss,
+    grads, adj_q0, states) where states are q_1..q_k."""
     fx = None if force_x_row is None else _t(force_x_row)
     pt = [(_t(w).requires_grad_(grads), _t(b).requires_grad_(grads)) for w, b in params]
     q = [_t(q0[k]).requires_grad_(grads) for k in ("drho", "u", "v")]
@@ -158,6 +177,9 @@ def unrolled_loss(p: Params, params, in_scale: Sequence[float], out_scale: Seque
         states.append({kk: t.detach().numpy().copy() for kk, t in zip(("drho", "u", "v"), q)})
         se = sum((((q[c] - _t(tgt[("drho", "u", "v")[c]])) / ds[c]) ** 2).sum() for c in active)
         loss = loss + se / (len(active) * q[0].numel())
+        if div_weight:
+            d = divergence(p, q[1] - s[1], q[2] - s[2])
+            loss = loss + div_weight * (d * d).mean()
     loss = loss / k
     if not grads:
         return float(loss.detach()), None, None, states

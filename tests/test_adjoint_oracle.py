@@ -188,3 +188,58 @@ def test_unrolled_gradients_match_central_differences(orc, adj):
                               grads=False)[0]) / (2 * h)
     an = sum(float((gq[k] * dq[k]).sum()) for k in KEYS)
     assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+def test_div_penalty_closed_form(orc, adj):
+    """A single Fourier mode u = A cos(2 pi m x / nx) has centred divergence
+    -A sin(2 pi m x / nx) sin(2 pi m / nx) / dx, so mean(div^2) =
+    A^2 sin^2(2 pi m / nx) / (2 dx^2); the gradient equals central
+    differences of the penalty."""
+    nx, ny, m, A = 16, 8, 3, 0.7
+    p = params2d(orc, nx, ny)
+    x = np.arange(nx)
+    a = {"u": np.tile(A * np.cos(2 * np.pi * m * x / nx), (ny, 1)), "v": np.zeros((ny, nx))}
+    b = {"u": np.zeros((ny, nx)), "v": np.zeros((ny, nx))}
+    val, ga, gb = adj.div_penalty(p, a, b, 2.0)
+    assert abs(val - 2.0 * A * A * np.sin(2 * np.pi * m / nx) ** 2 / 2.0) <= 1e-14
+    rng = np.random.Generator(np.random.PCG64(30))
+    a = {k: rng.standard_normal((ny, nx)) for k in ("u", "v")}
+    b = {k: rng.standard_normal((ny, nx)) for k in ("u", "v")}
+    val, ga, gb = adj.div_penalty(p, a, b, 0.3)
+    d = {k: rng.standard_normal((ny, nx)) for k in ("u", "v")}
+    h = 1e-6
+    fp = adj.div_penalty(p, {k: a[k] + h * d[k] for k in a}, b, 0.3)[0]
+    fm = adj.div_penalty(p, {k: a[k] - h * d[k] for k in a}, b, 0.3)[0]
+    an = sum(float((ga[k] * d[k]).sum()) for k in a)
+    assert abs((fp - fm) / (2 * h) - an) <= 1e-8 * abs(an)
+    for k in ("u", "v"):
+        np.testing.assert_allclose(gb[k], -ga[k], rtol=0, atol=1e-15)
+
+
+def test_unrolled_div_penalty_gradient(orc, adj):
+    """k = 2 with the divergence penalty: weight gradients against central
+    differences of the loss (h = 1e-7)."""
+    nx, ny = 16, 8
+    p = params2d(orc, nx, ny)
+    fx = force_row(ny)
+    q0 = inputs.seeded_state((ny, nx), seed=31, scale_u=0.05, scale_r=2e-3)
+    targets = [inputs.seeded_state((ny, nx), seed=32 + j, scale_u=0.05, scale_r=2e-3) for j in range(2)]
+    params = _net_params(34)
+    N = [300.0, 20.0, 20.0]
+    D = [0.0, 2e-3, 3e-3]
+    kw = dict(force_x_row=fx, div_weight=5e4)
+    l1, _, _, _ = adj.unrolled_loss(p, params, N, D, q0, targets, grads=False, force_x_row=fx)
+    loss, gp, _, _ = adj.unrolled_loss(p, params, N, D, q0, targets, **kw)
+    assert loss > l1
+    rng = np.random.Generator(np.random.PCG64(35))
+    h = 1e-7
+    for l in (1, 4):
+        d = rng.standard_normal(params[l][0].shape)
+        pp = [[w.copy(), b.copy()] for w, b in params]
+        pm = [[w.copy(), b.copy()] for w, b in params]
+        pp[l][0] += h * d
+        pm[l][0] -= h * d
+        fd = (adj.unrolled_loss(p, pp, N, D, q0, targets, grads=False, **kw)[0]
+              - adj.unrolled_loss(p, pm, N, D, q0, targets, grads=False, **kw)[0]) / (2 * h)
+        an = float((gp[l][0] * d).sum())
+        assert abs(fd - an) <= 1e-6 * abs(an), (l, fd, an)
