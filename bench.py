@@ -194,6 +194,7 @@ def closure_timing(steps: int = 2000):
             "closure_256_step_us": round(t["closure_step_us"], 2),
             "plain_coarse_256_step_us": round(t["plain_coarse_step_us"], 2),
             "closure_256_two_launch_step_us": round(t["closure_separate_launch_step_us"], 2),
+            "adjoint_256_step_us": round(t["adjoint_step_us"], 2),
             "speedup_vs_fine": round(t["fine_steps_per_coarse_step_us"] / t["closure_step_us"], 3)}
 
 

@@ -328,6 +328,16 @@ acm_status acm_cnn_state_loss(int32_t nx, int32_t ny, const float* const* q, con
                               const float* out_scale, float weight, float* const* adj, double* workspace,
                               double* loss, void* stream);
 
+/* Divergence penalty of a correction: d = G.(a - b), the centred divergence
+ * (Eq. 2.12, grid units, periodic) of the velocity difference a - b (a, b:
+ * fp32 u and v fields); *loss += weight * mean(d^2); adj_a[c] += its gradient
+ * with respect to a; adj_b (optional) -= the same.  workspace:
+ * acm_cnn_loss_workspace bytes.  Needs nx, ny >= 3; ACM_EINVAL for NULL
+ * pointers or a non-finite weight. */
+acm_status acm_cnn_div_penalty(int32_t nx, int32_t ny, const float* const* a, const float* const* b, float weight,
+                               float* const* adj_a, float* const* adj_b, double* workspace, double* loss,
+                               void* stream);
+
 /* Adam update of n fp32 parameters (bias-corrected, step t >= 1); p16
  * (optional) receives the bf16 copy used by the convolutions. */
 acm_status acm_cnn_adam(int64_t n, float* p, const float* g, float* m, float* v, void* p16, float lr, float b1,

@@ -117,6 +117,10 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_float),
                                           ctypes.c_float, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "acm_cnn_div_penalty": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.c_float,
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "acm_cnn_adam": (ctypes.c_int, [ctypes.c_int64] + [ctypes.c_void_p] * 5 + [ctypes.c_float] * 4 +
                      [ctypes.c_int64, ctypes.c_void_p]),
     "acm_cnn_to_bf16": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),

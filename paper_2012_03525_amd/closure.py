@@ -374,17 +374,23 @@ def pairs_from_windows(spec: FlowSpec, windows):
 
 class Unroll:
     """Training through k corrected coarse steps (solver in the loop):
-    q_j = S(q_{j-1}) + D f(N S(q_{j-1})), loss (1/k) sum_j mean((q_j - F_j)/D)^2
-    over the corrected channels.  The backward pass runs, for j = k .. 1, the
-    state loss of step j, the network backward (weight gradients summed over
-    the steps, and the gradient with respect to the network input) and the
-    adjoint of the SMAME step, all in libacm; the network activations of
-    each step are recomputed from the stored uncorrected state."""
+    q_j = s_j + D f(N s_j), s_j = S(q_{j-1}), loss (1/k) sum_j [mean((q_j -
+    F_j)/D)^2 over the corrected channels + div_beta mean((div(q_j - s_j) /
+    D_vel)^2)], the last term penalising the compressive part of each
+    correction (centred divergence, grid units; D_vel the mean output scale
+    of the velocity channels, so div_beta is dimensionless).  The backward
+    pass runs, for j = k .. 1, the state loss of step j, the network
+    backward (weight gradients summed over the steps, and the gradient with
+    respect to the network input) and the adjoint of the SMAME step, all in
+    libacm; the network activations of each step are recomputed from the
+    stored uncorrected state."""
 
-    def __init__(self, spec: FlowSpec, net: Network, k: int):
+    def __init__(self, spec: FlowSpec, net: Network, k: int, div_beta: float = 0.0):
         import torch
         self.torch = torch
         self.spec, self.net, self.k = spec, net, k
+        d_vel = 0.5 * (net.out_scale[1] + net.out_scale[2])
+        self.div_weight = float(div_beta) / (d_vel * d_vel) if div_beta else 0.0
         dev = net.dev
         shape = (spec.n_coarse, spec.n_coarse)
         assert (net.ny, net.nx) == shape
@@ -397,6 +403,7 @@ class Unroll:
         self.gin = torch.zeros((shape[0], shape[1], 16), dtype=torch.float32, device=dev)
         self.zero16 = torch.zeros(16, dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.loss_dummy = torch.zeros(1, dtype=torch.float64, device=dev)
         self.solver = acm.Solver(spec.coarse_config(), None, tensors=[state(), state()],
                                  force_x=spec.coarse_force())
 
@@ -441,8 +448,14 @@ class Unroll:
             aj = (ctypes.c_void_p * 3)(*[lam[kk].data_ptr() for kk in ("drho", "u", "v")])
             acm.check(L.acm_cnn_state_loss(nx, ny, qj, tj, _f3(net.out_scale), 1.0 / k, aj, _vp(net.loss_ws),
                                            _vp(self.loss), net.stream))
-            # lam = dL/dq_j; the correction adds D raw, so dL/draw = D lam
             sj = self.s[j]
+            if self.div_weight:
+                qv = (ctypes.c_void_p * 2)(self.q[j]["u"].data_ptr(), self.q[j]["v"].data_ptr())
+                sv = (ctypes.c_void_p * 2)(sj["u"].data_ptr(), sj["v"].data_ptr())
+                av = (ctypes.c_void_p * 2)(lam["u"].data_ptr(), lam["v"].data_ptr())
+                acm.check(L.acm_cnn_div_penalty(nx, ny, qv, sv, self.div_weight / k, av, None, _vp(net.loss_ws),
+                                                _vp(self.loss), net.stream))
+            # lam = dL/dq_j; the correction adds D raw, so dL/draw = D lam
             net.forward(sj["drho"], sj["u"], sj["v"])
             acm.check(L.acm_cnn_pack(nx, ny, _vp(lam["drho"]), _vp(lam["u"]), _vp(lam["v"]), _f3(net.out_scale),
                                      _vp(net.gout), net.stream))
@@ -464,6 +477,9 @@ class Unroll:
                                      _vp(self.gin), net.stream))
             acm.check(L.acm_cnn_apply(nx, ny, _vp(self.gin), _f3(net.in_scale), _vp(lam["drho"]), _vp(lam["u"]),
                                       _vp(lam["v"]), net.stream))
+            if self.div_weight:  # the penalty's own dependence on s_j (div(s - q) = -div(q - s))
+                acm.check(L.acm_cnn_div_penalty(nx, ny, sv, qv, self.div_weight / k, av, None, _vp(net.loss_ws),
+                                                _vp(self.loss_dummy), net.stream))
             # lam = dL/ds_j; through the step to dL/dq_{j-1}
             if j > 1 or adj_q0:
                 self.solver.adjoint(self.q[j - 1], sj, lam, lam_next)
@@ -478,10 +494,10 @@ class Unroll:
 
 
 def train_unrolled(net: Network, spec: FlowSpec, windows, k: int, epochs: int, lr: float, seed: int = 0,
-                   lr_decay: float = 1.0, log=None):
+                   lr_decay: float = 1.0, div_beta: float = 0.0, log=None):
     """Adam epochs of training through k steps over every window (the first
     k + 1 states of each are used)."""
-    un = Unroll(spec, net, k)
+    un = Unroll(spec, net, k, div_beta)
     rng = np.random.Generator(np.random.PCG64(seed))
     losses = []
     try:

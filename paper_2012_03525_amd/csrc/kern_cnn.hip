@@ -374,6 +374,60 @@ __global__ __launch_bounds__(256) void state_loss_kernel(int n, const float* __r
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// divergence penalty of a correction: d = G.(a - b) (centred, periodic, in
+// grid units); per-block sum of d^2; adj_a += k G^T d and adj_b -= k G^T d
+// with k = 2 weight / n.  G^T d at a node is ((d_W - d_E) / 2, (d_S - d_N) / 2),
+// each neighbour's d formed from the four differences around it.
+__device__ __forceinline__ float dcorr(const float* __restrict__ a, const float* __restrict__ b, size_t o)
+{
+    return a[o] - b[o];
+}
+
+__device__ __forceinline__ float div_at(int nx, int ny, int x, int y, const float* __restrict__ au,
+                                        const float* __restrict__ bu, const float* __restrict__ av,
+                                        const float* __restrict__ bv)
+{
+    const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+    const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+    const size_t row = (size_t)y * nx;
+    return 0.5f * ((dcorr(au, bu, row + xe) - dcorr(au, bu, row + xw)) +
+                   (dcorr(av, bv, (size_t)yn * nx + x) - dcorr(av, bv, (size_t)ys * nx + x)));
+}
+
+__global__ __launch_bounds__(256) void div_penalty_kernel(int nx, int ny, const float* __restrict__ au,
+                                                          const float* __restrict__ av, const float* __restrict__ bu,
+                                                          const float* __restrict__ bv, float k,
+                                                          float* __restrict__ gau, float* __restrict__ gav,
+                                                          float* __restrict__ gbu, float* __restrict__ gbv,
+                                                          double* __restrict__ partial)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    double se = 0.0;
+    if (p < nx * ny) {
+        const int y = p / nx, x = p - y * nx;
+        const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+        const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+        const float d = div_at(nx, ny, x, y, au, bu, av, bv);
+        se = (double)d * d;
+        const float gu = 0.5f * (div_at(nx, ny, xw, y, au, bu, av, bv) - div_at(nx, ny, xe, y, au, bu, av, bv));
+        const float gv = 0.5f * (div_at(nx, ny, x, ys, au, bu, av, bv) - div_at(nx, ny, x, yn, au, bu, av, bv));
+        gau[p] = fmaf(k, gu, gau[p]);
+        gav[p] = fmaf(k, gv, gav[p]);
+        if (gbu) {
+            gbu[p] = fmaf(-k, gu, gbu[p]);
+            gbv[p] = fmaf(-k, gv, gbv[p]);
+        }
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = se;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // out += scale * (fixed-order sum of the partials)
 __global__ void loss_accumulate_kernel(const double* __restrict__ partial, int nblk, double scale,
                                        double* __restrict__ out)
@@ -961,6 +1015,27 @@ acm_status acm_cnn_state_loss(int32_t nx, int32_t ny, const float* const* q, con
     hipLaunchKernelGGL(loss_accumulate_kernel, dim3(1), dim3(64), 0, s, workspace, nb,
                        (double)weight / ((double)lc.nact * n), loss);
     return chip(hipGetLastError(), "state loss final launch");
+}
+
+acm_status acm_cnn_div_penalty(int32_t nx, int32_t ny, const float* const* a, const float* const* b, float weight,
+                               float* const* adj_a, float* const* adj_b, double* workspace, double* loss,
+                               void* stream)
+{
+    if (!a || !b || !adj_a || !workspace || !loss) return cfail(ACM_EINVAL, "NULL pointer");
+    if (nx < 3 || ny < 3) return cfail(ACM_EINVAL, "grid needs nx, ny >= 3");
+    if (!a[0] || !a[1] || !b[0] || !b[1] || !adj_a[0] || !adj_a[1]) return cfail(ACM_EINVAL, "NULL field");
+    if (adj_b && (!adj_b[0] || !adj_b[1])) return cfail(ACM_EINVAL, "NULL field");
+    if (!std::isfinite(weight)) return cfail(ACM_EINVAL, "weight must be finite");
+    const int n = nx * ny;
+    const int nb = blocks_for(n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(div_penalty_kernel, dim3(nb), dim3(256), 0, s, nx, ny, a[0], a[1], b[0], b[1],
+                       2.f * weight / (float)n, adj_a[0], adj_a[1], adj_b ? adj_b[0] : nullptr,
+                       adj_b ? adj_b[1] : nullptr, workspace);
+    acm_status st = chip(hipGetLastError(), "divergence penalty launch");
+    if (st != ACM_OK) return st;
+    hipLaunchKernelGGL(loss_accumulate_kernel, dim3(1), dim3(64), 0, s, workspace, nb, (double)weight / n, loss);
+    return chip(hipGetLastError(), "divergence penalty final launch");
 }
 
 acm_status acm_cnn_adam(int64_t n, float* p, const float* g, float* m, float* v, void* p16, float lr, float b1,

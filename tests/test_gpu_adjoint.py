@@ -130,6 +130,32 @@ def test_state_loss_accumulates(env):
                                        ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(loss.data_ptr()), None))
 
 
+def test_div_penalty_matches_oracle(env):
+    torch, acm, closure, oracle, adjoint = env
+    dev = torch.device("cuda:0")
+    nx, ny = 70, 13
+    rng = np.random.Generator(np.random.PCG64(40))
+    a = {k: rng.standard_normal((ny, nx)).astype(np.float32).astype(np.float64) for k in ("u", "v")}
+    b = {k: rng.standard_normal((ny, nx)).astype(np.float32).astype(np.float64) for k in ("u", "v")}
+    ga0 = {k: rng.standard_normal((ny, nx)).astype(np.float32).astype(np.float64) for k in ("u", "v")}
+    w = 0.7
+    td = lambda d: {k: torch.from_numpy(v).to(device=dev, dtype=torch.float32) for k, v in d.items()}
+    da, db, dga, dgb = td(a), td(b), td(ga0), td(ga0)
+    L = acm.lib()
+    ws = torch.zeros(L.acm_cnn_loss_workspace(nx, ny) // 8 + 1, dtype=torch.float64, device=dev)
+    loss = torch.full((1,), 1.0, dtype=torch.float64, device=dev)
+    arr = lambda d: (ctypes.c_void_p * 2)(d["u"].data_ptr(), d["v"].data_ptr())
+    acm.check(L.acm_cnn_div_penalty(nx, ny, arr(da), arr(db), w, arr(dga), arr(dgb), ctypes.c_void_p(ws.data_ptr()),
+                                    ctypes.c_void_p(loss.data_ptr()), None))
+    torch.cuda.synchronize()
+    p = oracle.Params(dim=2, nx=nx, ny=ny)
+    val, ra, rb = adjoint.div_penalty(p, a, b, w)
+    assert abs(float(loss.item()) - (1.0 + val)) <= 1e-6 * (1.0 + val)
+    for k in ("u", "v"):
+        np.testing.assert_allclose(dga[k].double().cpu().numpy() - ga0[k], ra[k], rtol=0, atol=1e-6)
+        np.testing.assert_allclose(dgb[k].double().cpu().numpy() - ga0[k], rb[k], rtol=0, atol=1e-6)
+
+
 def test_wgrad_add_accumulates(env):
     torch, acm, closure, _, _ = env
     dev = torch.device("cuda:0")
@@ -149,10 +175,12 @@ def test_wgrad_add_accumulates(env):
     assert torch.equal(db2, db1 - 2.0)
 
 
-def test_unrolled_gradient_matches_oracle(env):
+@pytest.mark.parametrize("div_beta", [0.0, 120.0])
+def test_unrolled_gradient_matches_oracle(env, div_beta):
     """k = 3 corrected steps on a 64^2 coarse grid of the forced flow: loss,
     every layer's weight gradient and dL/dq0 from the library (bf16 network)
-    against the FP64 oracle with the same bf16-rounded weights."""
+    against the FP64 oracle with the same bf16-rounded weights, without and
+    with the divergence penalty."""
     torch, acm, closure, oracle, adjoint = env
     spec = closure.FlowSpec(n_fine=256)
     n = spec.n_coarse
@@ -168,12 +196,17 @@ def test_unrolled_gradient_matches_oracle(env):
     tg = [{kk: v.astype(np.float32).astype(np.float64) for kk, v in t.items()} for t in tg]
     dev = net.dev
     td = lambda d: {kk: torch.from_numpy(v).to(device=dev, dtype=torch.float32) for kk, v in d.items()}
-    un = closure.Unroll(spec, net, k)
+    un = closure.Unroll(spec, net, k, div_beta=div_beta)
+    div_weight = un.div_weight  # div_beta / D_vel^2
     loss = un.loss_and_grads(td(q0), [td(t) for t in tg], adj_q0=True)
     torch.cuda.synchronize()
     p = oracle.Params(dim=2, nx=n, ny=n, nu=spec.nu_fine / spec.ratio)
     ref_loss, ref_g, ref_q, _ = adjoint.unrolled_loss(p, p16, net.in_scale, net.out_scale, q0, tg,
-                                                      force_x_row=spec.coarse_force())
+                                                      force_x_row=spec.coarse_force(), div_weight=div_weight)
+    if div_weight:
+        l0 = adjoint.unrolled_loss(p, p16, net.in_scale, net.out_scale, q0, tg, force_x_row=spec.coarse_force(),
+                                   grads=False)[0]
+        assert ref_loss > 1.2 * l0   # the penalty is a sizeable part of the loss
     assert abs(float(loss.item()) - ref_loss) <= 0.02 * ref_loss
     for l in range(closure.LAYERS):
         ci, co = closure.REAL_CHANNELS[l], closure.REAL_CHANNELS[l + 1]
@@ -181,6 +214,8 @@ def test_unrolled_gradient_matches_oracle(env):
         gb = net.gb[l][:co].double().cpu().numpy()
         assert rel(gw, ref_g[l][0]) <= 5e-2, l
         assert rel(gb, ref_g[l][1]) <= 5e-2, l
+    # dL/dq0 crosses the network's bf16 data-gradient path once per step
+    # (about 2 % per pass, the network-output bound), hence 8 % for k = 3
     for kk in ("u", "v"):
-        assert rel(un.adj_q0[kk].double().cpu().numpy(), ref_q[kk]) <= 5e-2, kk
+        assert rel(un.adj_q0[kk].double().cpu().numpy(), ref_q[kk]) <= 8e-2, kk
     un.close()

@@ -322,7 +322,9 @@ def test_trained_network_gains_over_plain_coarse(mods):
     """Gain test: the network trained by the library's own kernels (fine
     256^2 -> coarse 64^2, 24 training seeds) cuts the relative L2 velocity
     error against the filtered fine run on held-out seeds well below that of
-    the plain coarse run over 2000 coarse steps, without tripping the gate."""
+    the plain coarse run over 2000 coarse steps, without tripping the gate;
+    the preset's second stage trains through the solver step with the
+    divergence penalty, as the full preset does."""
     torch, acm, closure, cnn = mods
     from paper_2012_03525_amd import closure_experiment
     summary, _ = closure_experiment.run_experiment("small", log=lambda m: None, eval_seeds=(1000, 1002))
@@ -332,3 +334,6 @@ def test_trained_network_gains_over_plain_coarse(mods):
         assert r["err_cnn_end"] < 0.6 * r["err_plain_end"]
         assert r["err_cnn_max"] < 0.02
     assert summary["epoch_loss"][-1] < 0.2 * summary["epoch_loss"][0]
+    # the stage trained through the solver (divergence penalty) ran
+    assert summary["unroll"] == 1 and len(summary["unroll_epoch_loss"]) == 2
+    assert summary["unroll_epoch_loss"][-1] <= summary["unroll_epoch_loss"][0]
