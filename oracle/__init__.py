@@ -52,6 +52,7 @@ class _Params(ctypes.Structure):
         ("two_phase", ctypes.c_int),
         ("sigma", ctypes.c_double), ("width", ctypes.c_double), ("mobility", ctypes.c_double),
         ("wet_cos", ctypes.c_double * 6),
+        ("axisym", ctypes.c_int),
     ]
 
 
@@ -81,6 +82,7 @@ class Params:
     width: float = 4.0
     mobility: float = 0.0
     wet_cos: Sequence[float] = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)  # cos(contact angle) per wall face
+    axisym: bool = False  # 2D: x axial, y radial with the axis on the -y face (a symmetry plane)
 
     def c(self) -> _Params:
         p = _Params()
@@ -97,6 +99,7 @@ class Params:
         p.sigma, p.width, p.mobility = self.sigma, self.width, self.mobility
         for f in range(6):
             p.wet_cos[f] = float(self.wet_cos[f])
+        p.axisym = 1 if self.axisym else 0
         return p
 
     @property

@@ -206,6 +206,7 @@ static int check_params(const orc_params* p)
     if (p->nx < 2 || p->ny < 2) return -1;
     if (p->dim == 3 && p->nz < 2) return -1;
     if (p->two_phase && !(p->width > 0.0)) return -1;
+    if (p->axisym && (p->dim != 2 || p->two_phase || p->bc[2] != ORC_SYMMETRY)) return -1;
     int nf = (p->dim == 3) ? 6 : 4;
     for (int a = 0; a < nf; a += 2) {
         int lo = p->bc[a], hi = p->bc[a + 1];
@@ -338,13 +339,26 @@ int orc_step(const orc_params* p, const double* force_x_row,
     const double dx = p->dx, dt = p->dt, cs2 = p->cs * p->cs, nu = p->nu;
 
     /* 2. continuity, Eq. (2.10):
-     *    rho' = rho - dt d_a(rho u_a) + 1/2 cs^2 dt^2 d_aa rho                */
+     *    rho' = rho - dt d_a(rho u_a) + 1/2 cs^2 dt^2 d_aa rho
+     * Axisymmetric runs (y = radius r, axis on the -y face) take the
+     * cylindrical divergence (1/r) d_r(r f) and Laplacian (1/r) d_r(r d_r f)
+     * in flux form with face radii r -+ dx/2: the face value of f is the
+     * mean of its two nodes, which is the centred difference (2.12) away
+     * from the axis and makes sum(r drho) exact with the axis and wall
+     * ghosts. */
     for (int k = 0; k < g.nz; ++k)
         for (int j = 0; j < g.ny; ++j)
             for (int i = 0; i < g.nx; ++i) {
                 long c = P(&g, i, j, k);
                 double div = 0.0, lap = 0.0;
                 for (int a = 0; a < nv; ++a) {
+                    if (p->axisym && a == 1) {
+                        const double rc = j + 0.5, rp = j + 1.0, rm = j;  /* radii in units of dx */
+                        long cp = c + st[1], cm = c - st[1];
+                        div += (rp * (m[1][c] + m[1][cp]) - rm * (m[1][cm] + m[1][c])) / (2.0 * dx * rc);
+                        lap += (rp * (r[cp] - r[c]) - rm * (r[c] - r[cm])) / (dx * dx * rc);
+                        continue;
+                    }
                     div += (m[a][c + st[a]] - m[a][c - st[a]]) / (2.0 * dx);
                     lap += (r[c + st[a]] + r[c - st[a]] - 2.0 * r[c]) / (dx * dx);
                 }
@@ -372,8 +386,23 @@ int orc_step(const orc_params* p, const double* force_x_row,
                             pip += cs2 * r[cp];
                             pim += cs2 * r[cm];
                         }
+                        if (p->axisym && b == 1) {  /* (1/r) d_r(r Pi_ar), (1/r) d_r(r d_r m_a) */
+                            const double rc = j + 0.5, rp = j + 1.0, rm = j;
+                            double pic = m[a][c] * uu[b][c] + (a == b ? cs2 * r[c] : 0.0);
+                            flux += (rp * (pic + pip) - rm * (pim + pic)) / (2.0 * dx * rc);
+                            visc += (rp * (m[a][cp] - m[a][c]) - rm * (m[a][c] - m[a][cm])) / (dx * dx * rc);
+                            continue;
+                        }
                         flux += (pip - pim) / (2.0 * dx);
                         visc += (m[a][cp] + m[a][cm] - 2.0 * m[a][c]) / (dx * dx);
+                    }
+                    if (p->axisym && a == 1) {
+                        /* radial component: hoop term -Pi_thth / r of the
+                         * divergence (Pi_thth = cs^2 drho without swirl) and
+                         * -m_r / r^2 of the vector Laplacian */
+                        const double rr = (j + 0.5) * dx;
+                        flux -= cs2 * r[c] / rr;
+                        visc -= m[1][c] / (rr * rr);
                     }
                     long ap = c + st[a], am = c - st[a];
                     double grad_new = (rn[ap] - rn[am]) / (2.0 * dx);
