@@ -30,7 +30,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="tgv3d_256",
-                    choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024", "drop_spreading_96", "batch512"])
+                    choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024", "drop_spreading_96", "batch512",
+                             "pipe_axisym_4096x2048"])
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the closure step timing in the default workload's line")
     ap.add_argument("--tile", type=int, default=0)
@@ -85,6 +86,18 @@ def workload(name, tile):
         meta = {"workload": "2D periodic Taylor-Green vortex 64^2, FP64", "grid": [n, n], "u0": 0.01, "nu": 0.01}
         bytes_per_lup = 48
         kernel = "step2d_kernel"
+    elif name == "pipe_axisym_4096x2048":
+        # axisymmetric pipe (x axial, periodic; y radial: axis, wall at r = R = 2048): start-up of the
+        # axially forced flow from a perturbed profile; g sets the Poiseuille centre speed to 0.05
+        nxa, R, nu = 4096, 2048, 0.05
+        g = 4.0 * nu * 0.05 / (R * R)
+        cfg = acm.make_config(2, nxa, R, nu=nu, g=(g, 0.0, 0.0), precision="f32", bc=(0, 0, 2, 1, 0, 0),
+                              axisym=True, tile=tile, graph_chunk=100)
+        st = inputs.pipe_state(nxa, R, seed=3)
+        meta = {"workload": "axisymmetric pipe flow 4096 (axial) x 2048 (radial), FP32 drho storage",
+                "grid": [nxa, R], "nu": nu, "g": g}
+        bytes_per_lup = 24  # read drho,u,v + write drho,u,v (FP32)
+        kernel = "axisym2d_kernel"
     elif name == "drop_spreading_96":
         # drop spreading on a wall (Sec. 3.6): N_L = 32, c = 10, Re = 100 (Oh = 0.1), Cn = 0.1,
         # Pe = 8000, theta = 60 degrees; [0,3]^3 with symmetry planes at the sides, walls at z = 0, 3

@@ -86,7 +86,8 @@ typedef struct acm_config {
     int32_t graph_chunk;    /* steps per captured HIP graph (even); 0 = 64    */
     int32_t tile;           /* kernel tile variant; 0 = default.  2D single-
                                phase: 1 32x8, 2 64x8, 3 16x16, 4 128x4,
-                               5 32x16 (0: 64x4).  2D two-phase: 1 32x8,
+                               5 32x16 (0: 64x4).  2D axisymmetric: 1
+                               32x8, 2 64x8, 4 64x4 (0: 32x16).  2D two-phase: 1 32x8,
                                2 64x8, 3 16x16 (0: 32x16).  3D: low byte
                                1 32x8, 2 64x8, 3 32x4, 4 64x4, 5 64x16,
                                7 32x16, 9 128x4, 12 128x8, 13 64x8 with two
@@ -101,6 +102,15 @@ typedef struct acm_config {
                                for the wetting condition of Sec. 2,
                                d_n phi = -(2/W) cos(theta) (1 - phi_w^2),
                                in [-1, 1]; 0 (90 degrees) mirrors phi       */
+    int32_t axisym;         /* 1: axisymmetric 2D single-phase run, x axial,
+                               y radial, the -y face the axis (must be
+                               ACM_BC_SYMMETRY), row j at r = (j + 1/2) dx;
+                               Eqs. (2.10)-(2.11) with the cylindrical
+                               divergence and Laplacian in flux form, the
+                               hoop term -cs^2 drho / r and -m_r / r^2 in the
+                               radial momentum.  The stability guard uses the
+                               planar symbol; diagnostics are plain node
+                               sums (not r-weighted).  0: planar            */
 } acm_config;
 
 /* Device pointers of one complete state.  w is used in 3D only, phi in

@@ -35,6 +35,7 @@ class Config(ctypes.Structure):
         ("two_phase", ctypes.c_int32), ("sigma", ctypes.c_double), ("width", ctypes.c_double),
         ("mobility", ctypes.c_double), ("precision", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
         ("graph_chunk", ctypes.c_int32), ("tile", ctypes.c_int32), ("wet_cos", ctypes.c_double * 6),
+        ("axisym", ctypes.c_int32),
     ]
 
 
@@ -176,7 +177,7 @@ def make_config(dim: int, nx: int, ny: int, nz: int = 1, *, dx: float = 1.0, dt:
                 bc: Sequence[int] = (0, 0, 0, 0, 0, 0), wall_u=None, two_phase: bool = False,
                 sigma: float = 0.0, width: float = 4.0, mobility: float = 0.0, precision: str = "f32",
                 allow_unstable: bool = False, graph_chunk: int = 0, tile: int = 0,
-                wet_cos: Optional[Sequence[float]] = None) -> Config:
+                wet_cos: Optional[Sequence[float]] = None, axisym: bool = False) -> Config:
     c = Config()
     c.dim, c.nx, c.ny, c.nz = dim, nx, ny, (nz if dim == 3 else 1)
     c.dx, c.dt, c.nu, c.cs, c.rho0 = dx, dt, nu, cs, rho0
@@ -195,6 +196,7 @@ def make_config(dim: int, nx: int, ny: int, nz: int = 1, *, dx: float = 1.0, dt:
     c.tile = tile
     for f in range(6):
         c.wet_cos[f] = float(wet_cos[f]) if wet_cos is not None else 0.0
+    c.axisym = 1 if axisym else 0
     return c
 
 

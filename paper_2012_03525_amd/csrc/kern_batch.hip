@@ -307,7 +307,8 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
         const acm_batch_case& k = cases[i];
         std::string err;
         if (api_validate(&k.cfg, err) != ACM_OK) return bfail(ACM_EINVAL, "case " + std::to_string(i) + ": " + err);
-        if (k.cfg.dim != 2 || k.cfg.two_phase) return bfail(ACM_EINVAL, "batched cases are 2D single-phase");
+        if (k.cfg.dim != 2 || k.cfg.two_phase || k.cfg.axisym)
+            return bfail(ACM_EINVAL, "batched cases are 2D single-phase planar");
         if (k.cfg.precision != prec) return bfail(ACM_EINVAL, "every case of a batch needs the same precision");
         if (!k.a.drho || !k.a.u || !k.a.v || !k.b.drho || !k.b.u || !k.b.v)
             return bfail(ACM_EINVAL, "case " + std::to_string(i) + ": missing field pointers");

@@ -1205,8 +1205,8 @@ acm_status acm_closure_init(const acm_config* cfg, const acm_fields* a, const ac
     *out = nullptr;
     std::string err;
     if (api_validate(cfg, err) != ACM_OK) return cfail(ACM_EINVAL, err);
-    if (cfg->dim != 2 || cfg->two_phase || cfg->precision != ACM_F32)
-        return cfail(ACM_EINVAL, "the closure runs 2D single-phase FP32 coarse grids");
+    if (cfg->dim != 2 || cfg->two_phase || cfg->axisym || cfg->precision != ACM_F32)
+        return cfail(ACM_EINVAL, "the closure runs 2D single-phase planar FP32 coarse grids");
     if (cfg->nx < fused::T || cfg->ny < fused::T || cfg->nx % fused::T || cfg->ny % fused::T)
         return cfail(ACM_EINVAL, "closure grids need nx and ny multiples of 16");
     if (!a || !b || !a->drho || !a->u || !a->v || !b->drho || !b->u || !b->v || !weights || !biases || !in_scale ||

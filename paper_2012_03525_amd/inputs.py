@@ -245,3 +245,22 @@ def seeded_state(shape, seed: int, scale_u: float = 0.02, scale_r: float = 1e-3,
     if two_phase:
         st["phi"] = rng.uniform(-1, 1, size=shape)
     return st
+
+
+def pipe_state(nx: int, ny: int, seed: int, u_amp: float = 0.04, r_amp: float = 1e-3) -> Dict[str, np.ndarray]:
+    """Axisymmetric test state on an axial-periodic pipe (x axial, y radial,
+    row j at r = (j + 1/2)/ny of the radius): a seeded axial profile
+    u_amp (1 - r^2)(1 + 0.3 sin(2 pi x + p1)), a radial velocity
+    0.2 u_amp r (1 - r) sin(2 pi x + p2) (odd at the axis, zero at the wall) and
+    a density pulse r_amp sum_m a_m cos(2 pi m x + q_m) cos(pi m r)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = ((np.arange(nx) + 0.5) / nx)[None, :]
+    r = ((np.arange(ny) + 0.5) / ny)[:, None]
+    p1, p2 = rng.uniform(0, 2 * math.pi, size=2)
+    u = u_amp * (1 - r * r) * (1 + 0.3 * np.sin(2 * math.pi * x + p1))
+    v = 0.2 * u_amp * r * (1 - r) * np.sin(2 * math.pi * x + p2)
+    drho = np.zeros((ny, nx))
+    for m in (1, 2):
+        a, q = rng.standard_normal(), rng.uniform(0, 2 * math.pi)
+        drho = drho + r_amp * a * np.cos(2 * math.pi * m * x + q) * np.cos(math.pi * m * r)
+    return {"drho": drho, "u": u, "v": v}

@@ -1,0 +1,125 @@
+"""GPU parity of the axisymmetric step (x axial, y radial, axis on the -y
+face) against the FP64 oracle: FP64 to 1e-12 on ragged multi-tile grids with
+walls, a moving wall, body force and forcing row; FP32 over 500 steps;
+the discrete Poiseuille fixed point; every tile shape bit for bit; and the
+configurations the library rejects."""
+import numpy as np
+import pytest
+
+from paper_2012_03525_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SYM, WALL = 2, 1
+KEYS = ("drho", "u", "v")
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import oracle
+    from paper_2012_03525_amd import acm
+    acm.lib()
+    oracle.lib()
+    return torch, acm, oracle
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def case(mods, nx, ny, bc, precision, wall_speed=0.0, force=True, tile=0):
+    _, acm, oracle = mods
+    wu = [[0.0] * 3 for _ in range(6)]
+    wu[3] = [wall_speed, 0.0, 0.0]
+    fx = 2e-6 * np.cos(2 * np.pi * np.arange(ny) / ny) if force else None
+    kw = dict(nu=0.04, g=(3e-6, 0.0, 0.0), bc=bc, wall_u=wu)
+    cfg = acm.make_config(2, nx, ny, precision=precision, axisym=True, tile=tile, **kw)
+    p = oracle.Params(dim=2, nx=nx, ny=ny, axisym=True, **kw)
+    return cfg, p, fx
+
+
+@pytest.mark.parametrize("nx,ny,bc,wall", [(100, 37, (0, 0, SYM, WALL, 0, 0), 0.02),
+                                           (70, 20, (WALL, WALL, SYM, SYM, 0, 0), 0.0),
+                                           (128, 64, (0, 0, SYM, WALL, 0, 0), 0.0),
+                                           (20, 9, (SYM, SYM, SYM, WALL, 0, 0), 0.01)])
+def test_axisym_f64_matches_oracle(mods, nx, ny, bc, wall):
+    torch, acm, oracle = mods
+    cfg, p, fx = case(mods, nx, ny, bc, "f64", wall_speed=wall)
+    st = inputs.pipe_state(nx, ny, seed=nx + ny)
+    print(f"axisym f64 {nx}x{ny} bc {bc}", flush=True)
+    s = acm.Solver(cfg, st, force_x=fx)
+    s.run(20)
+    got = s.state()
+    s.close()
+    ref = oracle.run(p, st, 20, force_x_row=fx)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) <= 1e-12, k
+
+
+def test_axisym_f32_matches_oracle(mods):
+    """500 steps on 128 x 64: velocity <= 1e-4, drho <= 1e-3 relative L2 (the
+    bounds of the FP32 batch cases: FP32 storage error grows with the step
+    count)."""
+    torch, acm, oracle = mods
+    nx, ny = 128, 64
+    cfg, p, fx = case(mods, nx, ny, (0, 0, SYM, WALL, 0, 0), "f32", wall_speed=0.01)
+    st = inputs.pipe_state(nx, ny, seed=5)
+    st32 = {k: v.astype(np.float32).astype(np.float64) for k, v in st.items()}
+    fx32 = fx.astype(np.float32).astype(np.float64)
+    s = acm.Solver(cfg, st32, force_x=fx32)
+    s.run(500)
+    got = s.state()
+    s.close()
+    ref = oracle.run(p, st32, 500, force_x_row=fx32)
+    err_u = float(np.sqrt(((got["u"] - ref["u"]) ** 2 + (got["v"] - ref["v"]) ** 2).sum() /
+                          (ref["u"] ** 2 + ref["v"] ** 2).sum()))
+    print(f"f32 500 steps: velocity {err_u:.2e} drho {rel(got['drho'], ref['drho']):.2e}")
+    assert err_u <= 1e-4
+    assert rel(got["drho"], ref["drho"]) <= 1e-3
+
+
+def test_axisym_poiseuille_fixed_point(mods):
+    torch, acm, oracle = mods
+    nx, ny, nu, g = 64, 24, 0.08, 1e-6
+    cfg = acm.make_config(2, nx, ny, nu=nu, g=(g, 0.0, 0.0), bc=(0, 0, SYM, WALL, 0, 0), precision="f64",
+                          axisym=True)
+    r = np.arange(ny) + 0.5
+    u = np.tile((g * (ny * ny + 0.25 - r * r) / (4 * nu))[:, None], (1, nx))
+    st = {"drho": np.zeros((ny, nx)), "u": u, "v": np.zeros((ny, nx))}
+    s = acm.Solver(cfg, st)
+    s.run(10)
+    got = s.state()
+    s.close()
+    assert np.max(np.abs(got["u"] - u)) <= 1e-14 * np.max(u)
+    assert np.max(np.abs(got["v"])) == 0.0 and np.max(np.abs(got["drho"])) == 0.0
+
+
+def test_axisym_tiles_bitwise_identical(mods):
+    torch, acm, oracle = mods
+    nx, ny = 100, 37
+    st = inputs.pipe_state(nx, ny, seed=9)
+    outs = []
+    for tile in (0, 1, 2, 4):
+        cfg, _, fx = case(mods, nx, ny, (0, 0, SYM, WALL, 0, 0), "f32", wall_speed=0.02, tile=tile)
+        s = acm.Solver(cfg, st, force_x=fx)
+        s.run(30)
+        outs.append(s.state())
+        s.close()
+    for o in outs[1:]:
+        for k in KEYS:
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
+def test_axisym_rejected_configurations(mods):
+    torch, acm, oracle = mods
+    st = inputs.pipe_state(32, 16, seed=1)
+    for kw in (dict(bc=(0, 0, WALL, WALL, 0, 0)), dict(bc=(0, 0, 0, 0, 0, 0)),
+               dict(bc=(0, 0, SYM, WALL, 0, 0), two_phase=True, sigma=0.01, width=4.0, mobility=0.1)):
+        cfg = acm.make_config(2, 32, 16, nu=0.05, axisym=True, **kw)
+        with pytest.raises(acm.AcmError):
+            acm.Solver(cfg, dict(st, phi=np.zeros((16, 32))))
+    cfg3 = acm.make_config(3, 16, 16, 16, nu=0.05, bc=(0, 0, SYM, WALL, 0, 0), axisym=True)
+    with pytest.raises(acm.AcmError):
+        acm.Solver(cfg3, {k: np.zeros((16, 16, 16)) for k in ("drho", "u", "v", "w")})
