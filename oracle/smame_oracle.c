@@ -206,7 +206,7 @@ static int check_params(const orc_params* p)
     if (p->nx < 2 || p->ny < 2) return -1;
     if (p->dim == 3 && p->nz < 2) return -1;
     if (p->two_phase && !(p->width > 0.0)) return -1;
-    if (p->axisym && (p->dim != 2 || p->two_phase || p->bc[2] != ORC_SYMMETRY)) return -1;
+    if (p->axisym && (p->dim != 2 || p->bc[2] != ORC_SYMMETRY)) return -1;
     int nf = (p->dim == 3) ? 6 : 4;
     for (int a = 0; a < nf; a += 2) {
         int lo = p->bc[a], hi = p->bc[a + 1];
@@ -260,8 +260,19 @@ static double liso(const orc_params* p, const double* f, long c, const long st[3
     return (wa * ax + ed - w0 * f[c]) / (6.0 * p->dx * p->dx);
 }
 
+/* axisymmetric runs: (1/r) G_iso,r f, the extra part of the cylindrical
+ * Laplacian (1/r) d_r(r d_r f) = d_rr f + (1/r) d_r f, with the radius of
+ * the node (row j at r = (j + 1/2) dx); 0 for planar runs */
+static double axi_lap_extra(const orc_params* p, const pgrid* g, const double* f, long c, const long st[3])
+{
+    if (!p->axisym) return 0.0;
+    int j = (int)((c / g->px) % g->py) - 1;
+    return giso(p, f, c, st, 1) / ((j + 0.5) * p->dx);
+}
+
 /* mu = 4 a phi (phi^2 - 1) - kappa L_iso phi on interior nodes of padded arrays,
- * a = 3 sigma / (4 W), kappa = 3 sigma W / 8 (Sec. 2) */
+ * a = 3 sigma / (4 W), kappa = 3 sigma W / 8 (Sec. 2); axisymmetric runs
+ * take the cylindrical Laplacian L_iso phi + (1/r) G_iso,r phi */
 static void chem_pot(const orc_params* p, const pgrid* g, const double* phi, double* mu)
 {
     double a = 3.0 * p->sigma / (4.0 * p->width);
@@ -273,17 +284,19 @@ static void chem_pot(const orc_params* p, const pgrid* g, const double* phi, dou
             for (int i = 0; i < g->nx; ++i) {
                 long c = P(g, i, j, k);
                 double f = phi[c];
-                mu[c] = 4.0 * a * f * (f * f - 1.0) - kappa * liso(p, phi, c, st);
+                mu[c] = 4.0 * a * f * (f * f - 1.0) - kappa * (liso(p, phi, c, st) + axi_lap_extra(p, g, phi, c, st));
             }
 }
 
-/* CHE right-hand side (2.14): R = M L_iso mu - u_a G_iso,a phi */
+/* CHE right-hand side (2.14): R = M L_iso mu - u_a G_iso,a phi (cylindrical
+ * Laplacian in axisymmetric runs; the advection u . grad phi has no extra
+ * term) */
 static double che_rhs(const orc_params* p, const pgrid* g, const double* phi, const double* mu,
                       double* const uu[3], long c)
 {
     long st[3];
     axis_strides(g, st);
-    double diff = p->mobility * liso(p, mu, c, st);
+    double diff = p->mobility * (liso(p, mu, c, st) + axi_lap_extra(p, g, mu, c, st));
     double adv = 0.0;
     for (int a = 0; a < p->dim; ++a) adv += uu[a][c] * giso(p, phi, c, st, a);
     return diff - adv;

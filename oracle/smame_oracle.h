@@ -32,9 +32,9 @@ typedef struct {
     double sigma, width, mobility;
     double wet_cos[6];          /* cos(contact angle) of each wall face;
                                    0 = 90 degrees (phi mirrored)             */
-    int axisym;                 /* 2D single-phase: x is the axial coordinate,
-                                   y the radius; the -y face is the axis
-                                   (symmetry plane), node j at r = (j+1/2) dx */
+    int axisym;                 /* 2D: x is the axial coordinate, y the
+                                   radius; the -y face is the axis (symmetry
+                                   plane), node j at r = (j+1/2) dx          */
 } orc_params;
 
 /* One time step.  in_* are level n, out_* receive level n+1 (must not alias

@@ -264,3 +264,14 @@ def pipe_state(nx: int, ny: int, seed: int, u_amp: float = 0.04, r_amp: float = 
         a, q = rng.standard_normal(), rng.uniform(0, 2 * math.pi)
         drho = drho + r_amp * a * np.cos(2 * math.pi * m * x + q) * np.cos(math.pi * m * r)
     return {"drho": drho, "u": u, "v": v}
+
+
+def drop_on_axis(nx: int, ny: int, radius: float, width: float) -> Dict[str, np.ndarray]:
+    """A drop (phi = +1 inside) of the given radius centred on the axis at the
+    middle of an axial period (x axial, row j at r = j + 1/2), at rest:
+    phi = tanh(2 (R - d) / W), d the distance to the centre."""
+    x = (np.arange(nx) - nx / 2.0)[None, :]
+    r = (np.arange(ny) + 0.5)[:, None]
+    d = np.sqrt(x * x + r * r)
+    z = np.zeros((ny, nx))
+    return {"drho": z.copy(), "u": z.copy(), "v": z.copy(), "phi": np.tanh(2.0 * (radius - d) / width)}

@@ -83,9 +83,9 @@ def test_axisym_parameter_checks(orc):
     st = inputs.seeded_state((8, 8), seed=1)
     for kw in (dict(dim=2, nx=8, ny=8, bc=(0, 0, WALL, WALL, 0, 0), axisym=True),     # axis must be a symmetry face
                dict(dim=2, nx=8, ny=8, bc=(0, 0, 0, 0, 0, 0), axisym=True),           # periodic in r
-               dict(dim=2, nx=8, ny=8, bc=(0, 0, SYM, WALL, 0, 0), axisym=True, two_phase=True)):
+               dict(dim=3, nx=8, ny=8, nz=8, bc=(0, 0, SYM, WALL, 0, 0), axisym=True)):
         with pytest.raises(ValueError):
-            orc.step(orc.Params(**kw), dict(st, phi=np.zeros((8, 8))))
+            orc.step(orc.Params(**kw), dict(st, w=np.zeros((8, 8, 8)), **{k: np.zeros((8, 8, 8)) for k in st}))
 
 
 def test_radial_vector_laplacian(orc):
@@ -122,3 +122,46 @@ def test_axial_momentum_is_conserved_with_a_symmetry_rim(orc):
     scale = float((r * np.abs(st["u"])).sum())
     assert abs(mz(out) - mz(st)) <= 1e-15 * scale
     assert abs(float(((1.0 + out["drho"]) * out["u"]).sum()) - float(((1.0 + st["drho"]) * st["u"]).sum())) > 1e-12
+
+
+def _drop_mu(orc, W, R, nx, ny, axi, sig=0.01):
+    p = orc.Params(dim=2, nx=nx, ny=ny, nu=0.1, bc=(0, 0, SYM, SYM, 0, 0), axisym=axi, two_phase=True,
+                   sigma=sig, width=W, mobility=0.1)
+    return orc.chemical_potential(p, inputs.drop_on_axis(nx, ny, R, W)["phi"])
+
+
+def test_axisym_chemical_potential_of_a_sphere(orc):
+    """For phi = tanh(2 (R - d)/W) centred on the axis, the axisymmetric mu is
+    that of a sphere and the planar one that of a circle: their difference is
+    the curvature term -kappa psi'(d) / d (psi' = -(2/W)(1 - psi^2)).  Within
+    3 % near the interface at W = 8, and second order in dx / W (W = 4 vs 8)."""
+    errs = []
+    for W, R, nx, ny in ((4.0, 24.0, 96, 48), (8.0, 40.0, 160, 80)):
+        kappa = 3 * 0.01 * W / 8
+        dmu = _drop_mu(orc, W, R, nx, ny, True) - _drop_mu(orc, W, R, nx, ny, False)
+        x = (np.arange(nx) - nx / 2.0)[None, :]
+        r = (np.arange(ny) + 0.5)[:, None]
+        d = np.sqrt(x * x + r * r)
+        psi = np.tanh(2 * (R - d) / W)
+        ana = kappa * (2 / W) * (1 - psi * psi) / d
+        m = np.abs(d - R) < W
+        errs.append(np.abs(dmu[m] - ana[m]).max() / np.abs(ana[m]).max())
+    assert errs[1] <= 0.03
+    assert errs[0] / errs[1] >= 3.0
+
+
+def test_axisym_cahn_hilliard_conserves_r_weighted_phi_from_rest(orc):
+    """From rest the Cahn-Hilliard update is pure diffusion of mu; summed over
+    the axial direction the isotropic cylindrical Laplacian is the radial flux
+    form, so sum(r phi) is unchanged by one step (both Heun stages use u^n = 0)
+    while the unweighted sum is not."""
+    nx, ny, W, R = 48, 32, 4.0, 12.0
+    p = orc.Params(dim=2, nx=nx, ny=ny, nu=0.1, bc=(0, 0, SYM, SYM, 0, 0), axisym=True, two_phase=True,
+                   sigma=0.01, width=W, mobility=0.1)
+    st = inputs.drop_on_axis(nx, ny, R, W)
+    rng = np.random.Generator(np.random.PCG64(44))
+    st["phi"] = st["phi"] + 0.05 * rng.standard_normal((ny, nx))
+    out = orc.step(p, st)
+    r = (np.arange(ny) + 0.5)[:, None]
+    assert abs(float((r * (out["phi"] - st["phi"])).sum())) <= 1e-14 * float((r * np.abs(st["phi"])).sum())
+    assert abs(float((out["phi"] - st["phi"]).sum())) > 1e-3
