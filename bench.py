@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="tgv3d_256",
                     choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024", "drop_spreading_96", "batch512",
-                             "pipe_axisym_4096x2048"])
+                             "pipe_axisym_4096x2048", "drop_axisym_2048x1024"])
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the closure step timing in the default workload's line")
     ap.add_argument("--tile", type=int, default=0)
@@ -98,6 +98,17 @@ def workload(name, tile):
                 "grid": [nxa, R], "nu": nu, "g": g}
         bytes_per_lup = 24  # read drho,u,v + write drho,u,v (FP32)
         kernel = "axisym2d_kernel"
+    elif name == "drop_axisym_2048x1024":
+        # axisymmetric two-phase: a drop (sphere) of radius 256 on the axis of an axially periodic
+        # 2048 x 1024 domain with a symmetry rim, relaxing under surface tension
+        nxa, nr, R, W = 2048, 1024, 256.0, 4.0
+        cfg = acm.make_config(2, nxa, nr, nu=0.1, precision="f32", bc=(0, 0, 2, 2, 0, 0), axisym=True,
+                              two_phase=True, sigma=0.01, width=W, mobility=0.1, tile=tile, graph_chunk=100)
+        st = inputs.drop_on_axis(nxa, nr, R, W)
+        meta = {"workload": "axisymmetric two-phase drop on the axis 2048 (axial) x 1024 (radial), FP32",
+                "grid": [nxa, nr], "R": R, "W": W, "sigma": 0.01, "mobility": 0.1, "nu": 0.1}
+        bytes_per_lup = 32  # read drho,u,v,phi + write them (FP32)
+        kernel = "twophase2d_kernel (axisymmetric)"
     elif name == "drop_spreading_96":
         # drop spreading on a wall (Sec. 3.6): N_L = 32, c = 10, Re = 100 (Oh = 0.1), Cn = 0.1,
         # Pe = 8000, theta = 60 degrees; [0,3]^3 with symmetry planes at the sides, walls at z = 0, 3

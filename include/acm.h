@@ -102,15 +102,17 @@ typedef struct acm_config {
                                for the wetting condition of Sec. 2,
                                d_n phi = -(2/W) cos(theta) (1 - phi_w^2),
                                in [-1, 1]; 0 (90 degrees) mirrors phi       */
-    int32_t axisym;         /* 1: axisymmetric 2D single-phase run, x axial,
-                               y radial, the -y face the axis (must be
+    int32_t axisym;         /* 1: axisymmetric 2D run, x axial, y radial,
+                               the -y face the axis (must be
                                ACM_BC_SYMMETRY), row j at r = (j + 1/2) dx;
                                Eqs. (2.10)-(2.11) with the cylindrical
                                divergence and Laplacian in flux form, the
                                hoop term -cs^2 drho / r and -m_r / r^2 in the
-                               radial momentum.  The stability guard uses the
-                               planar symbol; diagnostics are plain node
-                               sums (not r-weighted).  0: planar            */
+                               radial momentum; two-phase runs add
+                               (1/r) G_iso,r to L_iso in mu and in (2.14).
+                               The stability guard uses the planar symbol;
+                               diagnostics are plain node sums (not
+                               r-weighted).  0: planar                      */
 } acm_config;
 
 /* Device pointers of one complete state.  w is used in 3D only, phi in

@@ -105,8 +105,8 @@ acm_status validate(const acm_config* c)
             return fail(ACM_EINVAL, "wet_cos must lie in [-1, 1]");
     if (c->precision != ACM_F64 && c->precision != ACM_F32) return fail(ACM_EINVAL, "unknown precision");
     if (c->axisym != 0 && c->axisym != 1) return fail(ACM_EINVAL, "axisym must be 0 or 1");
-    if (c->axisym && (c->dim != 2 || c->two_phase || c->bc[2] != ACM_BC_SYMMETRY))
-        return fail(ACM_EINVAL, "axisymmetric runs are 2D single-phase with the axis (-y face) a symmetry plane");
+    if (c->axisym && (c->dim != 2 || c->bc[2] != ACM_BC_SYMMETRY))
+        return fail(ACM_EINVAL, "axisymmetric runs are 2D with the axis (-y face) a symmetry plane");
     const int nf = c->dim == 3 ? 6 : 4;
     for (int f = 0; f < nf; ++f) {
         if (c->bc[f] < 0 || c->bc[f] > 2) return fail(ACM_EINVAL, "unknown boundary type");
@@ -227,6 +227,7 @@ hipError_t launch_typed(const acm_handle* h, const Coef<T>& c, int from, hipStre
     const State<T> out = state_of<T>(h->set[1 - from]);
     if (h->cfg.two_phase && h->cfg.dim == 3)
         return launch_twophase3d<T>(c, in, out, static_cast<T*>(h->scratch), h->cfg.tile, s);
+    if (h->cfg.two_phase && h->cfg.axisym) return launch_twophase_axisym2d<T>(c, in, out, h->cfg.tile, s);
     if (h->cfg.two_phase) return launch_twophase2d<T>(c, in, out, h->cfg.tile, s);
     if (h->cfg.dim == 3) return launch_step3d<T>(c, in, out, h->cfg.tile, s);
     if (h->cfg.axisym) return launch_axisym2d<T>(c, in, out, h->cfg.tile, s);

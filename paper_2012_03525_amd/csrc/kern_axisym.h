@@ -11,4 +11,10 @@ namespace acm {
 template <typename T>
 hipError_t launch_axisym2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile, hipStream_t s);
 
+// One axisymmetric two-phase step (kern_twophase.hip); tile codes as for the
+// planar two-phase step.
+template <typename T>
+hipError_t launch_twophase_axisym2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
+                                    hipStream_t s);
+
 }  // namespace acm

@@ -11,12 +11,19 @@
 // with the D2Q9-weighted isotropic stencils
 //   G_iso,x f = [4 (f_E - f_W) + (f_NE + f_SE - f_NW - f_SW)] / (12 dx)
 //   L_iso f   = [4 (f_E + f_W + f_N + f_S) + (f_NE + f_NW + f_SE + f_SW) - 20 f] / (6 dx^2).
+// AXI = true is the axisymmetric form (x axial, y radial, axis on the -y
+// face, row j at r = (j + 1/2) dx): L_iso gains (1/r) G_iso,r in mu and in
+// the Cahn-Hilliard diffusion, continuity and momentum take the
+// cylindrical flux forms of the single-phase axisymmetric step
+// (kern_axisym.hip); the advection and the surface-tension force are
+// unchanged.
 // Dependency radii: phi needs a 4-node halo (mu on tile+3, phi* on tile+2,
 // mu* on tile+1), the flow fields a 2-node halo.  Ghost positions of every
 // intermediate take the value at their mirror node for walls and symmetry
 // planes, so they are computed there; phi and phi* ghosts across a wall
 // then take the wetting rule of Sec. 2 (identity for a 90 degree angle).
 #include "acm_internal.h"
+#include "kern_axisym.h"
 #include "tile2d.h"
 
 namespace acm {
@@ -59,6 +66,32 @@ __device__ __forceinline__ T chem(const Coef<T>& c, const T* f, int e)
     return fmaT(c.a4 * p, fmaT(p, p, T(-1)), -c.kap6 * liso_num<T, W>(f, e));
 }
 
+// chemical potential with the cylindrical Laplacian when AXI (irc =
+// 1 / (row + 1/2)): -kappa (1/r) G_iso,r phi = -(kappa / 6 dx^2) irc gy / 2
+template <typename T, int W, bool AXI>
+__device__ __forceinline__ T chem_a(const Coef<T>& c, const T* f, int e, T irc)
+{
+    const T m = chem<T, W>(c, f, e);
+    if constexpr (AXI) return fmaT(T(-0.5) * c.kap6 * irc, gisoy_num<T, W>(f, e), m);
+    else return m;
+}
+
+// numerator of the (cylindrical when AXI) isotropic Laplacian in units of
+// 1 / (6 dx^2): L_iso + (1/r) G_iso,r = [liso_num + irc gy_num / 2] / (6 dx^2)
+template <typename T, int W, bool AXI>
+__device__ __forceinline__ T lap_a(const T* f, int e, T irc)
+{
+    if constexpr (AXI) return fmaT(T(0.5) * irc, gisoy_num<T, W>(f, e), liso_num<T, W>(f, e));
+    else return liso_num<T, W>(f, e);
+}
+
+template <bool AXI, typename T>
+__device__ __forceinline__ T inv_radius(int row)
+{
+    if constexpr (AXI) return T(1) / (T(row) + T(0.5));
+    else return T(0);
+}
+
 // local coordinate (in a region with halo h) whose value stands in for the
 // position l: the mirror node for wall / symmetry ghosts, else l itself
 __device__ __forceinline__ int ghost_src(int l, int h, int o0, int n, int bc_lo, int lo, int hi)
@@ -67,7 +100,7 @@ __device__ __forceinline__ int ghost_src(int l, int h, int o0, int n, int bc_lo,
     return min(max(g - o0 + h, lo), hi);
 }
 
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, bool AXI>
 __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, State<T> out, int nbx)
 {
     using S = Shape2P<TX, TY>;
@@ -156,7 +189,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
             ex = ghost_src(lx, 3, x0, nx, c.bc[0], 0, MX - 1) + 1;
             ey = ghost_src(ly, 3, y0, ny, c.bc[2], 0, S::MY - 1) + 1;
         }
-        smu[q] = chem<T, PX>(c, sp, ey * PX + ex);
+        smu[q] = chem_a<T, PX, AXI>(c, sp, ey * PX + ex, inv_radius<AXI, T>(y0 + ey - 4));
     }
     for (int q = tid; q < S::DXY; q += NT) {
         const int ly = q / DX, lx = q - ly * DX;
@@ -168,8 +201,17 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         const int e = ey * RX + ex;
         const T rc = sr[e];
         const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
-        const T div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) + mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0);
-        const T lap = ((rE + rW) + (rN + rS)) - T(4) * rc;
+        T div, lap;
+        if constexpr (AXI) {  // cylindrical flux forms (kern_axisym.hip)
+            const T g = T(y0 + ey - 2), irc = inv_radius<AXI, T>(y0 + ey - 2);
+            const T myC = momc2(rc, sv[e], c.rho0), myN = momc2(rN, sv[e + RX], c.rho0);
+            div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) +
+                  fmaT(g, mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0), myC + myN) * irc;
+            lap = ((rE + rW) - T(2) * rc) + fmaT(g, (rN + rS) - T(2) * rc, rN - rc) * irc;
+        } else {
+            div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) + mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0);
+            lap = ((rE + rW) + (rN + rS)) - T(4) * rc;
+        }
         srn[q] = fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
     }
     __syncthreads();
@@ -187,7 +229,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         const int ef = ey * RX + ex;
         const T gxp = gisox_num<T, PX>(sp, ep), gyp = gisoy_num<T, PX>(sp, ep);
         const T adv = fmaT(su[ef], gxp, sv[ef] * gyp) * c.gi;
-        const T rhs = fmaT(c.mob * c.li, liso_num<T, MX>(smu, em), -adv);
+        const T rhs = fmaT(c.mob * c.li, lap_a<T, MX, AXI>(smu, em, inv_radius<AXI, T>(y0 + ey - 2)), -adv);
         T val = fmaT(c.dt, rhs, sp[ep]);
         if (mirror && c.wet) {  // a ghost position takes the wetting rule of its wall faces
             const int gx = x0 + lx - 2, gy = y0 + ly - 2;
@@ -208,7 +250,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
             ex = ghost_src(lx, 1, x0, nx, c.bc[0], 0, DX - 1) + 1;
             ey = ghost_src(ly, 1, y0, ny, c.bc[2], 0, S::DY - 1) + 1;
         }
-        sms[q] = chem<T, RX>(c, sps, ey * RX + ex);
+        sms[q] = chem_a<T, RX, AXI>(c, sps, ey * RX + ex, inv_radius<AXI, T>(y0 + ey - 2));
     }
     __syncthreads();
 
@@ -233,10 +275,22 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         const T myE = momc2(rE, vE, rho0), myW = momc2(rW, vW, rho0);
         const T myN = momc2(rN, vN, rho0), myS = momc2(rS, vS, rho0);
         const T rnC = srn[d];
-        const T fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + (mxN * vN - mxS * vS);
-        const T fyy = (myE * uE - myW * uW) + (fmaT(myN, vN, cs2 * rN) - fmaT(myS, vS, cs2 * rS));
-        const T lpx = ((mxE + mxW) + (mxN + mxS)) - T(4) * mxC;
-        const T lpy = ((myE + myW) + (myN + myS)) - T(4) * myC;
+        const T irc = inv_radius<AXI, T>(gy);
+        T fxx, fyy, lpx, lpy;
+        if constexpr (AXI) {  // cylindrical flux forms, hoop term, -m_r / r^2 (kern_axisym.hip)
+            const T g = T(gy);
+            const T pxyC = mxC * vc, pxyN = mxN * vN, pxyS = mxS * vS;
+            const T pyyC = fmaT(myC, vc, cs2 * rc), pyyN = fmaT(myN, vN, cs2 * rN), pyyS = fmaT(myS, vS, cs2 * rS);
+            fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + fmaT(g, pxyN - pxyS, pxyC + pxyN) * irc;
+            fyy = (myE * uE - myW * uW) + fmaT(g, pyyN - pyyS, pyyC + pyyN) * irc - T(2) * cs2 * rc * irc;
+            lpx = ((mxE + mxW) - T(2) * mxC) + fmaT(g, (mxN + mxS) - T(2) * mxC, mxN - mxC) * irc;
+            lpy = ((myE + myW) - T(2) * myC) + fmaT(g, (myN + myS) - T(2) * myC, myN - myC) * irc - myC * irc * irc;
+        } else {
+            fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + (mxN * vN - mxS * vS);
+            fyy = (myE * uE - myW * uW) + (fmaT(myN, vN, cs2 * rN) - fmaT(myS, vS, cs2 * rS));
+            lpx = ((mxE + mxW) + (mxN + mxS)) - T(4) * mxC;
+            lpy = ((myE + myW) + (myN + myS)) - T(4) * myC;
+        }
         const T sx = (srn[d + 1] - srn[d - 1]) - (rE - rW);
         const T sy = (srn[d + DX] - srn[d - DX]) - (rN - rS);
         const T rho_n = rho0 + rnC;
@@ -253,7 +307,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         // Cahn-Hilliard second stage
         const T gxs = gisox_num<T, RX>(sps, e), gys = gisoy_num<T, RX>(sps, e);
         const T adv = fmaT(uc, gxs, vc * gys) * c.gi;
-        const T rhs = fmaT(c.mob * c.li, liso_num<T, DX>(sms, d), -adv);
+        const T rhs = fmaT(c.mob * c.li, lap_a<T, DX, AXI>(sms, d, irc), -adv);
         const T phin = T(0.5) * fmaT(c.dt, rhs, pc + sps[e]);
         const size_t o = (size_t)gy * nx + gx;
         out.r[o] = rnC;
@@ -263,26 +317,43 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
     }
 }
 
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, bool AXI>
 static hipError_t launch2p_variant(const Coef<T>& c, const State<T>& in, const State<T>& out, hipStream_t s)
 {
     const int nbx = (c.nx + TX - 1) / TX, nby = (c.ny + TY - 1) / TY;
-    hipLaunchKernelGGL((twophase2d_kernel<T, TX, TY, NT>), dim3(nbx * nby), dim3(NT), 0, s, c, in, out, nbx);
+    hipLaunchKernelGGL((twophase2d_kernel<T, TX, TY, NT, AXI>), dim3(nbx * nby), dim3(NT), 0, s, c, in, out, nbx);
     return hipGetLastError();
+}
+
+template <typename T, bool AXI>
+static hipError_t launch2p(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile, hipStream_t s)
+{
+    switch (tile) {
+        case 1: return launch2p_variant<T, 32, 8, 256, AXI>(c, in, out, s);
+        case 2: return launch2p_variant<T, 64, 8, 256, AXI>(c, in, out, s);
+        case 3: return launch2p_variant<T, 16, 16, 256, AXI>(c, in, out, s);
+        default: return launch2p_variant<T, 32, 16, 256, AXI>(c, in, out, s);
+    }
 }
 
 template <typename T>
 hipError_t launch_twophase2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile, hipStream_t s)
 {
-    switch (tile) {
-        case 1: return launch2p_variant<T, 32, 8, 256>(c, in, out, s);
-        case 2: return launch2p_variant<T, 64, 8, 256>(c, in, out, s);
-        case 3: return launch2p_variant<T, 16, 16, 256>(c, in, out, s);
-        default: return launch2p_variant<T, 32, 16, 256>(c, in, out, s);
-    }
+    return launch2p<T, false>(c, in, out, tile, s);
+}
+
+template <typename T>
+hipError_t launch_twophase_axisym2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
+                                    hipStream_t s)
+{
+    return launch2p<T, true>(c, in, out, tile, s);
 }
 
 template hipError_t launch_twophase2d<float>(const Coef<float>&, const State<float>&, const State<float>&, int, hipStream_t);
 template hipError_t launch_twophase2d<double>(const Coef<double>&, const State<double>&, const State<double>&, int, hipStream_t);
+template hipError_t launch_twophase_axisym2d<float>(const Coef<float>&, const State<float>&, const State<float>&, int,
+                                                    hipStream_t);
+template hipError_t launch_twophase_axisym2d<double>(const Coef<double>&, const State<double>&, const State<double>&,
+                                                     int, hipStream_t);
 
 }  // namespace acm

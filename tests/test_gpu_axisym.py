@@ -1,7 +1,8 @@
 """GPU parity of the axisymmetric step (x axial, y radial, axis on the -y
 face) against the FP64 oracle: FP64 to 1e-12 on ragged multi-tile grids with
 walls, a moving wall, body force and forcing row; FP32 over 500 steps;
-the discrete Poiseuille fixed point; every tile shape bit for bit; and the
+the discrete Poiseuille fixed point; every tile shape bit for bit; the
+two-phase form (drop on the axis, wetting wall) in FP64 and FP32; and the
 configurations the library rejects."""
 import numpy as np
 import pytest
@@ -115,11 +116,81 @@ def test_axisym_tiles_bitwise_identical(mods):
 def test_axisym_rejected_configurations(mods):
     torch, acm, oracle = mods
     st = inputs.pipe_state(32, 16, seed=1)
-    for kw in (dict(bc=(0, 0, WALL, WALL, 0, 0)), dict(bc=(0, 0, 0, 0, 0, 0)),
-               dict(bc=(0, 0, SYM, WALL, 0, 0), two_phase=True, sigma=0.01, width=4.0, mobility=0.1)):
+    for kw in (dict(bc=(0, 0, WALL, WALL, 0, 0)), dict(bc=(0, 0, 0, 0, 0, 0))):
         cfg = acm.make_config(2, 32, 16, nu=0.05, axisym=True, **kw)
         with pytest.raises(acm.AcmError):
             acm.Solver(cfg, dict(st, phi=np.zeros((16, 32))))
     cfg3 = acm.make_config(3, 16, 16, 16, nu=0.05, bc=(0, 0, SYM, WALL, 0, 0), axisym=True)
     with pytest.raises(acm.AcmError):
         acm.Solver(cfg3, {k: np.zeros((16, 16, 16)) for k in ("drho", "u", "v", "w")})
+
+
+def twophase_case(mods, nx, ny, bc, precision, wet=0.0, tile=0):
+    _, acm, oracle = mods
+    wc = [0.0] * 6
+    wc[3] = wet
+    kw = dict(nu=0.1, bc=bc, two_phase=True, sigma=0.01, width=4.0, mobility=0.1, wet_cos=wc)
+    cfg = acm.make_config(2, nx, ny, precision=precision, axisym=True, tile=tile, **kw)
+    p = oracle.Params(dim=2, nx=nx, ny=ny, axisym=True, **kw)
+    return cfg, p
+
+
+@pytest.mark.parametrize("nx,ny,bc,wet", [(100, 37, (0, 0, SYM, SYM, 0, 0), 0.0),
+                                          (70, 40, (SYM, SYM, SYM, WALL, 0, 0), 0.5),
+                                          (64, 48, (0, 0, SYM, WALL, 0, 0), -0.3)])
+def test_axisym_twophase_f64_matches_oracle(mods, nx, ny, bc, wet):
+    """A drop of radius 14 on the axis (a sphere), perturbed, 20 steps."""
+    torch, acm, oracle = mods
+    cfg, p = twophase_case(mods, nx, ny, bc, "f64", wet=wet)
+    st = inputs.drop_on_axis(nx, ny, 14.0, 4.0)
+    rng = np.random.Generator(np.random.PCG64(nx + ny))
+    st["phi"] = np.clip(st["phi"] + 0.02 * rng.standard_normal((ny, nx)), -1, 1)
+    st["u"] = 0.01 * rng.standard_normal((ny, nx))
+    print(f"axisym two-phase f64 {nx}x{ny} bc {bc} wet {wet}", flush=True)
+    s = acm.Solver(cfg, st)
+    s.run(20)
+    got = s.state()
+    s.close()
+    ref = oracle.run(p, st, 20)
+    for k in KEYS + ("phi",):
+        assert rel(got[k], ref[k]) <= 1e-12, k
+
+
+def test_axisym_twophase_f32_matches_oracle(mods):
+    """300 steps of the relaxing drop on 96 x 48: phi <= 1e-5, velocity and
+    drho <= 1e-3 relative L2 (the flow starts at rest and is driven by the
+    surface-tension force alone, so velocity and drho are small differences,
+    as in the 3D drop of the planar tests)."""
+    torch, acm, oracle = mods
+    nx, ny = 96, 48
+    cfg, p = twophase_case(mods, nx, ny, (0, 0, SYM, SYM, 0, 0), "f32")
+    st = inputs.drop_on_axis(nx, ny, 16.0, 4.0)
+    st = {k: v.astype(np.float32).astype(np.float64) for k, v in st.items()}
+    s = acm.Solver(cfg, st)
+    s.run(300)
+    got = s.state()
+    s.close()
+    ref = oracle.run(p, st, 300)
+    err_u = float(np.sqrt(((got["u"] - ref["u"]) ** 2 + (got["v"] - ref["v"]) ** 2).sum() /
+                          (ref["u"] ** 2 + ref["v"] ** 2).sum()))
+    print(f"two-phase f32 300 steps: phi {rel(got['phi'], ref['phi']):.2e} velocity {err_u:.2e} "
+          f"drho {rel(got['drho'], ref['drho']):.2e}")
+    assert rel(got["phi"], ref["phi"]) <= 1e-5
+    assert err_u <= 1e-3
+    assert rel(got["drho"], ref["drho"]) <= 1e-3
+
+
+def test_axisym_twophase_tiles_bitwise_identical(mods):
+    torch, acm, oracle = mods
+    nx, ny = 100, 37
+    st = inputs.drop_on_axis(nx, ny, 14.0, 4.0)
+    outs = []
+    for tile in (0, 1, 2, 3):
+        cfg, _ = twophase_case(mods, nx, ny, (0, 0, SYM, WALL, 0, 0), "f32", wet=0.4, tile=tile)
+        s = acm.Solver(cfg, st)
+        s.run(30)
+        outs.append(s.state())
+        s.close()
+    for o in outs[1:]:
+        for k in KEYS + ("phi",):
+            assert np.array_equal(o[k], outs[0][k]), k
