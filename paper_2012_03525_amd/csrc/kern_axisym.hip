@@ -5,13 +5,9 @@
 // form with face radii r -+ dx/2 (the face value of a flux is the mean of its
 // two nodes), and the radial momentum gains the hoop term of the divergence
 // of Pi, -Pi_thth / r with Pi_thth = cs^2 drho (no swirl), and the
-// -m_r / r^2 of the vector Laplacian.  With rows j - 1, j, j + 1 at radii
-// (g, g + 1/2, g + 1) dx around node row g, the radial parts are written as
-//   (1/r) d_r(r f):     [g (f_N - f_S) + (f_C + f_N)] / (2 (g + 1/2) dx)
-//   (1/r) d_r(r d_r f): [g (f_N + f_S - 2 f_C) + (f_N - f_C)] / ((g + 1/2) dx^2)
-// (the same sums as the face form, arranged so that FP32 keeps the centred
-// difference instead of cancelling two r-weighted sums).  Staging, ghosts
-// and the per-node density update order are those of the 2D tile kernel.
+// -m_r / r^2 of the vector Laplacian (the radial sums are written out in
+// kern_axisym.h and shared with the two-phase kernel).  Staging, ghosts and
+// the per-node density update order are those of the 2D tile kernel.
 #include <hip/hip_runtime.h>
 
 #include "../../include/acm.h"
@@ -29,12 +25,9 @@ __device__ __forceinline__ T rho_new_axi(const Coef<T>& c, const T* sr, const T*
 {
     const T g = T(gy), irc = T(1) / (T(gy) + T(0.5));
     const T rc = sr[e];
-    const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
-    const T myC = momc(rc, sv[e], c.rho0), myN = momc(rN, sv[e + RX], c.rho0);
-    const T divr = fmaT(g, mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0), myC + myN) * irc;
-    const T div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) + divr;
-    const T lapr = fmaT(g, (rN + rS) - T(2) * rc, rN - rc) * irc;
-    const T lap = ((rE + rW) - T(2) * rc) + lapr;
+    T div, lap;
+    axi_continuity(c.rho0, g, irc, rc, sr[e + 1], sr[e - 1], sr[e + RX], sr[e - RX], su[e + 1], su[e - 1], sv[e],
+                   sv[e + RX], sv[e - RX], div, lap);
     return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
 }
 
@@ -86,14 +79,9 @@ __global__ __launch_bounds__(NT) void axisym2d_kernel(Coef<T> c, State<T> in, St
         const T myN = momc(rN, vN, rho0), myS = momc(rS, vS, rho0);
         const T rnC = srn[d];
         const T rnE = srn[d + 1], rnW = srn[d - 1], rnN = srn[d + DX], rnS = srn[d - DX];
-        // axial flux: d_x Pi_xx + (1/r) d_r(r Pi_xr); radial: d_x Pi_rx + (1/r) d_r(r Pi_rr) - Pi_thth / r
-        const T pxyC = mxC * vc, pxyN = mxN * vN, pxyS = mxS * vS;
-        const T pyyC = fmaT(myC, vc, cs2 * rc), pyyN = fmaT(myN, vN, cs2 * rN), pyyS = fmaT(myS, vS, cs2 * rS);
-        const T fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + fmaT(g, pxyN - pxyS, pxyC + pxyN) * irc;
-        const T fyy = (myE * uE - myW * uW) + fmaT(g, pyyN - pyyS, pyyC + pyyN) * irc - T(2) * cs2 * rc * irc;
-        const T lx_ = ((mxE + mxW) - T(2) * mxC) + fmaT(g, (mxN + mxS) - T(2) * mxC, mxN - mxC) * irc;
-        const T ly_ = ((myE + myW) - T(2) * myC) + fmaT(g, (myN + myS) - T(2) * myC, myN - myC) * irc -
-                      myC * irc * irc;
+        T fxx, fyy, lx_, ly_;
+        axi_momentum(cs2, g, irc, rc, rE, rW, rN, rS, uE, uW, vc, vN, vS, mxC, mxE, mxW, mxN, mxS, myC, myE, myW, myN,
+                     myS, fxx, fyy, lx_, ly_);
         const T sx = (rnE - rnW) - (rE - rW);
         const T sy = (rnN - rnS) - (rN - rS);
         const T rho_n = rho0 + rnC;

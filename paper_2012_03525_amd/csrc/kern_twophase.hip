@@ -15,7 +15,7 @@
 // face, row j at r = (j + 1/2) dx): L_iso gains (1/r) G_iso,r in mu and in
 // the Cahn-Hilliard diffusion, continuity and momentum take the
 // cylindrical flux forms of the single-phase axisymmetric step
-// (kern_axisym.hip); the advection and the surface-tension force are
+// (kern_axisym.h); the advection and the surface-tension force are
 // unchanged.
 // Dependency radii: phi needs a 4-node halo (mu on tile+3, phi* on tile+2,
 // mu* on tile+1), the flow fields a 2-node halo.  Ghost positions of every
@@ -202,12 +202,9 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         const T rc = sr[e];
         const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
         T div, lap;
-        if constexpr (AXI) {  // cylindrical flux forms (kern_axisym.hip)
-            const T g = T(y0 + ey - 2), irc = inv_radius<AXI, T>(y0 + ey - 2);
-            const T myC = momc2(rc, sv[e], c.rho0), myN = momc2(rN, sv[e + RX], c.rho0);
-            div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) +
-                  fmaT(g, mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0), myC + myN) * irc;
-            lap = ((rE + rW) - T(2) * rc) + fmaT(g, (rN + rS) - T(2) * rc, rN - rc) * irc;
+        if constexpr (AXI) {  // cylindrical flux forms (kern_axisym.h)
+            axi_continuity(c.rho0, T(y0 + ey - 2), inv_radius<AXI, T>(y0 + ey - 2), rc, rE, rW, rN, rS, su[e + 1],
+                           su[e - 1], sv[e], sv[e + RX], sv[e - RX], div, lap);
         } else {
             div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) + mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0);
             lap = ((rE + rW) + (rN + rS)) - T(4) * rc;
@@ -277,14 +274,9 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         const T rnC = srn[d];
         const T irc = inv_radius<AXI, T>(gy);
         T fxx, fyy, lpx, lpy;
-        if constexpr (AXI) {  // cylindrical flux forms, hoop term, -m_r / r^2 (kern_axisym.hip)
-            const T g = T(gy);
-            const T pxyC = mxC * vc, pxyN = mxN * vN, pxyS = mxS * vS;
-            const T pyyC = fmaT(myC, vc, cs2 * rc), pyyN = fmaT(myN, vN, cs2 * rN), pyyS = fmaT(myS, vS, cs2 * rS);
-            fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + fmaT(g, pxyN - pxyS, pxyC + pxyN) * irc;
-            fyy = (myE * uE - myW * uW) + fmaT(g, pyyN - pyyS, pyyC + pyyN) * irc - T(2) * cs2 * rc * irc;
-            lpx = ((mxE + mxW) - T(2) * mxC) + fmaT(g, (mxN + mxS) - T(2) * mxC, mxN - mxC) * irc;
-            lpy = ((myE + myW) - T(2) * myC) + fmaT(g, (myN + myS) - T(2) * myC, myN - myC) * irc - myC * irc * irc;
+        if constexpr (AXI) {  // cylindrical flux forms, hoop term, -m_r / r^2 (kern_axisym.h)
+            axi_momentum(cs2, T(gy), irc, rc, rE, rW, rN, rS, uE, uW, vc, vN, vS, mxC, mxE, mxW, mxN, mxS, myC, myE,
+                         myW, myN, myS, fxx, fyy, lpx, lpy);
         } else {
             fxx = (fmaT(mxE, uE, cs2 * rE) - fmaT(mxW, uW, cs2 * rW)) + (mxN * vN - mxS * vS);
             fyy = (myE * uE - myW * uW) + (fmaT(myN, vN, cs2 * rN) - fmaT(myS, vS, cs2 * rS));
