@@ -332,6 +332,8 @@ def generate_windows(spec: FlowSpec, seeds: Sequence[int], warmup: int, windows_
     F(fine_{t + k r}) one coarse step apart.  Returns a list of lists of
     k + 1 state dicts (device tensors)."""
     import torch
+    if stride < k * spec.ratio:
+        raise ValueError(f"stride {stride} is shorter than a window of {k} coarse steps ({k * spec.ratio} fine steps)")
     dev = torch.device("cuda:0")
     shape_c = (spec.n_coarse, spec.n_coarse)
     out = []
