@@ -32,12 +32,14 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16_t;
 
-// float -> bf16, round to nearest even (finite inputs)
-__device__ __forceinline__ bf16_t f2bf(float f)
+// float -> bf16, round to nearest even, by the hardware conversion
+// (v_cvt_pk_bf16_f32 converts two values per instruction)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bf16_t f2bf(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
+__device__ __forceinline__ unsigned f2bf2(float lo, float hi)
 {
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (bf16_t)(u >> 16);
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, bf16x2v));
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((unsigned)h) << 16); }
 
@@ -567,10 +569,7 @@ struct Args {
 
 __device__ __forceinline__ bf16x8 lds8(const bf16_t* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
-__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d)
-{
-    return uint2{(unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16), (unsigned)f2bf(c) | ((unsigned)f2bf(d) << 16)};
-}
+__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) { return uint2{f2bf2(a, b), f2bf2(c, d)}; }
 
 // One 32-input-channel layer: output side SO (input side SO + 2), NH blocks
 // of 16 output channels.  RELU: bias + ReLU into `out`; otherwise the lanes
@@ -594,6 +593,7 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
 #pragma unroll
         for (int j = 0; j < 4; ++j) bb[nh][j] = bias[nh * 16 + 4 * lg + j];
 
+    // the accumulators start from the bias, so acc = conv + b
     auto finish = [&](int g, const f32x4* acc) {
         const int p = 16 * g + l16;
         if (p >= NP) return;
@@ -601,8 +601,8 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
 #pragma unroll
             for (int nh = 0; nh < NH; ++nh)
                 *reinterpret_cast<uint2*>(out + p * AS + nh * 16 + 4 * lg) =
-                    pack4(fmaxf(acc[nh][0] + bb[nh][0], 0.f), fmaxf(acc[nh][1] + bb[nh][1], 0.f),
-                          fmaxf(acc[nh][2] + bb[nh][2], 0.f), fmaxf(acc[nh][3] + bb[nh][3], 0.f));
+                    pack4(fmaxf(acc[nh][0], 0.f), fmaxf(acc[nh][1], 0.f), fmaxf(acc[nh][2], 0.f),
+                          fmaxf(acc[nh][3], 0.f));
         } else {
             if (lg == 0) {
                 const int py = p / SO, px = p - py * SO;
@@ -611,7 +611,7 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
                 for (int c = 0; c < 3; ++c) {
                     // the uncorrected state: from LDS when the kernel ran the step itself
                     const float q = sq ? sq[c * T * T + p] : a.qi[c][o];
-                    a.qo[c][o] = a.d[c] != 0.f ? fmaf(a.d[c], acc[0][c] + bb[0][c], q) : q;
+                    a.qo[c][o] = a.d[c] != 0.f ? fmaf(a.d[c], acc[0][c], q) : q;
                 }
             }
         }
@@ -627,7 +627,7 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
         const int b0 = base_of(g), b1 = base_of(g + NW);
         f32x4 a0[NH], a1[NH];
 #pragma unroll
-        for (int nh = 0; nh < NH; ++nh) a0[nh] = a1[nh] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nh = 0; nh < NH; ++nh) a0[nh] = a1[nh] = f32x4{bb[nh][0], bb[nh][1], bb[nh][2], bb[nh][3]};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int off = ((t / 3 - 1) * SN + (t % 3 - 1)) * AS;
@@ -645,7 +645,7 @@ __device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const flo
         const int b0 = base_of(g);
         f32x4 a0[NH];
 #pragma unroll
-        for (int nh = 0; nh < NH; ++nh) a0[nh] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nh = 0; nh < NH; ++nh) a0[nh] = f32x4{bb[nh][0], bb[nh][1], bb[nh][2], bb[nh][3]};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int off = ((t / 3 - 1) * SN + (t % 3 - 1)) * AS;
@@ -797,14 +797,15 @@ __global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a, Coe
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 x[j] = 8 * lg + j < 27 ? __builtin_bit_cast(__bf16, sb[base + koff[j]]) : __bf16(0.f);
-            f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, x, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-            f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, x, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            // accumulators start from the bias
+            f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, x, f32x4{bb[0][0], bb[0][1], bb[0][2], bb[0][3]},
+                                                              0, 0, 0);
+            f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, x, f32x4{bb[1][0], bb[1][1], bb[1][2], bb[1][3]},
+                                                              0, 0, 0);
             *reinterpret_cast<uint2*>(sa + p * AS + 4 * lg) =
-                pack4(fmaxf(c0[0] + bb[0][0], 0.f), fmaxf(c0[1] + bb[0][1], 0.f), fmaxf(c0[2] + bb[0][2], 0.f),
-                      fmaxf(c0[3] + bb[0][3], 0.f));
+                pack4(fmaxf(c0[0], 0.f), fmaxf(c0[1], 0.f), fmaxf(c0[2], 0.f), fmaxf(c0[3], 0.f));
             *reinterpret_cast<uint2*>(sa + p * AS + 16 + 4 * lg) =
-                pack4(fmaxf(c1[0] + bb[1][0], 0.f), fmaxf(c1[1] + bb[1][1], 0.f), fmaxf(c1[2] + bb[1][2], 0.f),
-                      fmaxf(c1[3] + bb[1][3], 0.f));
+                pack4(fmaxf(c1[0], 0.f), fmaxf(c1[1], 0.f), fmaxf(c1[2], 0.f), fmaxf(c1[3], 0.f));
         }
     }
     __syncthreads();
