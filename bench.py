@@ -228,10 +228,11 @@ def cpu_baseline(name, cfg, st, budget_s):
     import oracle
     oracle.build(force=False)
     p = oracle.Params(dim=cfg.dim, nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, dx=cfg.dx, dt=cfg.dt, nu=cfg.nu,
-                      cs=(cfg.cs if cfg.cs > 0 else cfg.dx / (cfg.dt * math.sqrt(3))),
+                      cs=(cfg.cs if cfg.cs > 0 else cfg.dx / (cfg.dt * math.sqrt(3))), rho0=cfg.rho0,
+                      sat_rho=cfg.sat_rho, sat_mom=cfg.sat_mom, g=[cfg.g[a] for a in range(3)],
                       bc=list(cfg.bc), wall_u=[[cfg.wall_u[f][a] for a in range(3)] for f in range(6)],
                       two_phase=bool(cfg.two_phase), sigma=cfg.sigma, width=cfg.width, mobility=cfg.mobility,
-                      wet_cos=[cfg.wet_cos[f] for f in range(6)])
+                      wet_cos=[cfg.wet_cos[f] for f in range(6)], axisym=bool(cfg.axisym))
     nodes = cfg.nx * cfg.ny * (cfg.nz if cfg.dim == 3 else 1)
     t0 = time.perf_counter()
     steps = 0
@@ -242,9 +243,15 @@ def cpu_baseline(name, cfg, st, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or steps >= 1000:
             break
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": nodes * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{steps} whole-grid FP64 steps of the same workload ({nodes} nodes) in {el:.1f} s, "
-                      f"single thread, host has {os.cpu_count()} logical CPUs"}
+                      f"single thread, host has {os.cpu_count()} logical CPUs ({model})"}
 
 
 def main():
