@@ -194,3 +194,62 @@ def test_axisym_twophase_tiles_bitwise_identical(mods):
     for o in outs[1:]:
         for k in KEYS + ("phi",):
             assert np.array_equal(o[k], outs[0][k]), k
+
+
+def _bench_cfg(mods, name):
+    """The bench line's own configuration and initial state for a workload."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "bench_mod", os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    cfg, st, _, _, _ = bench.workload(name, 0)
+    return cfg, st
+
+
+def _oparams(oracle, cfg):
+    return oracle.Params(dim=2, nx=cfg.nx, ny=cfg.ny, nu=cfg.nu, g=[cfg.g[a] for a in range(3)], bc=list(cfg.bc),
+                         two_phase=bool(cfg.two_phase), sigma=cfg.sigma, width=cfg.width, mobility=cfg.mobility,
+                         axisym=True)
+
+
+def test_pipe_full_size_one_step(mods):
+    """The 4096 x 2048 axisymmetric pipe of the bench (FP32, default launch
+    shape): one step node by node against the oracle."""
+    torch, acm, oracle = mods
+    cfg, st = _bench_cfg(mods, "pipe_axisym_4096x2048")
+    st = {k: v.astype(np.float32).astype(np.float64) for k, v in st.items()}
+    print("axisym pipe 4096x2048 one step", flush=True)
+    s = acm.Solver(cfg, st)
+    s.step()
+    g = s.state()
+    s.close()
+    o = oracle.step(_oparams(oracle, cfg), st)
+    umax = max(np.abs(o[k]).max() for k in ("u", "v"))
+    for k in ("u", "v"):
+        assert np.abs(g[k] - o[k]).max() / umax < 1e-6, k
+    assert np.abs(g["drho"] - o["drho"]).max() < 1e-9
+
+
+def test_drop_axisym_full_size_one_step(mods):
+    """The 2048 x 1024 axisymmetric drop of the bench (FP32): one step node by
+    node against the oracle.  The first step's velocity is the surface-tension
+    impulse alone (1.4e-4 here, R = 256), while the kernel's FP32 chemical
+    potential carries rounding of about kappa (20/6) ulp(1) = 0.015 * 3.3 *
+    6e-8 = 3e-9 in the bulk (phi^2 - 1 and L_iso phi of values one ulp from
+    +-1), which one step turns into a velocity error of the same size whatever
+    the drop radius; the bound is therefore absolute, 2e-8."""
+    torch, acm, oracle = mods
+    cfg, st = _bench_cfg(mods, "drop_axisym_2048x1024")
+    st = {k: v.astype(np.float32).astype(np.float64) for k, v in st.items()}
+    print("axisym drop 2048x1024 one step", flush=True)
+    s = acm.Solver(cfg, st)
+    s.step()
+    g = s.state()
+    s.close()
+    o = oracle.step(_oparams(oracle, cfg), st)
+    for k in ("u", "v"):
+        assert np.abs(g[k] - o[k]).max() < 2e-8, k
+    assert np.abs(g["phi"] - o["phi"]).max() < 1e-6
+    assert np.abs(g["drho"] - o["drho"]).max() < 1e-9
