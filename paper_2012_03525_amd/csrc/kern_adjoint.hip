@@ -40,7 +40,7 @@ constexpr int ATX = 64, ATY = 4, ANT = 256;
 
 // periodic index for -2 <= i < n + ATX + 2 (a tile's staging region may pass
 // the far end of a grid narrower than the tile more than once)
-__device__ __forceinline__ int pwrap(int i, int n) { return (i + 2 * n) % n; }
+__device__ __forceinline__ int pwrap(int i, int n) { return (int)(((long long)i + 2LL * n) % n); }
 
 template <typename T>
 __global__ __launch_bounds__(ANT) void step2d_adjoint_kernel(Coef<T> c, State<T> q, State<T> s, State<T> as,

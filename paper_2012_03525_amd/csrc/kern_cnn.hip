@@ -17,6 +17,7 @@
 // n + 16*(i/4), element i%4.  Here i = pixel (forward) and k, n = channels.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -865,6 +866,8 @@ acm_status chip(hipError_t e, const char* what)
     return e == hipErrorInvalidValue ? ACM_EINVAL : ACM_EHIP;
 }
 bool grid_ok(int nx, int ny) { return nx > 0 && ny > 0 && nx % 64 == 0 && ny % 8 == 0; }
+// per-pixel kernels index pixels with int
+bool pixels_ok(int nx, int ny) { return nx > 0 && ny > 0 && (int64_t)nx * ny <= INT32_MAX - 256; }
 int blocks_for(size_t n) { return (int)((n + 255) / 256); }
 }  // namespace
 
@@ -946,7 +949,7 @@ acm_status acm_cnn_transpose(int32_t cin, int32_t cout, const void* w, void* wt,
 acm_status acm_cnn_pack(int32_t nx, int32_t ny, const float* drho, const float* u, const float* v,
                         const float* in_scale, void* a0, void* stream)
 {
-    if (!drho || !u || !v || !in_scale || !a0 || nx <= 0 || ny <= 0) return cfail(ACM_EINVAL, "bad pack arguments");
+    if (!drho || !u || !v || !in_scale || !a0 || !pixels_ok(nx, ny)) return cfail(ACM_EINVAL, "bad pack arguments");
     const int n = nx * ny;
     hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, drho,
                        u, v, in_scale[0], in_scale[1], in_scale[2], static_cast<bf16_t*>(a0));
@@ -956,7 +959,7 @@ acm_status acm_cnn_pack(int32_t nx, int32_t ny, const float* drho, const float* 
 acm_status acm_cnn_apply(int32_t nx, int32_t ny, const float* raw, const float* out_scale, float* drho, float* u,
                          float* v, void* stream)
 {
-    if (!raw || !out_scale || !drho || !u || !v || nx <= 0 || ny <= 0) return cfail(ACM_EINVAL, "bad apply arguments");
+    if (!raw || !out_scale || !drho || !u || !v || !pixels_ok(nx, ny)) return cfail(ACM_EINVAL, "bad apply arguments");
     const int n = nx * ny;
     hipLaunchKernelGGL(apply_correction_kernel, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
                        n, raw, out_scale[0], out_scale[1], out_scale[2], drho, u, v);
@@ -969,6 +972,7 @@ acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* c
                         const float* out_scale, void* grad, double* workspace, double* loss, void* stream)
 {
     if (!raw || !base || !target || !out_scale || !grad || !workspace || !loss) return cfail(ACM_EINVAL, "NULL pointer");
+    if (!pixels_ok(nx, ny)) return cfail(ACM_EINVAL, "bad grid");
     const int n = nx * ny;
     const int nb = blocks_for(n);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -993,7 +997,7 @@ acm_status acm_cnn_state_loss(int32_t nx, int32_t ny, const float* const* q, con
                               double* loss, void* stream)
 {
     if (!q || !target || !out_scale || !adj || !workspace || !loss) return cfail(ACM_EINVAL, "NULL pointer");
-    if (nx <= 0 || ny <= 0) return cfail(ACM_EINVAL, "bad grid");
+    if (!pixels_ok(nx, ny)) return cfail(ACM_EINVAL, "bad grid");
     for (int c = 0; c < 3; ++c)
         if (!q[c] || !target[c] || !adj[c]) return cfail(ACM_EINVAL, "NULL field");
     if (!std::isfinite(weight)) return cfail(ACM_EINVAL, "weight must be finite");
@@ -1023,7 +1027,7 @@ acm_status acm_cnn_div_penalty(int32_t nx, int32_t ny, const float* const* a, co
                                void* stream)
 {
     if (!a || !b || !adj_a || !workspace || !loss) return cfail(ACM_EINVAL, "NULL pointer");
-    if (nx < 3 || ny < 3) return cfail(ACM_EINVAL, "grid needs nx, ny >= 3");
+    if (nx < 3 || ny < 3 || !pixels_ok(nx, ny)) return cfail(ACM_EINVAL, "grid needs nx, ny >= 3");
     if (!a[0] || !a[1] || !b[0] || !b[1] || !adj_a[0] || !adj_a[1]) return cfail(ACM_EINVAL, "NULL field");
     if (adj_b && (!adj_b[0] || !adj_b[1])) return cfail(ACM_EINVAL, "NULL field");
     if (!std::isfinite(weight)) return cfail(ACM_EINVAL, "weight must be finite");

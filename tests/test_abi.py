@@ -230,3 +230,42 @@ def test_calibration_refinement_is_exact_on_band_limited_fields():
     f = {"u": np.sin(3 * x)[None, :] * np.cos(2 * x)[:, None]}
     g = _refine2(f, n)["u"]
     assert np.abs(g - np.sin(3 * x2)[None, :] * np.cos(2 * x2)[:, None]).max() < 1e-13
+
+
+def test_training_entry_points_reject_bad_arguments_without_touching_the_gpu():
+    """acm_cnn_state_loss, acm_cnn_div_penalty, acm_step_adjoint and the
+    per-pixel pack / apply calls reject NULL pointers, bad scales, non-finite
+    weights and pixel counts beyond int before any launch."""
+    L = acm.lib()
+    P3 = ctypes.c_void_p * 3
+    P2 = ctypes.c_void_p * 2
+    q, t, a = P3(1 << 20, 2 << 20, 3 << 20), P3(4 << 20, 5 << 20, 6 << 20), P3(7 << 20, 8 << 20, 9 << 20)
+    ok = (ctypes.c_float * 3)(0.0, 1.0, 1.0)
+    for sc in ((0.0, 0.0, 0.0), (1.0, -1.0, 1.0), (1.0, float("nan"), 1.0)):
+        s = (ctypes.c_float * 3)(*sc)
+        assert L.acm_cnn_state_loss(64, 64, q, t, s, 1.0, a, 10 << 20, 11 << 20, None) == acm.EINVAL, sc
+    assert L.acm_cnn_state_loss(64, 64, q, t, ok, float("nan"), a, 10 << 20, 11 << 20, None) == acm.EINVAL
+    assert L.acm_cnn_state_loss(70000, 70000, q, t, ok, 1.0, a, 10 << 20, 11 << 20, None) == acm.EINVAL
+    assert L.acm_cnn_state_loss(64, 64, None, t, ok, 1.0, a, 10 << 20, 11 << 20, None) == acm.EINVAL
+    u2, v2, g2 = P2(1 << 20, 2 << 20), P2(3 << 20, 4 << 20), P2(5 << 20, 6 << 20)
+    assert L.acm_cnn_div_penalty(2, 64, u2, v2, 1.0, g2, None, 10 << 20, 11 << 20, None) == acm.EINVAL
+    assert L.acm_cnn_div_penalty(64, 64, u2, v2, float("inf"), g2, None, 10 << 20, 11 << 20, None) == acm.EINVAL
+    assert L.acm_cnn_div_penalty(70000, 70000, u2, v2, 1.0, g2, None, 10 << 20, 11 << 20, None) == acm.EINVAL
+    assert L.acm_cnn_div_penalty(64, 64, u2, v2, 1.0, None, None, 10 << 20, 11 << 20, None) == acm.EINVAL
+    sc = (ctypes.c_float * 3)(1.0, 1.0, 1.0)
+    assert L.acm_cnn_pack(70000, 70000, 1 << 20, 2 << 20, 3 << 20, sc, 4 << 20, None) == acm.EINVAL
+    assert L.acm_cnn_apply(70000, 70000, 1 << 20, sc, 2 << 20, 3 << 20, 4 << 20, None) == acm.EINVAL
+    f = acm.Fields(1 << 20, 2 << 20, 3 << 20, None, None)
+    assert L.acm_step_adjoint(None, ctypes.byref(f), ctypes.byref(f), ctypes.byref(f), ctypes.byref(f)) == acm.EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(dim=3, nz=16, bc=(0, 0, 2, 1, 0, 0)),     # axisymmetric runs are 2D
+                                dict(bc=(0, 0, 1, 1, 0, 0)),                    # the axis must be a symmetry plane
+                                dict(bc=(0, 0, 0, 0, 0, 0))])                   # periodic in r
+def test_axisymmetric_config_checks_without_touching_the_gpu(kw):
+    args = dict(kw)
+    dim = args.pop("dim", 2)
+    nz = args.pop("nz", 1)
+    cfg = acm.make_config(dim, 16, 16, nz, nu=0.05, axisym=True, **args)
+    assert _init(cfg) == acm.EINVAL
+    assert b"axis" in acm.lib().acm_last_error()
