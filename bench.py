@@ -33,7 +33,7 @@ def parse():
                     choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024", "drop_spreading_96", "batch512",
                              "pipe_axisym_4096x2048", "drop_axisym_2048x1024"])
     ap.add_argument("--no-closure", action="store_true",
-                    help="skip the closure step timing in the default workload's line")
+                    help="skip the closure step timing and evaluation in the default workload's line")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--batch-mode", type=int, default=0, choices=(0, 1),
                     help="batch512: 0 one workgroup per item, 1 persistent work queue")
@@ -222,6 +222,27 @@ def closure_timing(steps: int = 2000):
             "speedup_vs_fine": round(t["fine_steps_per_coarse_step_us"] / t["closure_step_us"], 3)}
 
 
+def closure_evaluation(train_seeds=(0, 50), eval_seeds=(2000, 2010)):
+    """The learned-coarse vs plain-fine comparison, live and bounded: the
+    full preset's recipe (256^2 coarse / 1024^2 fine, 10,000 coarse steps)
+    trained on fewer seeds and evaluated on ten held-out seeds; time to
+    solution of the gated closure run (gates and fallbacks included) against
+    40,000 plain fine steps, and the largest relative L2 velocity error over
+    the gates.  The 50-seed evaluation is the closure experiment's."""
+    from paper_2012_03525_amd import closure_experiment
+    t0 = time.perf_counter()
+    r, _ = closure_experiment.run_experiment("full", log=lambda m: None, train_seeds=train_seeds,
+                                             eval_seeds=eval_seeds)
+    return {"train_seeds": list(train_seeds), "eval_seeds": list(eval_seeds),
+            "time_to_solution_closure_ms": round(r["mean_t_closure_s"] * 1e3, 2),
+            "time_to_solution_fine_ms": round(r["mean_t_fine_s"] * 1e3, 2),
+            "speedup": round(r["mean_t_fine_s"] / r["mean_t_closure_s"], 3),
+            "max_rel_l2_err_closure": round(r["max_err_closure_max"], 5),
+            "gate_trips": r["gate_trips"],
+            "seeds_within_2pct_and_faster": r["seeds_closure_within_2pct_and_faster"],
+            "wall_s": round(time.perf_counter() - t0, 1)}
+
+
 def cpu_baseline(name, cfg, st, budget_s):
     """Time the FP64 CPU oracle (single thread) on a bounded sample of the
     same workload: whole-grid steps until about budget_s seconds pass."""
@@ -329,6 +350,8 @@ def main():
     if a.workload == "tgv3d_256" and not a.no_closure:
         print("[bench] closure step timing...", file=sys.stderr, flush=True)
         out["closure"] = closure_timing()
+        print("[bench] closure train + evaluation (10 held-out seeds)...", file=sys.stderr, flush=True)
+        out["closure"]["evaluation"] = closure_evaluation()
     if not a.no_cpu:
         print("[bench] CPU oracle baseline...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.workload, cfg, st, a.cpu_seconds)
