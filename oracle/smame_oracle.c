@@ -531,8 +531,14 @@ int orc_diag(const orc_params* p, const double* drho, const double* u,
     fill_velocity(p, &g, uu[0], uu[1], uu[2]);
     long st[3];
     axis_strides(&g, st);
+    /* axisymmetric runs weight every node by its cell volume 2 pi r dx^2
+     * (row j at r = (j + 1/2) dx): sums (mass, momentum, kinetic energy,
+     * sum phi) are volume integrals and the means (enstrophy, energy, rms
+     * divergence) are volume averages; planar runs weight nodes by 1 and
+     * scale the sums by dx^D */
+    const double PI = 3.14159265358979323846;
     double dxd = (nv == 3) ? p->dx * p->dx * p->dx : p->dx * p->dx;
-    long n = (long)g.nx * g.ny * g.nz;
+    double vol = 0;
     double mass = 0, mom[3] = {0, 0, 0}, ke = 0, dumax = 0, umax = 0, ens = 0;
     double div2 = 0, divmax = 0, phisum = 0;
     int bad = 0;
@@ -541,14 +547,16 @@ int orc_diag(const orc_params* p, const double* drho, const double* u,
             for (int i = 0; i < g.nx; ++i) {
                 long c = P(&g, i, j, k);
                 long d = D(&g, i, j, k);
+                const double cv = p->axisym ? 2.0 * PI * (j + 0.5) * p->dx * dxd : 1.0;
+                vol += cv;
                 double rho = p->rho0 + drho[d];
                 double q2 = 0;
                 for (int a = 0; a < nv; ++a) {
-                    mom[a] += rho * uu[a][c];
+                    mom[a] += rho * uu[a][c] * cv;
                     q2 += uu[a][c] * uu[a][c];
                 }
-                mass += drho[d];
-                ke += q2;
+                mass += drho[d] * cv;
+                ke += q2 * cv;
                 double mag = sqrt(q2);
                 if (mag > umax) umax = mag;
                 if (prev_u) {
@@ -572,27 +580,33 @@ int orc_diag(const orc_params* p, const double* drho, const double* u,
                     double oz = du[1][0] - du[0][1];
                     om2 = ox * ox + oy * oy + oz * oz;
                 }
-                ens += om2;
+                ens += om2 * cv;
                 double dv = 0;
                 for (int a = 0; a < nv; ++a) dv += du[a][a];
-                div2 += dv * dv;
+                if (p->axisym) {  /* (1/r) d_r(r u_r) in the face form of the step */
+                    const double rc = j + 0.5, rp = j + 1.0, rm = j;
+                    dv = du[0][0] + (rp * (uu[1][c] + uu[1][c + st[1]]) - rm * (uu[1][c - st[1]] + uu[1][c])) /
+                                        (2.0 * p->dx * rc);
+                }
+                div2 += dv * dv * cv;
                 if (fabs(dv) > divmax) divmax = fabs(dv);
-                if (p->two_phase && phi) phisum += phi[d];
+                if (p->two_phase && phi) phisum += phi[d] * cv;
                 double vals[5] = {drho[d], u[d], v[d], (nv == 3) ? w[d] : 0.0,
                                   (p->two_phase && phi) ? phi[d] : 0.0};
                 for (int f = 0; f < 5; ++f)
                     if (!isfinite(vals[f])) bad = 1;
             }
-    out[0] = mass * dxd;
-    out[1] = mom[0] * dxd;
-    out[2] = mom[1] * dxd;
-    out[3] = mom[2] * dxd;
-    out[4] = 0.5 * ke * dxd;
+    const double sc = p->axisym ? 1.0 : dxd;  /* planar sums are node sums times dx^D */
+    out[0] = mass * sc;
+    out[1] = mom[0] * sc;
+    out[2] = mom[1] * sc;
+    out[3] = mom[2] * sc;
+    out[4] = 0.5 * ke * sc;
     out[5] = dumax;
     out[6] = umax;
-    out[7] = ens / (2.0 * (double)n);
-    out[8] = ke / (2.0 * (double)n);
-    out[9] = sqrt(div2 / (double)n);
+    out[7] = ens / (2.0 * vol);
+    out[8] = ke / (2.0 * vol);
+    out[9] = sqrt(div2 / vol);
     out[10] = divmax;
     out[11] = phisum;
     out[12] = bad ? 1.0 : 0.0;

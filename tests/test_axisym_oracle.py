@@ -165,3 +165,38 @@ def test_axisym_cahn_hilliard_conserves_r_weighted_phi_from_rest(orc):
     r = (np.arange(ny) + 0.5)[:, None]
     assert abs(float((r * (out["phi"] - st["phi"])).sum())) <= 1e-14 * float((r * np.abs(st["phi"])).sum())
     assert abs(float((out["phi"] - st["phi"]).sum())) > 1e-3
+
+
+def test_axisym_diagnostics_are_volume_integrals(orc):
+    """Axisymmetric diagnostics weight each node by its cell volume
+    2 pi r dx^2: a uniform state drho = c, u = U in a pipe of radius R = ny dx
+    and length L = nx dx has mass c pi R^2 L, axial momentum (1 + c) U pi R^2 L,
+    kinetic energy U^2 pi R^2 L / 2 and volume-averaged energy U^2 / 2; the
+    planar diagnostics of the same arrays are the plain node sums times
+    dx^2."""
+    nx, ny, dx, c, U = 12, 9, 0.5, 2e-3, 0.04
+    st = {"drho": np.full((ny, nx), c), "u": np.full((ny, nx), U), "v": np.zeros((ny, nx))}
+    vol = np.pi * (ny * dx) ** 2 * (nx * dx)
+    p = orc.Params(dim=2, nx=nx, ny=ny, dx=dx, nu=0.05, bc=(0, 0, SYM, SYM, 0, 0), axisym=True)
+    d = orc.diag(p, st)
+    assert abs(d["mass"] - c * vol) <= 1e-14 * c * vol
+    assert abs(d["mom_x"] - (1 + c) * U * vol) <= 1e-14 * U * vol
+    assert abs(d["ke"] - 0.5 * U * U * vol) <= 1e-14 * U * U * vol
+    assert abs(d["energy"] - 0.5 * U * U) <= 1e-15
+    assert d["div_max"] == 0.0
+    pp = orc.Params(dim=2, nx=nx, ny=ny, dx=dx, nu=0.05, bc=(0, 0, SYM, SYM, 0, 0))
+    dp = orc.diag(pp, st)
+    assert abs(dp["mass"] - c * nx * ny * dx * dx) <= 1e-15
+
+
+def test_axisym_diagnostic_mass_is_conserved(orc):
+    """The volume-integral mass of an axisymmetric run is invariant (it is
+    2 pi dx^3 sum((j + 1/2) drho))."""
+    nx, ny = 16, 10
+    wu = [[0.0] * 3 for _ in range(6)]
+    wu[3] = [0.03, 0.0, 0.0]
+    p = pipe(orc, nx, ny, 0.05, 2e-6, wall_u=wu)
+    st = inputs.seeded_state((ny, nx), seed=46, scale_u=0.03, scale_r=2e-3)
+    m0 = orc.diag(p, st)["mass"]
+    m1 = orc.diag(p, orc.run(p, st, 40))["mass"]
+    assert abs(m1 - m0) <= 1e-14 * abs(m0)
