@@ -111,8 +111,9 @@ typedef struct acm_config {
                                radial momentum; two-phase runs add
                                (1/r) G_iso,r to L_iso in mu and in (2.14).
                                The stability guard uses the planar symbol;
-                               diagnostics are plain node sums (not
-                               r-weighted).  0: planar                      */
+                               diagnostics are volume integrals and volume
+                               averages (cell volume 2 pi r dx^2) with the
+                               cylindrical divergence.  0: planar           */
 } acm_config;
 
 /* Device pointers of one complete state.  w is used in 3D only, phi in
@@ -126,7 +127,10 @@ typedef struct acm_fields {
 } acm_fields;
 
 /* Diagnostics of the newest state (all FP64, deterministic reductions).
- * Sums over nodes use the cell volume dx^D where stated. */
+ * Sums over nodes use the cell volume dx^D where stated; in axisymmetric
+ * runs the cell volume is 2 pi r dx^2, phi_sum is weighted the same way, the
+ * means over S are volume averages and the divergence is the cylindrical
+ * one of the continuity update. */
 typedef struct acm_diag {
     double mass;        /* sum(drho) dx^D                                      */
     double mom[3];      /* sum(rho u_a) dx^D                                   */

@@ -381,7 +381,15 @@ acm_status acm_diagnostics(acm_handle* h, acm_diag* out)
     const acm_config& c = h->cfg;
     hipError_t e;
     const int have_prev = h->step > 0 ? 1 : 0;
-    if (c.precision == ACM_F64)
+    if (c.axisym && c.precision == ACM_F64)
+        e = launch_diag_axisym<double>(h->cd, c.two_phase, state_of<double>(h->set[h->which]),
+                                       state_of<double>(h->set[1 - h->which]), have_prev, h->partials,
+                                       h->diag_blocks, h->result, h->stream);
+    else if (c.axisym)
+        e = launch_diag_axisym<float>(h->cf, c.two_phase, state_of<float>(h->set[h->which]),
+                                      state_of<float>(h->set[1 - h->which]), have_prev, h->partials,
+                                      h->diag_blocks, h->result, h->stream);
+    else if (c.precision == ACM_F64)
         e = launch_diag<double>(h->cd, c.dim, c.two_phase, state_of<double>(h->set[h->which]),
                                 state_of<double>(h->set[1 - h->which]), have_prev, h->partials, h->diag_blocks,
                                 h->result, h->stream);
@@ -395,8 +403,12 @@ acm_status acm_diagnostics(acm_handle* h, acm_diag* out)
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     const double* r = h->host;
-    const double dxd = c.dim == 3 ? c.dx * c.dx * c.dx : c.dx * c.dx;
-    const double n = (double)c.nx * c.ny * (c.dim == 3 ? c.nz : 1);
+    // planar: node sums times dx^D, means over the node count; axisymmetric:
+    // sums of (j + 1/2) x value times 2 pi dx^3 (cell volume 2 pi r dx^2),
+    // means over the summed weights nx ny^2 / 2
+    const double pi = 3.14159265358979323846;
+    const double dxd = c.axisym ? 2.0 * pi * c.dx * c.dx * c.dx : (c.dim == 3 ? c.dx * c.dx * c.dx : c.dx * c.dx);
+    const double n = c.axisym ? 0.5 * (double)c.nx * c.ny * c.ny : (double)c.nx * c.ny * (c.dim == 3 ? c.nz : 1);
     const double inv2dx = 1.0 / (2.0 * c.dx);
     out->mass = r[0] * dxd;
     out->mom[0] = r[1] * dxd;
@@ -409,7 +421,7 @@ acm_status acm_diagnostics(acm_handle* h, acm_diag* out)
     out->energy = r[4] / (2.0 * n);
     out->div_rms = std::sqrt(r[8] / n) * inv2dx;
     out->div_max = r[9] * inv2dx;
-    out->phi_sum = r[10];
+    out->phi_sum = c.axisym ? r[10] * dxd : r[10];
     out->nonfinite = r[11] != 0.0 ? 1 : 0;
     out->step = h->step;
     out->which = h->which;

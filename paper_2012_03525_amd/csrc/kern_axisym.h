@@ -58,6 +58,13 @@ __device__ __forceinline__ void axi_momentum(T cs2, T g, T irc, T rC, T rE, T rW
 template <typename T>
 hipError_t launch_axisym2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile, hipStream_t s);
 
+// Diagnostics of an axisymmetric state (kern_diag.hip): the reductions of
+// launch_diag with every sum weighted by the node's radius (j + 1/2) dx / dx
+// and the cylindrical divergence.
+template <typename T>
+hipError_t launch_diag_axisym(const Coef<T>& c, int two_phase, const State<T>& cur, const State<T>& prev,
+                              int have_prev, double* partials, int nblocks, double* result, hipStream_t s);
+
 // One axisymmetric two-phase step (kern_twophase.hip); tile codes as for the
 // planar two-phase step.
 template <typename T>

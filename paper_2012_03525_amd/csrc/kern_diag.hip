@@ -10,7 +10,11 @@
 //  6 max |u|             7 sum |omega|^2 (centred vorticity, Eq. 3.4)
 //  8 sum div^2           9 max |div|   (centred divergence of u)
 // 10 sum phi            11 nonfinite flag (max)
+// Axisymmetric runs (AXI) weight the sums by the node's radius (j + 1/2), in
+// units of dx (the host scales by 2 pi dx^3 or divides by the summed
+// weights), and take the divergence in the cylindrical face form of the step.
 #include "acm_internal.h"
+#include "kern_axisym.h"
 
 namespace acm {
 
@@ -34,7 +38,7 @@ __device__ __forceinline__ void load_vel(const Coef<T>& c, int dim, const State<
     w = (double)qw;
 }
 
-template <typename T>
+template <typename T, bool AXI>
 __global__ __launch_bounds__(256) void diag_partial_kernel(Coef<T> c, int dim, int two_phase, State<T> cur,
                                                            State<T> prev, int have_prev, double* partials)
 {
@@ -50,12 +54,13 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(Coef<T> c, int dim, i
         const double u = (double)cur.u[i], v = (double)cur.v[i];
         const double w = dim == 3 ? (double)cur.w[i] : 0.0;
         const double rho = (double)c.rho0 + r;
-        acc[0] += r;
-        acc[1] += rho * u;
-        acc[2] += rho * v;
-        acc[3] += rho * w;
+        const double cv = AXI ? (double)gy + 0.5 : 1.0;  // node weight
+        acc[0] += r * cv;
+        acc[1] += rho * u * cv;
+        acc[2] += rho * v * cv;
+        acc[3] += rho * w * cv;
         const double q2 = u * u + v * v + w * w;
-        acc[4] += q2;
+        acc[4] += q2 * cv;
         const double mag = sqrt(q2);
         acc[6] = fmax(acc[6], mag);
         if (have_prev) {
@@ -65,6 +70,7 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(Coef<T> c, int dim, i
         }
         // centred derivatives d_b u_a (times 2 dx)
         double d[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        double vN = 0.0;
         {
             double a0, a1, a2, b0, b1, b2;
             load_vel(c, dim, cur, gx + 1, gy, gz, a0, a1, a2);
@@ -73,6 +79,7 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(Coef<T> c, int dim, i
             d[1][0] = a1 - b1;
             d[2][0] = a2 - b2;
             load_vel(c, dim, cur, gx, gy + 1, gz, a0, a1, a2);
+            vN = a1;
             load_vel(c, dim, cur, gx, gy - 1, gz, b0, b1, b2);
             d[0][1] = a0 - b0;
             d[1][1] = a1 - b1;
@@ -93,14 +100,15 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(Coef<T> c, int dim, i
             const double ox = d[2][1] - d[1][2], oy = d[0][2] - d[2][0], oz = d[1][0] - d[0][1];
             om2 = ox * ox + oy * oy + oz * oz;
         }
-        acc[7] += om2;  // scaled by 1/(2 dx)^2 on the host
-        const double dv = d[0][0] + d[1][1] + d[2][2];
-        acc[8] += dv * dv;
+        acc[7] += om2 * cv;  // scaled by 1/(2 dx)^2 on the host
+        // (times 2 dx) cylindrical: d_z u_z + [g (v_N - v_S) + (v_C + v_N)] / (g + 1/2)
+        const double dv = AXI ? d[0][0] + ((double)gy * d[1][1] + (v + vN)) / cv : d[0][0] + d[1][1] + d[2][2];
+        acc[8] += dv * dv * cv;
         acc[9] = fmax(acc[9], fabs(dv));
         double ph = 0.0;
         if (two_phase) {
             ph = (double)cur.phi[i];
-            acc[10] += ph;
+            acc[10] += ph * cv;
         }
         const double chk = r + u + v + w + ph;
         if (!isfinite(chk)) acc[11] = 1.0;
@@ -145,17 +153,36 @@ __global__ __launch_bounds__(256) void diag_final_kernel(const double* partials,
     }
 }
 
-template <typename T>
-hipError_t launch_diag(const Coef<T>& c, int dim, int two_phase, const State<T>& cur, const State<T>& prev,
-                       int have_prev, double* partials, int nblocks, double* result, hipStream_t s)
+template <typename T, bool AXI>
+hipError_t launch_diag_impl(const Coef<T>& c, int dim, int two_phase, const State<T>& cur, const State<T>& prev,
+                            int have_prev, double* partials, int nblocks, double* result, hipStream_t s)
 {
-    hipLaunchKernelGGL((diag_partial_kernel<T>), dim3(nblocks), dim3(256), 0, s, c, dim, two_phase, cur, prev,
+    hipLaunchKernelGGL((diag_partial_kernel<T, AXI>), dim3(nblocks), dim3(256), 0, s, c, dim, two_phase, cur, prev,
                        have_prev, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, result);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_diag(const Coef<T>& c, int dim, int two_phase, const State<T>& cur, const State<T>& prev,
+                       int have_prev, double* partials, int nblocks, double* result, hipStream_t s)
+{
+    return launch_diag_impl<T, false>(c, dim, two_phase, cur, prev, have_prev, partials, nblocks, result, s);
+}
+
+template <typename T>
+hipError_t launch_diag_axisym(const Coef<T>& c, int two_phase, const State<T>& cur, const State<T>& prev,
+                              int have_prev, double* partials, int nblocks, double* result, hipStream_t s)
+{
+    return launch_diag_impl<T, true>(c, 2, two_phase, cur, prev, have_prev, partials, nblocks, result, s);
+}
+
+template hipError_t launch_diag_axisym<float>(const Coef<float>&, int, const State<float>&, const State<float>&, int,
+                                              double*, int, double*, hipStream_t);
+template hipError_t launch_diag_axisym<double>(const Coef<double>&, int, const State<double>&, const State<double>&,
+                                               int, double*, int, double*, hipStream_t);
 
 template hipError_t launch_diag<float>(const Coef<float>&, int, int, const State<float>&, const State<float>&, int,
                                        double*, int, double*, hipStream_t);

@@ -2,8 +2,8 @@
 face) against the FP64 oracle: FP64 to 1e-12 on ragged multi-tile grids with
 walls, a moving wall, body force and forcing row; FP32 over 500 steps;
 the discrete Poiseuille fixed point; every tile shape bit for bit; the
-two-phase form (drop on the axis, wetting wall) in FP64 and FP32; and the
-configurations the library rejects."""
+two-phase form (drop on the axis, wetting wall) in FP64 and FP32; the
+volume-weighted diagnostics; and the configurations the library rejects."""
 import numpy as np
 import pytest
 
@@ -253,3 +253,44 @@ def test_drop_axisym_full_size_one_step(mods):
         assert np.abs(g[k] - o[k]).max() < 2e-8, k
     assert np.abs(g["phi"] - o["phi"]).max() < 1e-6
     assert np.abs(g["drho"] - o["drho"]).max() < 1e-9
+
+
+DIAG_CMP = ("mass", "mom_x", "mom_y", "mom_z", "ke", "dumax", "umax", "enstrophy", "energy", "div_rms",
+            "div_max", "phi_sum")
+
+
+@pytest.mark.parametrize("two_phase", [False, True])
+def test_axisym_diagnostics_match_oracle(mods, two_phase):
+    """Volume integrals and volume averages (cell volume 2 pi r dx^2) and the
+    cylindrical divergence of an axisymmetric state after 3 FP64 steps
+    against the oracle's, to 1e-11 relative; a ragged multi-block grid."""
+    torch, acm, oracle = mods
+    nx, ny = 100, 37
+    if two_phase:
+        cfg, p = twophase_case(mods, nx, ny, (0, 0, SYM, WALL, 0, 0), "f64", wet=0.3)
+        st = inputs.drop_on_axis(nx, ny, 14.0, 4.0)
+        rng = np.random.Generator(np.random.PCG64(5))
+        st["u"] = 0.01 * rng.standard_normal((ny, nx))
+        st["v"] = 0.01 * rng.standard_normal((ny, nx))
+    else:
+        cfg, p, _ = case(mods, nx, ny, (0, 0, SYM, WALL, 0, 0), "f64", wall_speed=0.02, force=False)
+        st = inputs.pipe_state(nx, ny, seed=3)
+        rng = np.random.Generator(np.random.PCG64(6))
+        st["v"] = 0.01 * rng.standard_normal((ny, nx))
+    print(f"axisym diagnostics two_phase={two_phase}", flush=True)
+    s = acm.Solver(cfg, st)
+    s.run(3)
+    d = s.diagnostics()
+    cur = s.state()
+    w = s.current()[0]
+    prev = {k: t.cpu().double().numpy() for k, t in s.sets[1 - w].items()}
+    s.close()
+    od = oracle.diag(p, cur, prev)
+    # the mass of these states nearly cancels: its floor is rounding on the
+    # sum of |drho| over the volume
+    vol = 2 * np.pi * nx * ny * ny / 2
+    floor = {"mass": 1e-13 * vol * float(np.max(np.abs(cur["drho"])))}
+    for k in DIAG_CMP:
+        assert d[k] == pytest.approx(od[k], rel=1e-11, abs=floor.get(k, 1e-15)), k
+    assert d["nonfinite"] == 0 and d["step"] == 3
+    assert od["div_rms"] > 0 and od["enstrophy"] > 0
