@@ -92,7 +92,10 @@ typedef struct acm_config {
                                1 32x8, 2 64x8, 3 32x4, 4 64x4, 5 64x16,
                                7 32x16, 9 128x4, 12 128x8, 13 64x8 with two
                                rows per thread on fully periodic grids
-                               (else as 2); 0: 13 with 64-plane chunks,
+                               (else as 2); 14 (FP32) 64x8, 15 32x8: two
+                               steps per launch on fully periodic grids with
+                               rho0 = 1 (acm_run; each run ends with one
+                               one-step launch), else the default; 0: 13 with 64-plane chunks,
                                or a smaller shape and chunk when that gives
                                fewer than two workgroups per CU (FP64 accepts
                                3, 4, else 32x8); bits 8+ = z chunk / 16 (0:
@@ -170,7 +173,9 @@ acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields
 acm_status acm_step(acm_handle* h);
 
 /* nsteps steps, launched as captured HIP graphs of graph_chunk steps plus
- * single launches for the remainder.  Async. */
+ * single launches for the remainder (tile codes 14 and 15: two steps per
+ * launch, the last step of the run on its own, so the other set always
+ * holds the state one step back).  Async. */
 acm_status acm_run(acm_handle* h, int64_t nsteps);
 
 /* Diagnostics of the newest state (dumax compares with the other set, so it

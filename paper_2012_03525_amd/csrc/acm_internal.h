@@ -154,6 +154,15 @@ hipError_t launch_step2d(const Coef<T>& c, const State<T>& in, const State<T>& o
 template <typename T>
 hipError_t launch_step3d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
                          hipStream_t s);
+// Two 3D steps in one launch (in -> out holds level n+2) on fully periodic
+// boxes with rho0 = 1 and fields below 2 GiB, selected by tile codes 14 and
+// 15; step3d_pair_ok says whether the configuration and tile code allow it
+// (kern_step_pair.hip).
+template <typename T>
+bool step3d_pair_ok(const Coef<T>& c, int tile);
+template <typename T>
+hipError_t launch_step3d_pair(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
+                              hipStream_t s);
 template <typename T>
 hipError_t launch_twophase2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
                              hipStream_t s);

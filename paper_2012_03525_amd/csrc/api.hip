@@ -202,6 +202,10 @@ struct acm_handle {
     int64_t step = 0;
     int chunk = 64;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // tile codes 14 / 15 on 3D periodic boxes: acm_run advances two steps
+    // per launch
+    bool pair = false;
+    hipGraphExec_t exec_pair[2] = {nullptr, nullptr};
     double* partials = nullptr;
     double* result = nullptr;
     double* host = nullptr;
@@ -240,12 +244,25 @@ hipError_t launch_one(const acm_handle* h, int from, hipStream_t s)
     return launch_typed<float>(h, h->cf, from, s);
 }
 
-acm_status build_graph(acm_handle* h, int parity)
+// two steps from set `from` into the other set
+hipError_t launch_pair(const acm_handle* h, int from, hipStream_t s)
+{
+    if (h->cfg.precision == ACM_F64)
+        return launch_step3d_pair<double>(h->cd, state_of<double>(h->set[from]), state_of<double>(h->set[1 - from]),
+                                          h->cfg.tile, s);
+    return launch_step3d_pair<float>(h->cf, state_of<float>(h->set[from]), state_of<float>(h->set[1 - from]),
+                                     h->cfg.tile, s);
+}
+
+// a graph of chunk steps from set `parity`: chunk one-step launches, or
+// chunk / 2 two-step launches
+acm_status build_graph(acm_handle* h, int parity, bool pair)
 {
     hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    for (int i = 0; i < h->chunk; ++i) {
-        e = launch_one(h, (parity + i) & 1, h->cap);
+    const int nl = pair ? h->chunk / 2 : h->chunk;
+    for (int i = 0; i < nl; ++i) {
+        e = pair ? launch_pair(h, (parity + i) & 1, h->cap) : launch_one(h, (parity + i) & 1, h->cap);
         if (e != hipSuccess) {
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(h->cap, &g);
@@ -256,10 +273,11 @@ acm_status build_graph(acm_handle* h, int parity)
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(h->cap, &g);
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&h->exec[parity], g, nullptr, nullptr, 0);
+    hipGraphExec_t* slot = pair ? &h->exec_pair[parity] : &h->exec[parity];
+    e = hipGraphInstantiate(slot, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        h->exec[parity] = nullptr;
+        *slot = nullptr;
         return hip_fail(e, "hipGraphInstantiate");
     }
     return ACM_OK;
@@ -323,6 +341,9 @@ acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields
     h->chunk = cfg->graph_chunk > 0 ? cfg->graph_chunk : 64;
     h->cf = make_coef<float>(*cfg, force_x);
     h->cd = make_coef<double>(*cfg, force_x);
+    if (cfg->dim == 3 && !cfg->two_phase)
+        h->pair = cfg->precision == ACM_F64 ? step3d_pair_ok<double>(h->cd, cfg->tile)
+                                            : step3d_pair_ok<float>(h->cf, cfg->tile);
     hipError_t e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete h;
@@ -357,10 +378,33 @@ acm_status acm_run(acm_handle* h, int64_t nsteps)
 {
     if (!h) return fail(ACM_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(ACM_EINVAL, "nsteps must be >= 0");
+    if (h->pair && nsteps >= 3) {
+        // two steps per launch; the run ends with a one-step launch, so the
+        // other set holds the state one step back, as after one-step runs
+        while (nsteps > h->chunk) {
+            const int p = h->which;
+            if (!h->exec_pair[p]) {
+                acm_status st = build_graph(h, p, true);
+                if (st != ACM_OK) return st;
+            }
+            hipError_t e = hipGraphLaunch(h->exec_pair[p], h->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            h->which ^= (h->chunk / 2) & 1;
+            h->step += h->chunk;
+            nsteps -= h->chunk;
+        }
+        while (nsteps >= 3) {
+            hipError_t e = launch_pair(h, h->which, h->stream);
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+            h->which ^= 1;
+            h->step += 2;
+            nsteps -= 2;
+        }
+    }
     while (nsteps >= h->chunk) {
         const int p = h->which;
         if (!h->exec[p]) {
-            acm_status st = build_graph(h, p);
+            acm_status st = build_graph(h, p, false);
             if (st != ACM_OK) return st;
         }
         hipError_t e = hipGraphLaunch(h->exec[p], h->stream);
@@ -477,8 +521,10 @@ void acm_destroy(acm_handle* h)
 {
     if (!h) return;
     if (h->stream || h->cap) (void)hipStreamSynchronize(h->stream);
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 2; ++p) {
         if (h->exec[p]) (void)hipGraphExecDestroy(h->exec[p]);
+        if (h->exec_pair[p]) (void)hipGraphExecDestroy(h->exec_pair[p]);
+    }
     if (h->partials) (void)hipFree(h->partials);
     if (h->result) (void)hipFree(h->result);
     if (h->host) (void)hipHostFree(h->host);

@@ -19,6 +19,7 @@
 #include <type_traits>
 
 #include "acm_internal.h"
+#include "step3d.h"
 #include "tile2d.h"
 
 namespace acm {
@@ -82,84 +83,6 @@ struct Shape3 {
     static constexpr int YS = TY / RPT;             // row stride between a thread's rows
     static constexpr int NL = (RXY + NT - 1) / NT;  // plane points staged per thread
     static constexpr int ND = (DXY + NT - 1) / NT;  // drho' points per thread
-};
-
-template <bool GEN, typename T>
-__device__ __forceinline__ T mom3(T r, T u, T rho0)
-{
-    if constexpr (GEN) return fmaT(r, u, rho0 * u);
-    else return fmaT(r, u, u);
-}
-
-// drho' at R-index e of plane slot (cur), with the planes below / above.
-// The momentum differences use the split form of mdiff (tile2d.h).
-template <bool GEN, typename T, int RX>
-__device__ __forceinline__ T rho_new_3d(const Coef<T>& c, const T* r0, const T* u0, const T* v0,
-                                        const T* rD, const T* wD, const T* rU, const T* wU, int e)
-{
-    const T rc = r0[e];
-    const T rE = r0[e + 1], rW = r0[e - 1], rN = r0[e + RX], rS = r0[e - RX];
-    const T rUp = rU[e], rDn = rD[e];
-    const T rho0 = GEN ? c.rho0 : T(1);
-    const T div = (mdiff(rE, u0[e + 1], rW, u0[e - 1], rho0) + mdiff(rN, v0[e + RX], rS, v0[e - RX], rho0)) +
-                  mdiff(rUp, wU[e], rDn, wD[e], rho0);
-    const T lap = (((rE + rW) + (rN + rS)) + (rUp + rDn)) - T(6) * rc;
-    return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
-}
-
-// Buffer-resource access for the z-march: 32-bit lane byte offsets within a
-// plane, fixed for the whole march, plus a uniform plane offset.  A field
-// below 2 GiB gets one descriptor for the march and the plane's byte offset
-// in the scalar offset operand, so moving to the next plane costs one scalar
-// multiply; a larger field (WIDE) gets a descriptor per field and plane.
-// The hardware range-checks every access against the descriptor's size.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
-}
-__device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
-}
-// streaming (non-temporal) store: the new state is not re-read in this step
-__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, 2);
-}
-__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff)
-{
-    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, 2);
-}
-
-// the four field descriptors of one plane (WIDE) or of the whole field, and
-// the scalar byte offset of plane z
-template <bool WIDE, typename T>
-struct PlaneAccess {
-    __amdgpu_buffer_rsrc_t r, u, v, w;
-    unsigned soff;
-    __device__ __forceinline__ PlaneAccess(const State<T>& f, int z, unsigned plane, unsigned pbytes,
-                                           unsigned fbytes)
-    {
-        if constexpr (WIDE) {
-            const size_t base = (size_t)z * plane;
-            r = plane_rsrc(f.r + base, pbytes);
-            u = plane_rsrc(f.u + base, pbytes);
-            v = plane_rsrc(f.v + base, pbytes);
-            w = plane_rsrc(f.w + base, pbytes);
-            soff = 0u;
-        } else {
-            r = plane_rsrc(f.r, fbytes);
-            u = plane_rsrc(f.u, fbytes);
-            v = plane_rsrc(f.v, fbytes);
-            w = plane_rsrc(f.w, fbytes);
-            soff = (unsigned)z * pbytes;
-        }
-    }
 };
 
 // WPE > 0 asks the compiler for at least WPE waves per SIMD (a register

@@ -1,0 +1,358 @@
+// Two SMAME steps per launch on fully periodic 3D boxes (the one-step fast
+// path's conditions: rho0 = 1, no per-node force).  A 2.5D march along z
+// forms level n+1 on the tile plus a two-node ring, keeps it in LDS, and from
+// it level n+2 on the tile, so HBM sees one read of level n and one write of
+// level n+2 per node: half the traffic of two one-step launches, for about
+// 1.3x their arithmetic (level n+1 is formed on (TX+4)(TY+4) nodes per
+// TX*TY outputs).  Every value comes from rho_new_3d and momentum3d, the
+// expressions of the one-step kernel in the same order, so a launch here
+// equals two one-step launches bit for bit.
+//
+// In-plane regions around a TX x TY tile:
+//   A  level n on the tile + 4 ring      staged from HBM, 3-plane LDS ring
+//   B  drho' on the tile + 3 ring        2 planes
+//   C  level n+1 on the tile + 2 ring    3-plane LDS ring
+//   D  drho'' on the tile + 1 ring       2 planes
+// One iteration forms level n+1 on plane k1 (stage 1) and level n+2 on plane
+// k2 = k1 - 2 (stage 2) with four barriers; level-n plane k1 + 3 is in flight
+// in registers meanwhile.  The plane below the one being updated (level n at
+// the stage-1 nodes, level n+1 at the own node) and its drho' / drho'' stay
+// in registers, as in the one-step march.
+//
+// Selected by tile codes 14 and 15 only.  On a 256^3 grid it takes 350 us per
+// launch (175 us per step) against 137 us per one-step launch: the four
+// level-n+1 fields on the grown tile take LDS that holds the CU to eight
+// waves (two per SIMD), too few to hide the LDS latency of the larger
+// per-node work, so halving the HBM traffic does not pay.
+#include <hip/hip_runtime.h>
+
+#include "acm_internal.h"
+#include "step3d.h"
+
+namespace acm {
+
+namespace {
+
+template <int TX, int TY>
+struct ShapeP {
+    static constexpr int AX = TX + 8, AXY = AX * (TY + 8);
+    static constexpr int BX = TX + 6, BXY = BX * (TY + 6);
+    static constexpr int CX = TX + 4, CXY = CX * (TY + 4);
+    static constexpr int DX = TX + 2, DXY = DX * (TY + 2);
+    static constexpr int NT = TX * TY;  // one output column per thread
+    static constexpr int NA = (AXY + NT - 1) / NT, NB = (BXY + NT - 1) / NT;
+    static constexpr int NC = (CXY + NT - 1) / NT, ND = (DXY + NT - 1) / NT;
+};
+
+template <typename T>
+constexpr size_t pair_lds_bytes(int tx, int ty)
+{
+    return sizeof(T) * (12 * (size_t)(tx + 8) * (ty + 8) + 2 * (size_t)(tx + 6) * (ty + 6) +
+                        12 * (size_t)(tx + 4) * (ty + 4) + 2 * (size_t)(tx + 2) * (ty + 2));
+}
+
+__device__ __forceinline__ int pwrap(int g, int n)
+{
+    g %= n;
+    return g < 0 ? g + n : g;
+}
+
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T> in, State<T> out, int zc, int nbx,
+                                                             int nby)
+{
+    using S = ShapeP<TX, TY>;
+    constexpr int AX = S::AX, AXY = S::AXY, BX = S::BX, BXY = S::BXY, CX = S::CX, CXY = S::CXY;
+    constexpr int DX = S::DX, DXY = S::DXY, NT = S::NT;
+    constexpr int NA = S::NA, NB = S::NB, NC = S::NC, ND = S::ND;
+    static_assert(pair_lds_bytes<T>(TX, TY) <= 160 * 1024, "LDS");
+    __shared__ T ar[3][AXY], au[3][AXY], av[3][AXY], aw[3][AXY];
+    __shared__ T bd[2][BXY];
+    __shared__ T cr[3][CXY], cu[3][CXY], cv[3][CXY], cw[3][CXY];
+    __shared__ T dd[2][DXY];
+
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = lb % nbx;
+    const int t1 = lb / nbx;
+    const int by = t1 % nby, bz = t1 / nby;
+    const int x0 = bx * TX, y0 = by * TY;
+    const int z0 = bz * zc;
+    const int z1 = min(z0 + zc, c.nz);
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const unsigned pbytes = plane * (unsigned)sizeof(T);
+    const unsigned fbytes = pbytes * (unsigned)nz;  // below 2^31 (checked by the launcher)
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+
+    // staging map of region A (periodic images); padding lanes load a valid
+    // duplicate and skip the LDS store
+    unsigned voff[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int q = tid + i * NT;
+        const int qq = q < AXY ? q : tid;
+        const int ly = qq / AX, lx = qq - ly * AX;
+        const int sx = pwrap(x0 + lx - 4, nx), sy = pwrap(y0 + ly - 4, ny);
+        voff[i] = ((unsigned)sy * (unsigned)nx + (unsigned)sx) * (unsigned)sizeof(T);
+    }
+    // region-B points (drho') as A indices
+    int eB[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int q = min(tid + i * NT, BXY - 1);
+        const int ly = q / BX, lx = q - ly * BX;
+        eB[i] = (ly + 1) * AX + lx + 1;
+    }
+    // stage-1 nodes (region C) as A and B indices, with their row's x force
+    int eA1[NC], eB1[NC];
+    T fx1[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const int q = min(tid + i * NT, CXY - 1);
+        const int ly = q / CX, lx = q - ly * CX;
+        eA1[i] = (ly + 2) * AX + lx + 2;
+        eB1[i] = (ly + 1) * BX + lx + 1;
+        fx1[i] = c.fx ? c.fx[pwrap(y0 + ly - 2, ny)] : T(0);
+    }
+    // region-D points (drho'') as C indices
+    int eD[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+        const int q = min(tid + i * NT, DXY - 1);
+        const int ly = q / DX, lx = q - ly * DX;
+        eD[i] = (ly + 1) * CX + lx + 1;
+    }
+    // the own node: C and D indices, output byte offset (a lane outside the
+    // grid gets the descriptor size, so the range check drops its stores)
+    const int e2 = (ty + 2) * CX + tx + 2, d2 = (ty + 1) * DX + tx + 1;
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool act = gx < nx && gy < ny;
+    const unsigned ooff = act ? ((unsigned)gy * (unsigned)nx + (unsigned)gx) * (unsigned)sizeof(T) : fbytes;
+    const T fx2 = c.fx ? c.fx[min(gy, ny - 1)] : T(0);
+
+    T pr[NA], pu[NA], pv[NA], pw[NA];
+    auto fetch = [&](int gz) {
+        const PlaneAccess<false, T> pa(in, pwrap(gz, nz), plane, pbytes, fbytes);
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            pr[i] = bload((T*)nullptr, pa.r, voff[i], pa.soff);
+            pu[i] = bload((T*)nullptr, pa.u, voff[i], pa.soff);
+            pv[i] = bload((T*)nullptr, pa.v, voff[i], pa.soff);
+            pw[i] = bload((T*)nullptr, pa.w, voff[i], pa.soff);
+        }
+    };
+    auto store = [&](int s) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int q = tid + i * NT;
+            if ((i + 1) * NT <= AXY || q < AXY) {
+                ar[s][q] = pr[i];
+                au[s][q] = pu[i];
+                av[s][q] = pv[i];
+                aw[s][q] = pw[i];
+            }
+        }
+    };
+    // drho' of the level-n plane in slot s0 (below sD, above sU) on region B
+    auto ring_b = [&](int s0, int sD, int sU, int db) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int q = tid + i * NT;
+            if ((i + 1) * NT <= BXY || q < BXY)
+                bd[db][q] = rho_new_3d<false, T, AX>(c, ar[s0], au[s0], av[s0], ar[sD], aw[sD], ar[sU], aw[sU], eB[i]);
+        }
+    };
+    // drho'' of the level-(n+1) plane in slot s0 on region D
+    auto ring_d = [&](int s0, int sD, int sU, int dq) {
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+            const int q = tid + i * NT;
+            if ((i + 1) * NT <= DXY || q < DXY)
+                dd[dq][q] = rho_new_3d<false, T, CX>(c, cr[s0], cu[s0], cv[s0], cr[sD], cw[sD], cr[sU], cw[sU], eD[i]);
+        }
+    };
+
+    // stage-1 registers: level n one plane below, and its drho'
+    T d1r[NC], d1u[NC], d1v[NC], d1w[NC], n1D[NC];
+    // stage-2 registers: level n+1 one plane below the own node, and its drho''
+    T d2r = T(0), d2u = T(0), d2v = T(0), d2w = T(0), n2D = T(0);
+
+    // level-n plane p sits in A slot (p - z0 + 4) mod 3 and its drho' in B
+    // slot (p - z0 + 4) mod 2; level n+1 likewise in the C and D slots
+    fetch(z0 - 4);
+    store(0);
+    fetch(z0 - 3);
+    store(1);
+    fetch(z0 - 2);
+    store(2);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const int e = eA1[i];
+        n1D[i] = rho_new_3d<false, T, AX>(c, ar[1], au[1], av[1], ar[0], aw[0], ar[2], aw[2], e);
+        d1r[i] = ar[1][e];
+        d1u[i] = au[1][e];
+        d1v[i] = av[1][e];
+        d1w[i] = aw[1][e];
+    }
+    __syncthreads();  // plane z0-1 replaces plane z0-4
+    fetch(z0 - 1);
+    store(0);
+    __syncthreads();
+    ring_b(2, 1, 0, 0);  // drho'(z0-2)
+    fetch(z0);
+    __syncthreads();  // the first store replaces plane z0-3, read just above
+
+    int sa = 2;  // A / C slot of plane k1
+    int sb = 0;  // B / D slot of plane k1
+    for (int k1 = z0 - 2; k1 <= z1 + 1; ++k1) {
+        const int sa1 = sa == 2 ? 0 : sa + 1, sa2 = sa1 == 2 ? 0 : sa1 + 1;  // planes k1+1, k1+2
+        const int sam1 = sa2, sam2 = sa1;                                    // planes k1-1, k1-2
+        const int sb1 = sb ^ 1;
+        store(sa2);  // level n, plane k1+2
+        fetch(min(k1 + 3, z1 + 3));
+        __syncthreads();
+        ring_b(sa1, sa, sa2, sb1);  // drho'(k1+1)
+        __syncthreads();
+        // stage 1: level n+1 on region C of plane k1
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const int q = tid + i * NT;
+            if ((i + 1) * NT <= CXY || q < CXY) {
+                const int e = eA1[i], b = eB1[i];
+                const T* r0 = ar[sa];
+                const T* u0 = au[sa];
+                const T* v0 = av[sa];
+                const T* w0 = aw[sa];
+                const Pt3<T> C{r0[e], u0[e], v0[e], w0[e]};
+                const Pt3<T> E{r0[e + 1], u0[e + 1], v0[e + 1], w0[e + 1]};
+                const Pt3<T> W{r0[e - 1], u0[e - 1], v0[e - 1], w0[e - 1]};
+                const Pt3<T> N{r0[e + AX], u0[e + AX], v0[e + AX], w0[e + AX]};
+                const Pt3<T> Sn{r0[e - AX], u0[e - AX], v0[e - AX], w0[e - AX]};
+                const Pt3<T> U{ar[sa1][e], au[sa1][e], av[sa1][e], aw[sa1][e]};
+                const Pt3<T> D{d1r[i], d1u[i], d1v[i], d1w[i]};
+                const T* dc = bd[sb];
+                const T rnC = dc[b];
+                T ro, uo, vo, wo;
+                momentum3d<false, T>(c, C, E, W, N, Sn, U, D, rnC, dc[b + 1], dc[b - 1], dc[b + BX], dc[b - BX],
+                                     bd[sb1][b], n1D[i], fx1[i], false, T(0), T(0), T(0), ro, uo, vo, wo);
+                cr[sa][q] = ro;
+                cu[sa][q] = uo;
+                cv[sa][q] = vo;
+                cw[sa][q] = wo;
+                d1r[i] = C.r;
+                d1u[i] = C.u;
+                d1v[i] = C.v;
+                d1w[i] = C.w;
+                n1D[i] = rnC;
+            }
+        }
+        __syncthreads();
+        if (k1 >= z0) ring_d(sam1, sam2, sa, sb1);  // drho''(k1-1) from level n+1 planes k1-2 .. k1
+        __syncthreads();
+        if (k1 == z0 + 1) {  // level n+1 of plane z0-1 at the own node
+            d2r = cr[sam2][e2];
+            d2u = cu[sam2][e2];
+            d2v = cv[sam2][e2];
+            d2w = cw[sam2][e2];
+            n2D = dd[sb][d2];
+        } else if (k1 >= z0 + 2) {
+            // stage 2: level n+2 at the own node of plane k2 = k1 - 2
+            const int k2 = k1 - 2;
+            const T* r0 = cr[sam2];
+            const T* u0 = cu[sam2];
+            const T* v0 = cv[sam2];
+            const T* w0 = cw[sam2];
+            const int e = e2;
+            const Pt3<T> C{r0[e], u0[e], v0[e], w0[e]};
+            const Pt3<T> E{r0[e + 1], u0[e + 1], v0[e + 1], w0[e + 1]};
+            const Pt3<T> W{r0[e - 1], u0[e - 1], v0[e - 1], w0[e - 1]};
+            const Pt3<T> N{r0[e + CX], u0[e + CX], v0[e + CX], w0[e + CX]};
+            const Pt3<T> Sn{r0[e - CX], u0[e - CX], v0[e - CX], w0[e - CX]};
+            const Pt3<T> U{cr[sam1][e], cu[sam1][e], cv[sam1][e], cw[sam1][e]};
+            const Pt3<T> D{d2r, d2u, d2v, d2w};
+            const T* dc = dd[sb];  // drho''(k2): k2 = k1 - 2 has the parity of k1
+            const T rnC = dc[d2];
+            T ro, uo, vo, wo;
+            momentum3d<false, T>(c, C, E, W, N, Sn, U, D, rnC, dc[d2 + 1], dc[d2 - 1], dc[d2 + DX], dc[d2 - DX],
+                                 dd[sb1][d2], n2D, fx2, false, T(0), T(0), T(0), ro, uo, vo, wo);
+            const PlaneAccess<false, T> po(out, k2, plane, pbytes, fbytes);
+            bstore(ro, po.r, ooff, po.soff);
+            bstore(uo, po.u, ooff, po.soff);
+            bstore(vo, po.v, ooff, po.soff);
+            bstore(wo, po.w, ooff, po.soff);
+            d2r = C.r;
+            d2u = C.u;
+            d2v = C.v;
+            d2w = C.w;
+            n2D = rnC;
+        }
+        sa = sa1;
+        sb = sb1;
+    }
+}
+
+template <typename T, int TX, int TY>
+hipError_t launch_pair(const Coef<T>& c, const State<T>& in, const State<T>& out, int zc, hipStream_t s)
+{
+    const int nbx = (c.nx + TX - 1) / TX, nby = (c.ny + TY - 1) / TY, nbz = (c.nz + zc - 1) / zc;
+    hipLaunchKernelGGL((step3d_pair_kernel<T, TX, TY>), dim3(nbx * nby * nbz), dim3(TX * TY), 0, s, c, in, out, zc,
+                       nbx, nby);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+bool step3d_pair_ok(const Coef<T>& c, int tile)
+{
+    const int shape = tile & 0xff;
+    if (shape != 14 && shape != 15) return false;
+    if (sizeof(T) == 8 && shape == 14) return false;
+    return c.nz >= 2 && !c.nonperiodic && c.rho0 == T(1) && !c.fst[0] &&
+           (size_t)c.nx * c.ny * c.nz * sizeof(T) < (size_t(1) << 31);
+}
+
+// tile codes: 14 = 64 x 8 (FP32), 15 = 32 x 8; bits 8+ = z chunk / 16.  The
+// default chunk is the longest (128, 64, 32 or 16 planes) that still gives
+// every CU a workgroup.
+template <typename T>
+hipError_t launch_step3d_pair(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile, hipStream_t s)
+{
+    const int shape = tile & 0xff;
+    const int tx = shape == 14 ? 64 : 32, ty = 8;
+    int zc = (tile >> 8) * 16;
+    if (zc <= 0) {
+        static int ncu = 0;
+        if (ncu == 0) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+                ncu = 256;
+        }
+        const long cols = (long)((c.nx + tx - 1) / tx) * ((c.ny + ty - 1) / ty);
+        zc = 16;
+        for (int z : {128, 64, 32}) {
+            if (cols * ((c.nz + z - 1) / z) >= ncu) {
+                zc = z;
+                break;
+            }
+        }
+    }
+    if (zc > c.nz) zc = c.nz;
+    if constexpr (sizeof(T) == 8) return launch_pair<T, 32, 8>(c, in, out, zc, s);
+    else {
+        if (shape == 14) return launch_pair<T, 64, 8>(c, in, out, zc, s);
+        return launch_pair<T, 32, 8>(c, in, out, zc, s);
+    }
+}
+
+template bool step3d_pair_ok<float>(const Coef<float>&, int);
+template bool step3d_pair_ok<double>(const Coef<double>&, int);
+template hipError_t launch_step3d_pair<float>(const Coef<float>&, const State<float>&, const State<float>&, int,
+                                              hipStream_t);
+template hipError_t launch_step3d_pair<double>(const Coef<double>&, const State<double>&, const State<double>&, int,
+                                               hipStream_t);
+
+}  // namespace acm
