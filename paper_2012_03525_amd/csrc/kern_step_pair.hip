@@ -14,17 +14,19 @@
 //   C  level n+1 on the tile + 2 ring    3-plane LDS ring
 //   D  drho'' on the tile + 1 ring       2 planes
 // One iteration forms level n+1 on plane k1 (stage 1) and level n+2 on plane
-// k2 = k1 - 2 (stage 2) with four barriers; level-n plane k1 + 3 is in flight
-// in registers meanwhile.  The plane below the one being updated (level n at
+// k2 = k1 - 2 (stage 2) with four barriers; level-n planes k1 + 3 and k1 + 4
+// are in flight in registers meanwhile.  The plane below the one being updated (level n at
 // the stage-1 nodes, level n+1 at the own node) and its drho' / drho'' stay
 // in registers, as in the one-step march.
 //
-// Selected by tile codes 14 and 15 only.  On a 256^3 grid it takes 350 us per
-// launch (175 us per step) against 137 us per one-step launch: the four
+// Selected by tile codes 14 and 15 only.  On a 256^3 grid it takes 345 us per
+// launch (172 us per step) against 137 us per one-step launch: the four
 // level-n+1 fields on the grown tile take LDS that holds the CU to eight
 // waves (two per SIMD), too few to hide the LDS latency of the larger
 // per-node work, so halving the HBM traffic does not pay.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "acm_internal.h"
 #include "step3d.h"
@@ -131,29 +133,35 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
     const unsigned ooff = act ? ((unsigned)gy * (unsigned)nx + (unsigned)gx) * (unsigned)sizeof(T) : fbytes;
     const T fx2 = c.fx ? c.fx[min(gy, ny - 1)] : T(0);
 
-    T pr[NA], pu[NA], pv[NA], pw[NA];
-    auto fetch = [&](int gz) {
+    // two register sets: level-n plane k1 + 4 is fetched while plane k1 + 2
+    // is stored, so a load has two iterations to arrive
+    T pr[2][NA], pu[2][NA], pv[2][NA], pw[2][NA];
+    auto fetch = [&](int gz, auto bset) {
+        constexpr int b = decltype(bset)::value;
         const PlaneAccess<false, T> pa(in, pwrap(gz, nz), plane, pbytes, fbytes);
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-            pr[i] = bload((T*)nullptr, pa.r, voff[i], pa.soff);
-            pu[i] = bload((T*)nullptr, pa.u, voff[i], pa.soff);
-            pv[i] = bload((T*)nullptr, pa.v, voff[i], pa.soff);
-            pw[i] = bload((T*)nullptr, pa.w, voff[i], pa.soff);
+            pr[b][i] = bload((T*)nullptr, pa.r, voff[i], pa.soff);
+            pu[b][i] = bload((T*)nullptr, pa.u, voff[i], pa.soff);
+            pv[b][i] = bload((T*)nullptr, pa.v, voff[i], pa.soff);
+            pw[b][i] = bload((T*)nullptr, pa.w, voff[i], pa.soff);
         }
     };
-    auto store = [&](int s) {
+    auto store = [&](int s, auto bset) {
+        constexpr int b = decltype(bset)::value;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int q = tid + i * NT;
             if ((i + 1) * NT <= AXY || q < AXY) {
-                ar[s][q] = pr[i];
-                au[s][q] = pu[i];
-                av[s][q] = pv[i];
-                aw[s][q] = pw[i];
+                ar[s][q] = pr[b][i];
+                au[s][q] = pu[b][i];
+                av[s][q] = pv[b][i];
+                aw[s][q] = pw[b][i];
             }
         }
     };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
     // drho' of the level-n plane in slot s0 (below sD, above sU) on region B
     auto ring_b = [&](int s0, int sD, int sU, int db) {
 #pragma unroll
@@ -180,12 +188,12 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
 
     // level-n plane p sits in A slot (p - z0 + 4) mod 3 and its drho' in B
     // slot (p - z0 + 4) mod 2; level n+1 likewise in the C and D slots
-    fetch(z0 - 4);
-    store(0);
-    fetch(z0 - 3);
-    store(1);
-    fetch(z0 - 2);
-    store(2);
+    fetch(z0 - 4, I0{});
+    store(0, I0{});
+    fetch(z0 - 3, I0{});
+    store(1, I0{});
+    fetch(z0 - 2, I0{});
+    store(2, I0{});
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
@@ -197,21 +205,23 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
         d1w[i] = aw[1][e];
     }
     __syncthreads();  // plane z0-1 replaces plane z0-4
-    fetch(z0 - 1);
-    store(0);
+    fetch(z0 - 1, I0{});
+    store(0, I0{});
     __syncthreads();
     ring_b(2, 1, 0, 0);  // drho'(z0-2)
-    fetch(z0);
+    fetch(z0, I0{});
+    fetch(z0 + 1, I1{});
     __syncthreads();  // the first store replaces plane z0-3, read just above
 
     int sa = 2;  // A / C slot of plane k1
     int sb = 0;  // B / D slot of plane k1
-    for (int k1 = z0 - 2; k1 <= z1 + 1; ++k1) {
+    // iteration k1 stores register set (k1 - z0) mod 2
+    auto iter = [&](int k1, auto bset) {
         const int sa1 = sa == 2 ? 0 : sa + 1, sa2 = sa1 == 2 ? 0 : sa1 + 1;  // planes k1+1, k1+2
         const int sam1 = sa2, sam2 = sa1;                                    // planes k1-1, k1-2
         const int sb1 = sb ^ 1;
-        store(sa2);  // level n, plane k1+2
-        fetch(min(k1 + 3, z1 + 3));
+        store(sa2, bset);  // level n, plane k1+2
+        fetch(min(k1 + 4, z1 + 3), bset);
         __syncthreads();
         ring_b(sa1, sa, sa2, sb1);  // drho'(k1+1)
         __syncthreads();
@@ -290,7 +300,13 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
         }
         sa = sa1;
         sb = sb1;
+    };
+    int k1 = z0 - 2;
+    for (; k1 + 1 <= z1 + 1; k1 += 2) {
+        iter(k1, I0{});
+        iter(k1 + 1, I1{});
     }
+    if (k1 <= z1 + 1) iter(k1, I0{});
 }
 
 template <typename T, int TX, int TY>
