@@ -10,17 +10,17 @@
 //
 // In-plane regions around a TX x TY tile:
 //   A  level n on the tile + 4 ring      staged from HBM, 3-plane LDS ring
-//   B  drho' on the tile + 3 ring        2 planes
+//   B  drho' on the tile + 3 ring        3 planes
 //   C  level n+1 on the tile + 2 ring    3-plane LDS ring
-//   D  drho'' on the tile + 1 ring       2 planes
+//   D  drho'' on the tile + 1 ring       3 planes
 // One iteration forms level n+1 on plane k1 (stage 1) and level n+2 on plane
-// k2 = k1 - 2 (stage 2) with four barriers; level-n planes k1 + 3 and k1 + 4
+// k2 = k1 - 2 (stage 2) with four barriers; level-n planes k1 + 3 .. k1 + 5
 // are in flight in registers meanwhile.  The plane below the one being updated (level n at
 // the stage-1 nodes, level n+1 at the own node) and its drho' / drho'' stay
 // in registers, as in the one-step march.
 //
-// Selected by tile codes 14 and 15 only.  On a 256^3 grid it takes 345 us per
-// launch (172 us per step) against 137 us per one-step launch: the four
+// Selected by tile codes 14 and 15 only.  On a 256^3 grid it takes 324 us per
+// launch (162 us per step) against 137 us per one-step launch: the four
 // level-n+1 fields on the grown tile take LDS that holds the CU to eight
 // waves (two per SIMD), too few to hide the LDS latency of the larger
 // per-node work, so halving the HBM traffic does not pay.
@@ -49,8 +49,8 @@ struct ShapeP {
 template <typename T>
 constexpr size_t pair_lds_bytes(int tx, int ty)
 {
-    return sizeof(T) * (12 * (size_t)(tx + 8) * (ty + 8) + 2 * (size_t)(tx + 6) * (ty + 6) +
-                        12 * (size_t)(tx + 4) * (ty + 4) + 2 * (size_t)(tx + 2) * (ty + 2));
+    return sizeof(T) * (12 * (size_t)(tx + 8) * (ty + 8) + 3 * (size_t)(tx + 6) * (ty + 6) +
+                        12 * (size_t)(tx + 4) * (ty + 4) + 3 * (size_t)(tx + 2) * (ty + 2));
 }
 
 __device__ __forceinline__ int pwrap(int g, int n)
@@ -69,9 +69,9 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
     constexpr int NA = S::NA, NB = S::NB, NC = S::NC, ND = S::ND;
     static_assert(pair_lds_bytes<T>(TX, TY) <= 160 * 1024, "LDS");
     __shared__ T ar[3][AXY], au[3][AXY], av[3][AXY], aw[3][AXY];
-    __shared__ T bd[2][BXY];
+    __shared__ T bd[3][BXY];
     __shared__ T cr[3][CXY], cu[3][CXY], cv[3][CXY], cw[3][CXY];
-    __shared__ T dd[2][DXY];
+    __shared__ T dd[3][DXY];
 
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = lb % nbx;
@@ -133,9 +133,9 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
     const unsigned ooff = act ? ((unsigned)gy * (unsigned)nx + (unsigned)gx) * (unsigned)sizeof(T) : fbytes;
     const T fx2 = c.fx ? c.fx[min(gy, ny - 1)] : T(0);
 
-    // two register sets: level-n plane k1 + 4 is fetched while plane k1 + 2
-    // is stored, so a load has two iterations to arrive
-    T pr[2][NA], pu[2][NA], pv[2][NA], pw[2][NA];
+    // three register sets: level-n plane k1 + 5 is fetched while plane k1 + 2
+    // is stored, so a load has three iterations to arrive
+    T pr[3][NA], pu[3][NA], pv[3][NA], pw[3][NA];
     auto fetch = [&](int gz, auto bset) {
         constexpr int b = decltype(bset)::value;
         const PlaneAccess<false, T> pa(in, pwrap(gz, nz), plane, pbytes, fbytes);
@@ -162,6 +162,7 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
     // drho' of the level-n plane in slot s0 (below sD, above sU) on region B
     auto ring_b = [&](int s0, int sD, int sU, int db) {
 #pragma unroll
@@ -186,42 +187,44 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
     // stage-2 registers: level n+1 one plane below the own node, and its drho''
     T d2r = T(0), d2u = T(0), d2v = T(0), d2w = T(0), n2D = T(0);
 
-    // level-n plane p sits in A slot (p - z0 + 4) mod 3 and its drho' in B
-    // slot (p - z0 + 4) mod 2; level n+1 likewise in the C and D slots
+    // level-n plane p, its drho', and level n+1 and drho'' of plane p sit in
+    // slot (p - z0 + 2) mod 3 of their rings; the loop is unrolled three
+    // times so that every slot and register set is fixed at compile time
     fetch(z0 - 4, I0{});
-    store(0, I0{});
-    fetch(z0 - 3, I0{});
     store(1, I0{});
-    fetch(z0 - 2, I0{});
+    fetch(z0 - 3, I0{});
     store(2, I0{});
+    fetch(z0 - 2, I0{});
+    store(0, I0{});
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
         const int e = eA1[i];
-        n1D[i] = rho_new_3d<false, T, AX>(c, ar[1], au[1], av[1], ar[0], aw[0], ar[2], aw[2], e);
-        d1r[i] = ar[1][e];
-        d1u[i] = au[1][e];
-        d1v[i] = av[1][e];
-        d1w[i] = aw[1][e];
+        n1D[i] = rho_new_3d<false, T, AX>(c, ar[2], au[2], av[2], ar[1], aw[1], ar[0], aw[0], e);
+        d1r[i] = ar[2][e];
+        d1u[i] = au[2][e];
+        d1v[i] = av[2][e];
+        d1w[i] = aw[2][e];
     }
     __syncthreads();  // plane z0-1 replaces plane z0-4
     fetch(z0 - 1, I0{});
-    store(0, I0{});
+    store(1, I0{});
     __syncthreads();
-    ring_b(2, 1, 0, 0);  // drho'(z0-2)
+    ring_b(0, 2, 1, 0);  // drho'(z0-2)
     fetch(z0, I0{});
     fetch(z0 + 1, I1{});
+    fetch(z0 + 2, I2{});
     __syncthreads();  // the first store replaces plane z0-3, read just above
 
-    int sa = 2;  // A / C slot of plane k1
-    int sb = 0;  // B / D slot of plane k1
-    // iteration k1 stores register set (k1 - z0) mod 2
-    auto iter = [&](int k1, auto bset) {
-        const int sa1 = sa == 2 ? 0 : sa + 1, sa2 = sa1 == 2 ? 0 : sa1 + 1;  // planes k1+1, k1+2
-        const int sam1 = sa2, sam2 = sa1;                                    // planes k1-1, k1-2
-        const int sb1 = sb ^ 1;
-        store(sa2, bset);  // level n, plane k1+2
-        fetch(min(k1 + 4, z1 + 3), bset);
+    // iteration k1 = z0 - 2 + j has J = j mod 3: plane k1 in slot J, and it
+    // stores register set J
+    auto iter = [&](int k1, auto jc) {
+        constexpr int J = decltype(jc)::value;
+        constexpr int sa = J, sa1 = (J + 1) % 3, sa2 = (J + 2) % 3;  // planes k1, k1+1, k1+2
+        constexpr int sam1 = sa2, sam2 = sa1;                        // planes k1-1, k1-2
+        constexpr int sb = sa, sb1 = sa1;
+        store(sa2, jc);  // level n, plane k1+2
+        fetch(min(k1 + 5, z1 + 3), jc);
         __syncthreads();
         ring_b(sa1, sa, sa2, sb1);  // drho'(k1+1)
         __syncthreads();
@@ -259,14 +262,14 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
             }
         }
         __syncthreads();
-        if (k1 >= z0) ring_d(sam1, sam2, sa, sb1);  // drho''(k1-1) from level n+1 planes k1-2 .. k1
+        if (k1 >= z0) ring_d(sam1, sam2, sa, sam1);  // drho''(k1-1) from level n+1 planes k1-2 .. k1
         __syncthreads();
         if (k1 == z0 + 1) {  // level n+1 of plane z0-1 at the own node
             d2r = cr[sam2][e2];
             d2u = cu[sam2][e2];
             d2v = cv[sam2][e2];
             d2w = cw[sam2][e2];
-            n2D = dd[sb][d2];
+            n2D = dd[sam2][d2];
         } else if (k1 >= z0 + 2) {
             // stage 2: level n+2 at the own node of plane k2 = k1 - 2
             const int k2 = k1 - 2;
@@ -282,11 +285,11 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
             const Pt3<T> Sn{r0[e - CX], u0[e - CX], v0[e - CX], w0[e - CX]};
             const Pt3<T> U{cr[sam1][e], cu[sam1][e], cv[sam1][e], cw[sam1][e]};
             const Pt3<T> D{d2r, d2u, d2v, d2w};
-            const T* dc = dd[sb];  // drho''(k2): k2 = k1 - 2 has the parity of k1
+            const T* dc = dd[sam2];  // drho''(k2)
             const T rnC = dc[d2];
             T ro, uo, vo, wo;
             momentum3d<false, T>(c, C, E, W, N, Sn, U, D, rnC, dc[d2 + 1], dc[d2 - 1], dc[d2 + DX], dc[d2 - DX],
-                                 dd[sb1][d2], n2D, fx2, false, T(0), T(0), T(0), ro, uo, vo, wo);
+                                 dd[sam1][d2], n2D, fx2, false, T(0), T(0), T(0), ro, uo, vo, wo);
             const PlaneAccess<false, T> po(out, k2, plane, pbytes, fbytes);
             bstore(ro, po.r, ooff, po.soff);
             bstore(uo, po.u, ooff, po.soff);
@@ -298,15 +301,15 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
             d2w = C.w;
             n2D = rnC;
         }
-        sa = sa1;
-        sb = sb1;
     };
     int k1 = z0 - 2;
-    for (; k1 + 1 <= z1 + 1; k1 += 2) {
+    for (; k1 + 2 <= z1 + 1; k1 += 3) {
         iter(k1, I0{});
         iter(k1 + 1, I1{});
+        iter(k1 + 2, I2{});
     }
     if (k1 <= z1 + 1) iter(k1, I0{});
+    if (k1 + 1 <= z1 + 1) iter(k1 + 1, I1{});
 }
 
 template <typename T, int TX, int TY>
