@@ -19,8 +19,8 @@
 // the stage-1 nodes, level n+1 at the own node) and its drho' / drho'' stay
 // in registers, as in the one-step march.
 //
-// Selected by tile codes 14 and 15 only.  On a 256^3 grid it takes 324 us per
-// launch (162 us per step) against 137 us per one-step launch: the four
+// Selected by tile codes 14 and 15 only.  On a 256^3 grid it takes 318 us per
+// launch (159 us per step) against 137 us per one-step launch: the four
 // level-n+1 fields on the grown tile take LDS that holds the CU to eight
 // waves (two per SIMD), too few to hide the LDS latency of the larger
 // per-node work, so halving the HBM traffic does not pay.
@@ -35,13 +35,17 @@ namespace acm {
 
 namespace {
 
+// All four regions share the row stride AX of region A, so that a wave's
+// lanes walk consecutive LDS words (no bank conflicts where a narrower region
+// would wrap to its next row) and the index of a point in one region is its
+// index in another plus a constant; the columns past a region's width are
+// left idle.
 template <int TX, int TY>
 struct ShapeP {
-    static constexpr int AX = TX + 8, AXY = AX * (TY + 8);
-    static constexpr int BX = TX + 6, BXY = BX * (TY + 6);
-    static constexpr int CX = TX + 4, CXY = CX * (TY + 4);
-    static constexpr int DX = TX + 2, DXY = DX * (TY + 2);
-    static constexpr int NT = TX * TY;  // one output column per thread
+    static constexpr int AX = TX + 8;
+    static constexpr int AXY = AX * (TY + 8), BXY = AX * (TY + 6), CXY = AX * (TY + 4), DXY = AX * (TY + 2);
+    static constexpr int BW = TX + 6, CW = TX + 4, DW = TX + 2;  // valid columns of B, C, D
+    static constexpr int NT = TX * TY;                           // one output column per thread
     static constexpr int NA = (AXY + NT - 1) / NT, NB = (BXY + NT - 1) / NT;
     static constexpr int NC = (CXY + NT - 1) / NT, ND = (DXY + NT - 1) / NT;
 };
@@ -49,8 +53,7 @@ struct ShapeP {
 template <typename T>
 constexpr size_t pair_lds_bytes(int tx, int ty)
 {
-    return sizeof(T) * (12 * (size_t)(tx + 8) * (ty + 8) + 3 * (size_t)(tx + 6) * (ty + 6) +
-                        12 * (size_t)(tx + 4) * (ty + 4) + 3 * (size_t)(tx + 2) * (ty + 2));
+    return sizeof(T) * (size_t)(tx + 8) * (12 * (ty + 8) + 3 * (ty + 6) + 12 * (ty + 4) + 3 * (ty + 2));
 }
 
 __device__ __forceinline__ int pwrap(int g, int n)
@@ -64,8 +67,7 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
                                                              int nby)
 {
     using S = ShapeP<TX, TY>;
-    constexpr int AX = S::AX, AXY = S::AXY, BX = S::BX, BXY = S::BXY, CX = S::CX, CXY = S::CXY;
-    constexpr int DX = S::DX, DXY = S::DXY, NT = S::NT;
+    constexpr int AX = S::AX, AXY = S::AXY, BXY = S::BXY, CXY = S::CXY, DXY = S::DXY, NT = S::NT;
     constexpr int NA = S::NA, NB = S::NB, NC = S::NC, ND = S::ND;
     static_assert(pair_lds_bytes<T>(TX, TY) <= 160 * 1024, "LDS");
     __shared__ T ar[3][AXY], au[3][AXY], av[3][AXY], aw[3][AXY];
@@ -98,36 +100,30 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
         const int sx = pwrap(x0 + lx - 4, nx), sy = pwrap(y0 + ly - 4, ny);
         voff[i] = ((unsigned)sy * (unsigned)nx + (unsigned)sx) * (unsigned)sizeof(T);
     }
-    // region-B points (drho') as A indices
-    int eB[NB];
+    // slots of regions B, C and D held by this thread, and whether each is a
+    // point of its region; the point at B (C, D) index q sits at A index
+    // q + AX + 1 (q + 2 AX + 2, and B index q + AX + 1; C index q + AX + 1)
+    bool vB[NB], vC[NC], vD[ND];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        const int q = min(tid + i * NT, BXY - 1);
-        const int ly = q / BX, lx = q - ly * BX;
-        eB[i] = (ly + 1) * AX + lx + 1;
+        const int q = tid + i * NT;
+        vB[i] = q < BXY && q % AX < S::BW;
     }
-    // stage-1 nodes (region C) as A and B indices, with their row's x force
-    int eA1[NC], eB1[NC];
-    T fx1[NC];
+    T fx1[NC];  // the row's x force at the stage-1 nodes
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-        const int q = min(tid + i * NT, CXY - 1);
-        const int ly = q / CX, lx = q - ly * CX;
-        eA1[i] = (ly + 2) * AX + lx + 2;
-        eB1[i] = (ly + 1) * BX + lx + 1;
-        fx1[i] = c.fx ? c.fx[pwrap(y0 + ly - 2, ny)] : T(0);
+        const int q = tid + i * NT;
+        vC[i] = q < CXY && q % AX < S::CW;
+        fx1[i] = c.fx ? c.fx[pwrap(y0 + min(q, CXY - 1) / AX - 2, ny)] : T(0);
     }
-    // region-D points (drho'') as C indices
-    int eD[ND];
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
-        const int q = min(tid + i * NT, DXY - 1);
-        const int ly = q / DX, lx = q - ly * DX;
-        eD[i] = (ly + 1) * CX + lx + 1;
+        const int q = tid + i * NT;
+        vD[i] = q < DXY && q % AX < S::DW;
     }
     // the own node: C and D indices, output byte offset (a lane outside the
     // grid gets the descriptor size, so the range check drops its stores)
-    const int e2 = (ty + 2) * CX + tx + 2, d2 = (ty + 1) * DX + tx + 1;
+    const int e2 = (ty + 2) * AX + tx + 2, d2 = (ty + 1) * AX + tx + 1;
     const int gx = x0 + tx, gy = y0 + ty;
     const bool act = gx < nx && gy < ny;
     const unsigned ooff = act ? ((unsigned)gy * (unsigned)nx + (unsigned)gx) * (unsigned)sizeof(T) : fbytes;
@@ -168,8 +164,9 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int q = tid + i * NT;
-            if ((i + 1) * NT <= BXY || q < BXY)
-                bd[db][q] = rho_new_3d<false, T, AX>(c, ar[s0], au[s0], av[s0], ar[sD], aw[sD], ar[sU], aw[sU], eB[i]);
+            if (vB[i])
+                bd[db][q] = rho_new_3d<false, T, AX>(c, ar[s0], au[s0], av[s0], ar[sD], aw[sD], ar[sU], aw[sU],
+                                                     q + AX + 1);
         }
     };
     // drho'' of the level-(n+1) plane in slot s0 on region D
@@ -177,8 +174,9 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
 #pragma unroll
         for (int i = 0; i < ND; ++i) {
             const int q = tid + i * NT;
-            if ((i + 1) * NT <= DXY || q < DXY)
-                dd[dq][q] = rho_new_3d<false, T, CX>(c, cr[s0], cu[s0], cv[s0], cr[sD], cw[sD], cr[sU], cw[sU], eD[i]);
+            if (vD[i])
+                dd[dq][q] = rho_new_3d<false, T, AX>(c, cr[s0], cu[s0], cv[s0], cr[sD], cw[sD], cr[sU], cw[sU],
+                                                     q + AX + 1);
         }
     };
 
@@ -199,7 +197,7 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-        const int e = eA1[i];
+        const int e = (vC[i] ? tid + i * NT : 0) + 2 * AX + 2;
         n1D[i] = rho_new_3d<false, T, AX>(c, ar[2], au[2], av[2], ar[1], aw[1], ar[0], aw[0], e);
         d1r[i] = ar[2][e];
         d1u[i] = au[2][e];
@@ -232,8 +230,8 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             const int q = tid + i * NT;
-            if ((i + 1) * NT <= CXY || q < CXY) {
-                const int e = eA1[i], b = eB1[i];
+            if (vC[i]) {
+                const int e = q + 2 * AX + 2, b = q + AX + 1;
                 const T* r0 = ar[sa];
                 const T* u0 = au[sa];
                 const T* v0 = av[sa];
@@ -248,7 +246,7 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
                 const T* dc = bd[sb];
                 const T rnC = dc[b];
                 T ro, uo, vo, wo;
-                momentum3d<false, T>(c, C, E, W, N, Sn, U, D, rnC, dc[b + 1], dc[b - 1], dc[b + BX], dc[b - BX],
+                momentum3d<false, T>(c, C, E, W, N, Sn, U, D, rnC, dc[b + 1], dc[b - 1], dc[b + AX], dc[b - AX],
                                      bd[sb1][b], n1D[i], fx1[i], false, T(0), T(0), T(0), ro, uo, vo, wo);
                 cr[sa][q] = ro;
                 cu[sa][q] = uo;
@@ -281,14 +279,14 @@ __global__ __launch_bounds__(TX* TY) void step3d_pair_kernel(Coef<T> c, State<T>
             const Pt3<T> C{r0[e], u0[e], v0[e], w0[e]};
             const Pt3<T> E{r0[e + 1], u0[e + 1], v0[e + 1], w0[e + 1]};
             const Pt3<T> W{r0[e - 1], u0[e - 1], v0[e - 1], w0[e - 1]};
-            const Pt3<T> N{r0[e + CX], u0[e + CX], v0[e + CX], w0[e + CX]};
-            const Pt3<T> Sn{r0[e - CX], u0[e - CX], v0[e - CX], w0[e - CX]};
+            const Pt3<T> N{r0[e + AX], u0[e + AX], v0[e + AX], w0[e + AX]};
+            const Pt3<T> Sn{r0[e - AX], u0[e - AX], v0[e - AX], w0[e - AX]};
             const Pt3<T> U{cr[sam1][e], cu[sam1][e], cv[sam1][e], cw[sam1][e]};
             const Pt3<T> D{d2r, d2u, d2v, d2w};
             const T* dc = dd[sam2];  // drho''(k2)
             const T rnC = dc[d2];
             T ro, uo, vo, wo;
-            momentum3d<false, T>(c, C, E, W, N, Sn, U, D, rnC, dc[d2 + 1], dc[d2 - 1], dc[d2 + DX], dc[d2 - DX],
+            momentum3d<false, T>(c, C, E, W, N, Sn, U, D, rnC, dc[d2 + 1], dc[d2 - 1], dc[d2 + AX], dc[d2 - AX],
                                  dd[sam1][d2], n2D, fx2, false, T(0), T(0), T(0), ro, uo, vo, wo);
             const PlaneAccess<false, T> po(out, k2, plane, pbytes, fbytes);
             bstore(ro, po.r, ooff, po.soff);
