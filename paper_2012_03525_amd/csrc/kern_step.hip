@@ -79,10 +79,14 @@ template <int TX, int TY, int RPT>
 struct Shape3 {
     static constexpr int RX = TX + 4, RY = TY + 4, RXY = RX * RY;
     static constexpr int DX = TX + 2, DY = TY + 2, DXY = DX * DY;
+    // the drho' ring is stored with the staged region's row stride RX (the
+    // last two columns of each row unused), so a wave's lanes walk
+    // consecutive LDS words instead of wrapping to the next DX-wide row
+    static constexpr int SDXY = RX * DY;
     static constexpr int NT = TX * TY / RPT;        // threads; each owns RPT rows of one column
     static constexpr int YS = TY / RPT;             // row stride between a thread's rows
     static constexpr int NL = (RXY + NT - 1) / NT;  // plane points staged per thread
-    static constexpr int ND = (DXY + NT - 1) / NT;  // drho' points per thread
+    static constexpr int ND = (SDXY + NT - 1) / NT;  // drho' slots per thread
 };
 
 // WPE > 0 asks the compiler for at least WPE waves per SIMD (a register
@@ -92,7 +96,7 @@ __global__ __launch_bounds__(TX * TY / RPT) __attribute__((amdgpu_waves_per_eu(W
                                                                 int nbx, int nby)
 {
     using S = Shape3<TX, TY, RPT>;
-    constexpr int RX = S::RX, RXY = S::RXY, DX = S::DX, DXY = S::DXY, NT = S::NT, NL = S::NL, ND = S::ND;
+    constexpr int RX = S::RX, RXY = S::RXY, DX = S::DX, SDXY = S::SDXY, NT = S::NT, NL = S::NL, ND = S::ND;
     constexpr int YS = S::YS;
     static_assert(NS == 3 || NS == 4, "three or four resident planes");
     // plane p lives in slot (p - z0) mod NS; the loop body is unrolled over P
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(TX * TY / RPT) __attribute__((amdgpu_waves_per_eu(W
     // compile time
     constexpr int P = NS == 4 ? 4 : 6;
     __shared__ T sr[NS][RXY], su[NS][RXY], sv[NS][RXY], sw[NS][RXY];
-    __shared__ T sd[2][DXY];
+    __shared__ T sd[2][SDXY];
     // ghost velocity rules u_a = gs[0][f][a] u_a + gs[1][f][a] per crossed
     // face f, looked up per lane from LDS (GEN only)
     __shared__ T gs[2][6][3];
@@ -140,11 +144,13 @@ __global__ __launch_bounds__(TX * TY / RPT) __attribute__((amdgpu_waves_per_eu(W
     }
     // drho' ring positions (mirror substitution for wall / symmetry ghosts)
     int dsrc[ND];
+    bool dval[ND];  // the slot holds a ring point
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
         const int q = tid + i * NT;
-        const int qq = q < DXY ? q : 0;
-        const int ly = qq / DX, lx = qq - ly * DX;
+        dval[i] = q < SDXY && q % RX < DX;
+        const int qq = dval[i] ? q : 0;
+        const int ly = qq / RX, lx = qq - ly * RX;
         int ex = lx + 1, ey = ly + 1;
         if (GEN && !inplane_interior && c.nonperiodic) {
             const int mx = mirror_coord(x0 + lx - 1, nx, c.bc[0]);
@@ -242,7 +248,7 @@ __global__ __launch_bounds__(TX * TY / RPT) __attribute__((amdgpu_waves_per_eu(W
 #pragma unroll
         for (int i = 0; i < ND; ++i) {
             const int q = tid + i * NT;
-            if ((i + 1) * NT <= DXY || q < DXY)
+            if (dval[i])
                 sd[ds][q] = rho_new_3d<GEN, T, RX>(c, sr[s0], su[s0], sv[s0], sr[sD], sw[sD], sr[sU], sw[sU],
                                                    dsrc[i]);
         }
@@ -302,7 +308,7 @@ __global__ __launch_bounds__(TX * TY / RPT) __attribute__((amdgpu_waves_per_eu(W
     __syncthreads();
     if (!(zperiodic || z0 > 0)) {  // wall / symmetry at z = 0: drho'(-1) is the mirror value
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) rn_prev[r] = sd[0][(tyb + r * YS + 1) * DX + (tx + 1)];
+        for (int r = 0; r < RPT; ++r) rn_prev[r] = sd[0][(tyb + r * YS + 1) * RX + (tx + 1)];
     }
 
     const T rho0 = c.rho0, cs2 = c.cs2;
@@ -344,7 +350,7 @@ __global__ __launch_bounds__(TX * TY / RPT) __attribute__((amdgpu_waves_per_eu(W
         for (int r = 0; r < RPT; ++r) {
             const int ty = tyb + r * YS;
             const int e = (ty + 2) * RX + (tx + 2);
-            const int dO = (ty + 1) * DX + (tx + 1);
+            const int dO = (ty + 1) * RX + (tx + 1);
             const T rc = r0[e], uc = u0[e], vc = v0[e], wc = w0[e];
             const T rnC = dc[dO];
             const T rn_next = upper_ghost ? rnC : dn[dO];
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(TX * TY / RPT) __attribute__((amdgpu_waves_per_eu(W
             const T lpy = fmaT(T(-6), myC, ((myE + myW) + (myN + myS)) + (myU + myD));
             const T lpz = fmaT(T(-6), mzC, ((mzE + mzW) + (mzN + mzS)) + (mzU + mzD));
             const T sx = (dc[dO + 1] - dc[dO - 1]) - gxr;
-            const T sy = (dc[dO + DX] - dc[dO - DX]) - gyr;
+            const T sy = (dc[dO + RX] - dc[dO - RX]) - gyr;
             const T sz = (rn_next - rn_prev[r]) - gzr;
             const T rho_n = rho0 + rnC;
             T gx_ = c.gdt[0];
