@@ -15,12 +15,12 @@
 //   D  drho'' on the tile + 1 ring       3 planes
 // One iteration forms level n+1 on plane k1 (stage 1) and level n+2 on plane
 // k2 = k1 - 2 (stage 2) with four barriers; level-n planes k1 + 3 .. k1 + 5
-// are in flight in registers meanwhile.  The plane below the one being updated (level n at
-// the stage-1 nodes, level n+1 at the own node) and its drho' / drho'' stay
-// in registers, as in the one-step march.
+// are in flight in registers meanwhile.  The plane below the one being
+// updated (level n at the stage-1 nodes, level n+1 at the own node) and its
+// drho' / drho'' stay in registers, as in the one-step march.
 //
 // Selected by tile codes 14 and 15 only.  On a 256^3 grid it takes 318 us per
-// launch (159 us per step) against 137 us per one-step launch: the four
+// launch (159 us per step) against 133-137 us per one-step launch: the four
 // level-n+1 fields on the grown tile take LDS that holds the CU to eight
 // waves (two per SIMD), too few to hide the LDS latency of the larger
 // per-node work, so halving the HBM traffic does not pay.
