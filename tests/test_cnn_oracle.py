@@ -103,3 +103,44 @@ def test_box_filter_and_prolongation(cnn):
     fine = cnn.prolong_bilinear(cm, 4)
     yf = np.arange(n) * 2 * np.pi / n
     assert np.abs(fine - np.sin(yf)[:, None]).max() < (2 * np.pi * 4 / n) ** 2 / 8 + 1e-12
+
+
+def test_box_filter_block_assignment_one_hot(cnn):
+    """Every fine node (J, I) of a non-square 12 x 20 grid, factor 4, as a
+    one-hot field: the filtered field is 1/16 at coarse node (J // 4, I // 4)
+    and zero elsewhere (coarse node (K, L) averages fine rows 4K..4K+3 and
+    columns 4L..4L+3; a transposed, strided or shifted block assignment fails
+    for some node).  A factor-2 filter of the same field puts 1/4 at
+    (J // 2, I // 2)."""
+    H, W = 12, 20
+    for J in range(H):
+        for I in range(W):
+            f = np.zeros((H, W))
+            f[J, I] = 1.0
+            for r in (4, 2):
+                c = cnn.box_filter(f, r)
+                assert c.shape == (H // r, W // r)
+                e = np.zeros((H // r, W // r))
+                e[J // r, I // r] = 1.0 / (r * r)
+                np.testing.assert_array_equal(c, e)
+
+
+def test_prolongation_places_coarse_nodes_at_block_centres(cnn):
+    """Coarse node I sits at fine coordinate r I + (r - 1)/2: prolonging a
+    one-hot coarse field gives the tent 1 - |x - x_I| / r around that point
+    (product over both axes), periodic, and the fine values of each coarse
+    block average back to the tent's cell averages; a linear field in a
+    period-free slice is reproduced exactly."""
+    Hc, Wc, r = 5, 6, 4
+    for K, L in [(0, 0), (2, 3), (4, 5)]:
+        c = np.zeros((Hc, Wc))
+        c[K, L] = 1.0
+        f = cnn.prolong_bilinear(c, r)
+        yc, xc = r * K + (r - 1) / 2, r * L + (r - 1) / 2
+        def tent(pos, centre, n):
+            d = np.abs(pos - centre)
+            d = np.minimum(d, n - d)  # periodic distance
+            return np.clip(1 - d / r, 0, None)
+        ty = tent(np.arange(Hc * r), yc, Hc * r)
+        tx = tent(np.arange(Wc * r), xc, Wc * r)
+        np.testing.assert_allclose(f, ty[:, None] * tx[None, :], rtol=0, atol=1e-15)
