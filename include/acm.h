@@ -158,16 +158,27 @@ typedef struct acm_handle acm_handle;
  * of the bulk Cahn-Hilliard mode (stable when <= 2).  Pure host call. */
 acm_status acm_stability(const acm_config* cfg, double* max_amplification, double* che_number);
 
-/* Validate cfg, check stability (unless allow_unstable), and bind the two
- * caller-owned state sets a and b (each sized for the grid and precision).
- * The initial state must already be in a.  force_x: NULL or a device array
- * of ny elements (precision type) added to g[0] on row j (e.g. Kolmogorov
- * forcing).  stream: hipStream_t or NULL.  The handle owns only host data,
- * graph executables and a small reduction buffer it allocates here, plus,
- * for 3D two-phase runs, 4 fields of intermediates (phi* and the surface-
- * tension force per axis). */
-acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b,
-                    const void* force_x, void* stream, acm_handle** out);
+/* Bytes of device scratch that acm_init needs for cfg: the FP64 partial and
+ * final sums of the diagnostics reductions (about 14 doubles per 256 nodes,
+ * at most 229 KiB) and, for 3D two-phase runs, four fields of nx*ny*nz
+ * values of the precision type (phi* of Heun's first stage and the surface-
+ * tension force phi G_iso mu per axis, Sec. 2).  Returns 0 and sets
+ * acm_last_error for an invalid cfg.  Pure host call. */
+size_t acm_scratch_bytes(const acm_config* cfg);
+
+/* Validate cfg, check stability (unless allow_unstable), bind the two
+ * caller-owned state sets a and b (each sized for the grid and precision)
+ * and the caller-owned scratch buffer, and capture the HIP graphs of one
+ * chunk of steps from either set.  The initial state must already be in a.
+ * force_x: NULL or a device array of ny elements (precision type) added to
+ * g[0] on row j (e.g. Kolmogorov forcing).  scratch: device memory of at
+ * least acm_scratch_bytes(cfg) bytes (scratch_bytes), 256-byte aligned; it
+ * must stay allocated, and must not be used by anything else, until
+ * acm_destroy.  stream: hipStream_t or NULL.  The handle allocates no device
+ * memory: it owns host data, a capture stream and the graph executables.
+ * ACM_EINVAL for a NULL, misaligned or short scratch buffer. */
+acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b, const void* force_x,
+                    void* scratch, size_t scratch_bytes, void* stream, acm_handle** out);
 
 /* One step: the newest state moves from one set to the other.  Async. */
 acm_status acm_step(acm_handle* h);
@@ -226,9 +237,9 @@ typedef struct acm_batch_case {
     acm_fields a, b;       /* caller-owned state sets; initial state in a    */
     const void* force_x;   /* NULL or ny values added to g[0] on row j       */
     int64_t nsteps;        /* steps to run (rounded up to whole chunks)      */
-    int32_t tile;          /* 2D tile variant 0..5, or -1: the autotuner's
-                              choice for this (nx, ny, precision), measured on
-                              first use and cached for the process             */
+    int32_t tile;          /* 2D tile variant 0..5, or -1: the tile recorded
+                              for this (nx, ny, precision, launch mode) by
+                              acm_batch_autotune / acm_batch_set_tuned_tile  */
 } acm_batch_case;
 
 typedef struct acm_batch_opts {
@@ -251,12 +262,24 @@ typedef struct acm_batch_case_status {
     double umax;           /* max |u| at the last health check               */
 } acm_batch_case_status;
 
+/* Bytes of device scratch acm_batch_init needs for these cases and options:
+ * the case records, the item table (for a case with tile -1 sized for the
+ * variant with the most tiles), the item count, two queue counters, the
+ * active list and the health pairs, each part 256-byte aligned.  Returns 0
+ * and sets acm_last_error when a case or option is invalid.  Pure host call. */
+size_t acm_batch_scratch_bytes(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts);
+
 /* Validate every case (2D, single-phase, common precision, stability unless
- * allow_unstable), upload the case table, size the persistent grid and
- * capture the chunk graph.  Allocates small device tables (case records,
- * item list, queue counters, health buffer) owned by the batch. */
-acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts,
-                          void* stream, acm_batch** out);
+ * allow_unstable), upload the case table into the caller's scratch (at least
+ * acm_batch_scratch_bytes bytes, 256-byte aligned, kept allocated and unused
+ * by anything else until acm_batch_destroy), size the persistent grid and
+ * capture the chunk graph.  A case with tile -1 takes the tile that
+ * acm_batch_autotune (or acm_batch_set_tuned_tile) recorded for its grid
+ * shape, precision and launch mode in this process: ACM_ESTATE if there is
+ * none.  The batch allocates no device memory.  Synchronises the stream
+ * once (the case table upload). */
+acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts, void* scratch,
+                          size_t scratch_bytes, void* stream, acm_batch** out);
 
 /* Run up to max_chunks chunks (-1: until every case finished or diverged).
  * Synchronises the stream once per chunk (health read-back).
@@ -271,13 +294,23 @@ acm_status acm_batch_timing(const acm_batch* b, double* total_ms, int64_t* latti
 
 void acm_batch_destroy(acm_batch* b);
 
-/* Tile autotuner: time `copies` periodic n x n cases for `steps` steps with
- * every 2D tile variant (0..5) through the batched kernel (mode 0; batches
- * in mode 1 tune through their own mode); ms_per_tile[6]
- * receives ms per step, *best the fastest variant.  Allocates and frees its
- * own scratch fields.  The choice changes only speed, never results. */
-acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int32_t steps, void* stream,
-                              double* ms_per_tile, int32_t* best);
+/* Tile autotuner: time `copies` periodic nx x ny cases for `steps` steps
+ * (even) with every 2D tile variant (0..5) through the batched kernel in the
+ * given launch mode; ms_per_tile[6] receives ms per step, *best the fastest
+ * variant, which is also recorded for (nx, ny, precision, mode) for the
+ * life of the process (the choice changes only speed, never results).
+ * scratch: device memory of acm_batch_autotune_scratch_bytes bytes,
+ * 256-byte aligned, for the copies' fields and the tuning batches' tables;
+ * free again when the call returns.  Synchronises the stream. */
+size_t acm_batch_autotune_scratch_bytes(int32_t nx, int32_t ny, int32_t precision, int32_t copies);
+acm_status acm_batch_autotune(int32_t nx, int32_t ny, int32_t precision, int32_t mode, int32_t copies, int32_t steps,
+                              void* scratch, size_t scratch_bytes, void* stream, double* ms_per_tile, int32_t* best);
+
+/* The tile recorded for (nx, ny, precision, mode) in this process
+ * (ACM_ESTATE if none), and a way to record one measured earlier, e.g. in a
+ * previous process on the same kind of GPU.  Pure host calls. */
+acm_status acm_batch_tuned_tile(int32_t nx, int32_t ny, int32_t precision, int32_t mode, int32_t* tile);
+acm_status acm_batch_set_tuned_tile(int32_t nx, int32_t ny, int32_t precision, int32_t mode, int32_t tile);
 
 /* ------------------------------------------------------------------------ */
 /* Learned closure: a CNN correcting a 4x-coarser SMAME step                 */

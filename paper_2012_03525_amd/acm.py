@@ -75,8 +75,10 @@ _lib: Optional[ctypes.CDLL] = None
 SIGNATURES = {
     "acm_stability": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]),
+    "acm_scratch_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config)]),
     "acm_init": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(Fields), ctypes.POINTER(Fields),
-                                ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_void_p)]),
     "acm_step": (ctypes.c_int, [ctypes.c_void_p]),
     "acm_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "acm_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diag)]),
@@ -88,16 +90,22 @@ SIGNATURES = {
     "acm_last_error": (ctypes.c_char_p, []),
     "acm_version": (ctypes.c_char_p, []),
     "acm_stream_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "acm_batch_scratch_bytes": (ctypes.c_size_t, [ctypes.POINTER(BatchCase), ctypes.c_int32,
+                                                  ctypes.POINTER(BatchOpts)]),
     "acm_batch_init": (ctypes.c_int, [ctypes.POINTER(BatchCase), ctypes.c_int32, ctypes.POINTER(BatchOpts),
-                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
     "acm_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "acm_batch_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(BatchCaseStatus)]),
     "acm_batch_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]),
     "acm_batch_destroy": (None, [ctypes.c_void_p]),
-    "acm_batch_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
-                                          ctypes.POINTER(ctypes.c_int32)]),
+    "acm_batch_autotune_scratch_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 4),
+    "acm_batch_autotune": (ctypes.c_int, [ctypes.c_int32] * 6 + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                                                 ctypes.POINTER(ctypes.c_double),
+                                                                 ctypes.POINTER(ctypes.c_int32)]),
+    "acm_batch_tuned_tile": (ctypes.c_int, [ctypes.c_int32] * 4 + [ctypes.POINTER(ctypes.c_int32)]),
+    "acm_batch_set_tuned_tile": (ctypes.c_int, [ctypes.c_int32] * 5),
     "acm_cnn_layer_shape": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32)]),
     "acm_cnn_conv": (ctypes.c_int, [ctypes.c_int32] * 5 + [ctypes.c_void_p] * 6),
@@ -206,6 +214,24 @@ def stability(cfg: Config):
     return amp.value, che.value
 
 
+def scratch_bytes(cfg: Config) -> int:
+    """Device scratch bytes acm_init needs for cfg."""
+    n = lib().acm_scratch_bytes(ctypes.byref(cfg))
+    if n == 0:
+        raise AcmError(EINVAL, lib().acm_last_error().decode())
+    return int(n)
+
+
+def scratch_tensor(nbytes: int, device):
+    """A device byte buffer of at least nbytes, 256-byte aligned (torch's
+    caching allocator hands out 512-byte aligned blocks; checked here)."""
+    import torch
+    t = torch.empty(max(1, nbytes), dtype=torch.uint8, device=device)
+    if t.data_ptr() % 256:
+        raise AcmError(EINVAL, "torch returned a scratch block that is not 256-byte aligned")
+    return t
+
+
 def stream_copy(dst, src, nbytes: int, stream=None):
     """Device copy through the library's plain copy kernel (torch tensors)."""
     import torch
@@ -249,9 +275,12 @@ class Solver:
                 device=self.device, dtype=self.dtype)
         self._f = [self._fields(s) for s in self.sets]
         self.stream = torch.cuda.current_stream(self.device)
+        nbytes = scratch_bytes(cfg)
+        self.scratch = scratch_tensor(nbytes, self.device)
         h = ctypes.c_void_p()
         check(lib().acm_init(ctypes.byref(cfg), ctypes.byref(self._f[0]), ctypes.byref(self._f[1]),
                              ctypes.c_void_p(self.force.data_ptr() if self.force is not None else None),
+                             ctypes.c_void_p(self.scratch.data_ptr()), ctypes.c_size_t(nbytes),
                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.h = h
 
@@ -350,8 +379,16 @@ class Batch:
         self._cases = arr
         opts = BatchOpts(chunk, blocks, grab, umax_limit, mode)
         self.stream = torch.cuda.current_stream()
+        untuned = {(c.nx, c.ny) for i, c in enumerate(cfgs) if tiles is None or int(tiles[i]) < 0}
+        if untuned:
+            ensure_tuned(sorted(untuned), prec, mode)
+        nbytes = lib().acm_batch_scratch_bytes(arr, n, ctypes.byref(opts))
+        if nbytes == 0:
+            raise AcmError(EINVAL, lib().acm_last_error().decode())
+        self.scratch = scratch_tensor(nbytes, device)
         h = ctypes.c_void_p()
-        check(lib().acm_batch_init(arr, n, ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
+        check(lib().acm_batch_init(arr, n, ctypes.byref(opts), ctypes.c_void_p(self.scratch.data_ptr()),
+                                   ctypes.c_size_t(nbytes), ctypes.c_void_p(self.stream.cuda_stream),
                                    ctypes.byref(h)))
         self.h = h
         self.n = n
@@ -390,15 +427,74 @@ class Batch:
             pass
 
 
-def autotune(n: int, precision: str = "f32", copies: int = 0, steps: int = 100):
-    """Time every 2D tile variant on copies of an n x n case; returns
-    (best_tile, ms_per_step_per_tile)."""
+def autotune(nx: int, ny: Optional[int] = None, precision: str = "f32", copies: int = 0, steps: int = 100,
+             mode: int = 0):
+    """Time every 2D tile variant on copies of a periodic nx x ny case through
+    the batched kernel; the library records the fastest for (nx, ny,
+    precision, mode).  Returns (best_tile, ms_per_step_per_tile)."""
     import torch
+    ny = nx if ny is None else ny
+    prec = {"f64": F64, "f32": F32}[precision] if isinstance(precision, str) else int(precision)
     if copies <= 0:
-        copies = max(1, (1 << 22) // (n * n))
+        copies = min(1024, max(1, (1 << 22) // (nx * ny)))
+    nbytes = lib().acm_batch_autotune_scratch_bytes(nx, ny, prec, copies)
+    if nbytes == 0:
+        raise AcmError(EINVAL, lib().acm_last_error().decode())
+    scratch = scratch_tensor(nbytes, torch.device("cuda", torch.cuda.current_device()))
     ms = (ctypes.c_double * 6)()
     best = ctypes.c_int32()
-    check(lib().acm_batch_autotune(int(n), {"f64": F64, "f32": F32}[precision], int(copies), int(steps),
+    check(lib().acm_batch_autotune(int(nx), int(ny), prec, int(mode), int(copies), int(steps),
+                                   ctypes.c_void_p(scratch.data_ptr()), ctypes.c_size_t(nbytes),
                                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ms,
                                    ctypes.byref(best)))
+    del scratch
     return best.value, list(ms)
+
+
+def _tune_cache_path() -> str:
+    base = os.environ.get("ACM_TUNE_CACHE")
+    if base:
+        return base
+    return os.path.join(os.path.expanduser("~"), ".cache", "paper_2012_03525_amd", "batch_tiles.json")
+
+
+def _gpu_arch() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def ensure_tuned(shapes, precision: int, mode: int = 0, steps: int = 20):
+    """Make sure the library holds a tuned tile for every (nx, ny) in shapes:
+    take it from the on-disk cache (keyed by GPU architecture, grid shape,
+    precision and launch mode) when present, else run the autotuner and add
+    its choice to the cache.  The tile changes only speed, never results."""
+    import json
+    path = _tune_cache_path()
+    try:
+        with open(path) as f:
+            disk = json.load(f)
+    except (OSError, ValueError):
+        disk = {}
+    arch = _gpu_arch()
+    changed = False
+    for nx, ny in shapes:
+        t = ctypes.c_int32()
+        if lib().acm_batch_tuned_tile(nx, ny, precision, mode, ctypes.byref(t)) == OK:
+            continue
+        key = f"{arch}/{nx}x{ny}/{'f64' if precision == F64 else 'f32'}/mode{mode}"
+        if key in disk and 0 <= int(disk[key]) < 6:
+            check(lib().acm_batch_set_tuned_tile(nx, ny, precision, mode, int(disk[key])))
+            continue
+        best, _ = autotune(nx, ny, precision, steps=steps, mode=mode)
+        disk[key] = best
+        changed = True
+    if changed:
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + f".{os.getpid()}.tmp"
+            with open(tmp, "w") as f:
+                json.dump(disk, f, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+        except OSError:
+            pass  # the in-process choice still holds

@@ -84,6 +84,31 @@ double che_number(const acm_config& c)
     return c.dt * c.mobility * lam * (8.0 * a + kappa * lam);
 }
 
+// Layout of the caller's scratch buffer, each part 256-byte aligned: the
+// diagnostics partial sums (NDIAG doubles per reduction workgroup), the
+// NDIAG final sums, and for 3D two-phase runs four fields of intermediates
+// (phi* and phi G_iso mu per axis).
+struct ScratchLayout {
+    int diag_blocks;
+    size_t partials, result, fields, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+ScratchLayout scratch_layout(const acm_config& c)
+{
+    ScratchLayout L{};
+    const double n = (double)c.nx * c.ny * (c.dim == 3 ? c.nz : 1);
+    L.diag_blocks = (int)std::fmin(2048.0, std::fmax(1.0, std::ceil(n / 256.0)));
+    L.partials = 0;
+    L.result = align256(sizeof(double) * NDIAG * (size_t)L.diag_blocks);
+    L.fields = L.result + align256(sizeof(double) * NDIAG);
+    L.total = L.fields;
+    if (c.two_phase && c.dim == 3)
+        L.total += align256((size_t)n * 4 * (c.precision == ACM_F64 ? sizeof(double) : sizeof(float)));
+    return L;
+}
+
 acm_status validate(const acm_config* c)
 {
     if (!c) return fail(ACM_EINVAL, "config is NULL");
@@ -206,13 +231,14 @@ struct acm_handle {
     // per launch
     bool pair = false;
     hipGraphExec_t exec_pair[2] = {nullptr, nullptr};
+    // carved from the caller's scratch buffer (acm_scratch_bytes)
     double* partials = nullptr;
     double* result = nullptr;
-    double* host = nullptr;
+    void* fields = nullptr;  // 3D two-phase intermediates (4 fields)
+    double host[NDIAG];      // diagnostics read-back
     int diag_blocks = 0;
     Coef<float> cf;
     Coef<double> cd;
-    void* scratch = nullptr;  // 3D two-phase intermediates (4 fields)
 };
 
 namespace {
@@ -230,7 +256,7 @@ hipError_t launch_typed(const acm_handle* h, const Coef<T>& c, int from, hipStre
     const State<T> in = state_of<T>(h->set[from]);
     const State<T> out = state_of<T>(h->set[1 - from]);
     if (h->cfg.two_phase && h->cfg.dim == 3)
-        return launch_twophase3d<T>(c, in, out, static_cast<T*>(h->scratch), h->cfg.tile, s);
+        return launch_twophase3d<T>(c, in, out, static_cast<T*>(h->fields), h->cfg.tile, s);
     if (h->cfg.two_phase && h->cfg.axisym) return launch_twophase_axisym2d<T>(c, in, out, h->cfg.tile, s);
     if (h->cfg.two_phase) return launch_twophase2d<T>(c, in, out, h->cfg.tile, s);
     if (h->cfg.dim == 3) return launch_step3d<T>(c, in, out, h->cfg.tile, s);
@@ -300,8 +326,15 @@ acm_status acm_stability(const acm_config* cfg, double* max_amp, double* che)
     return ACM_OK;
 }
 
+size_t acm_scratch_bytes(const acm_config* cfg)
+{
+    g_err.clear();
+    if (validate(cfg) != ACM_OK) return 0;
+    return scratch_layout(*cfg).total;
+}
+
 acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields* b, const void* force_x,
-                    void* stream, acm_handle** out)
+                    void* scratch, size_t scratch_bytes, void* stream, acm_handle** out)
 {
     g_err.clear();
     if (!out) return fail(ACM_EINVAL, "out is NULL");
@@ -316,6 +349,12 @@ acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields
         if (cfg->dim == 3 && !f->w) return fail(ACM_EINVAL, "w is required in 3D");
         if (cfg->two_phase && !f->phi) return fail(ACM_EINVAL, "phi is required for two-phase runs");
     }
+    const ScratchLayout L = scratch_layout(*cfg);
+    if (!scratch) return fail(ACM_EINVAL, "scratch is NULL (acm_scratch_bytes gives its size)");
+    if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0) return fail(ACM_EINVAL, "scratch must be 256-byte aligned");
+    if (scratch_bytes < L.total)
+        return fail(ACM_EINVAL, "scratch holds " + std::to_string(scratch_bytes) + " bytes, the configuration needs " +
+                                    std::to_string(L.total));
     if (!cfg->allow_unstable) {
         const double amp = max_amplification(*cfg);
         if (amp > 1.0 + 1e-12) {
@@ -341,6 +380,11 @@ acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields
     h->chunk = cfg->graph_chunk > 0 ? cfg->graph_chunk : 64;
     h->cf = make_coef<float>(*cfg, force_x);
     h->cd = make_coef<double>(*cfg, force_x);
+    char* base = static_cast<char*>(scratch);
+    h->partials = reinterpret_cast<double*>(base + L.partials);
+    h->result = reinterpret_cast<double*>(base + L.result);
+    h->fields = (cfg->two_phase && cfg->dim == 3) ? base + L.fields : nullptr;
+    h->diag_blocks = L.diag_blocks;
     if (cfg->dim == 3 && !cfg->two_phase)
         h->pair = cfg->precision == ACM_F64 ? step3d_pair_ok<double>(h->cd, cfg->tile)
                                             : step3d_pair_ok<float>(h->cf, cfg->tile);
@@ -349,16 +393,16 @@ acm_status acm_init(const acm_config* cfg, const acm_fields* a, const acm_fields
         delete h;
         return hip_fail(e, "hipStreamCreateWithFlags");
     }
-    const double n = (double)cfg->nx * cfg->ny * (cfg->dim == 3 ? cfg->nz : 1);
-    h->diag_blocks = (int)std::fmin(2048.0, std::fmax(1.0, std::ceil(n / 256.0)));
-    e = hipMalloc(&h->partials, sizeof(double) * NDIAG * (size_t)h->diag_blocks);
-    if (e == hipSuccess) e = hipMalloc(&h->result, sizeof(double) * NDIAG);
-    if (e == hipSuccess) e = hipHostMalloc(&h->host, sizeof(double) * NDIAG, hipHostMallocDefault);
-    if (e == hipSuccess && cfg->two_phase && cfg->dim == 3)
-        e = hipMalloc(&h->scratch, (size_t)n * 4 * (cfg->precision == ACM_F64 ? sizeof(double) : sizeof(float)));
-    if (e != hipSuccess) {
+    // capture the chunk graphs of both parities now, so that no run call
+    // pays for (or times) a capture
+    for (int p = 0; p < 2 && st == ACM_OK; ++p) {
+        st = build_graph(h, p, false);
+        if (st == ACM_OK && h->pair) st = build_graph(h, p, true);
+    }
+    if (st != ACM_OK) {
+        const std::string msg = g_err;
         acm_destroy(h);
-        return hip_fail(e, "allocating reduction and scratch buffers");
+        return fail(st, msg);
     }
     *out = h;
     return ACM_OK;
@@ -382,12 +426,7 @@ acm_status acm_run(acm_handle* h, int64_t nsteps)
         // two steps per launch; the run ends with a one-step launch, so the
         // other set holds the state one step back, as after one-step runs
         while (nsteps > h->chunk) {
-            const int p = h->which;
-            if (!h->exec_pair[p]) {
-                acm_status st = build_graph(h, p, true);
-                if (st != ACM_OK) return st;
-            }
-            hipError_t e = hipGraphLaunch(h->exec_pair[p], h->stream);
+            hipError_t e = hipGraphLaunch(h->exec_pair[h->which], h->stream);
             if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
             h->which ^= (h->chunk / 2) & 1;
             h->step += h->chunk;
@@ -402,12 +441,7 @@ acm_status acm_run(acm_handle* h, int64_t nsteps)
         }
     }
     while (nsteps >= h->chunk) {
-        const int p = h->which;
-        if (!h->exec[p]) {
-            acm_status st = build_graph(h, p, false);
-            if (st != ACM_OK) return st;
-        }
-        hipError_t e = hipGraphLaunch(h->exec[p], h->stream);
+        hipError_t e = hipGraphLaunch(h->exec[h->which], h->stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
         h->step += h->chunk;  // chunk is even: the parity is unchanged
         nsteps -= h->chunk;
@@ -525,10 +559,6 @@ void acm_destroy(acm_handle* h)
         if (h->exec[p]) (void)hipGraphExecDestroy(h->exec[p]);
         if (h->exec_pair[p]) (void)hipGraphExecDestroy(h->exec_pair[p]);
     }
-    if (h->partials) (void)hipFree(h->partials);
-    if (h->result) (void)hipFree(h->result);
-    if (h->host) (void)hipHostFree(h->host);
-    if (h->scratch) (void)hipFree(h->scratch);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
 }

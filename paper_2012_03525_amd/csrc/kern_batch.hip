@@ -187,16 +187,17 @@ struct acm_batch {
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
+    // device tables, carved from the caller's scratch (batch_layout)
     void* dcases = nullptr;   // BatchCaseDev<T>[n]
     int4* ditems = nullptr;
     int* dnitems = nullptr;
     int* dqueue = nullptr;
     int* dactive = nullptr;
     double* dhealth = nullptr;
-    int4* hitems = nullptr;   // pinned
-    int* hnitems = nullptr;   // pinned
-    int* hactive = nullptr;   // pinned
-    double* hhealth = nullptr;  // pinned
+    std::vector<int4> hitems;
+    int hnitems = 0;
+    std::vector<int> hactive;
+    std::vector<double> hhealth;
     size_t max_items = 0;
     std::vector<int> tile, nx, ny, state;
     std::vector<int64_t> nsteps, done;
@@ -208,6 +209,42 @@ struct acm_batch {
 };
 
 namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Items of one case: (tiles in x) * (tiles in y) of its tile variant; for
+// tile -1 the largest count over the variants, so the scratch size does not
+// depend on the autotuner's choice.
+size_t case_items(int nx, int ny, int tile)
+{
+    size_t m = 0;
+    for (int t = 0; t < NTILE2D; ++t) {
+        if (tile >= 0 && t != tile) continue;
+        m = std::max(m, (size_t)((nx + TILE_W[t] - 1) / TILE_W[t]) * ((ny + TILE_H[t] - 1) / TILE_H[t]));
+    }
+    return m;
+}
+
+// Layout of the batch's device tables in the caller's scratch, each part
+// 256-byte aligned: case records, item table, item count, queue counters,
+// active list, health pairs.
+struct BatchLayout {
+    size_t cases, items, nitems, queue, active, health, total;
+};
+
+BatchLayout batch_layout(int ncases, size_t max_items, int precision)
+{
+    const size_t rec = precision == ACM_F64 ? sizeof(BatchCaseDev<double>) : sizeof(BatchCaseDev<float>);
+    BatchLayout L{};
+    L.cases = 0;
+    L.items = L.cases + align256(rec * (size_t)ncases);
+    L.nitems = L.items + align256(sizeof(int4) * std::max<size_t>(1, max_items));
+    L.queue = L.nitems + 256;
+    L.active = L.queue + 256;
+    L.health = L.active + align256(sizeof(int) * (size_t)ncases);
+    L.total = L.health + align256(2 * sizeof(double) * (size_t)ncases);
+    return L;
+}
 
 template <typename T>
 hipError_t upload_cases(acm_batch* b, const acm_batch_case* cases)
@@ -221,9 +258,10 @@ hipError_t upload_cases(acm_batch* b, const acm_batch_case* cases)
                                  nullptr, nullptr};
         h[i].tile = b->tile[i];
     }
-    hipError_t e = hipMalloc(&b->dcases, sizeof(BatchCaseDev<T>) * b->n);
+    hipError_t e = hipMemcpyAsync(b->dcases, h.data(), sizeof(BatchCaseDev<T>) * b->n, hipMemcpyHostToDevice,
+                                  b->stream);
     if (e != hipSuccess) return e;
-    return hipMemcpy(b->dcases, h.data(), sizeof(BatchCaseDev<T>) * b->n, hipMemcpyHostToDevice);
+    return hipStreamSynchronize(b->stream);  // h is released on return
 }
 
 template <typename T>
@@ -286,23 +324,26 @@ acm_status build_graph(acm_batch* b)
 }  // namespace
 
 namespace {
-acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, void* stream, double* ms_per_tile,
-                          int32_t* best, int mode);
+acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, void* scratch, size_t scratch_bytes,
+                          void* stream, double* ms_per_tile, int32_t* best, int mode);
+
+bool tuned_tile(int nx, int ny, int precision, int mode, int* tile)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    const auto it = g_tune_cache.find(std::make_tuple(nx, ny, precision, mode));
+    if (it == g_tune_cache.end()) return false;
+    *tile = it->second;
+    return true;
 }
 
-extern "C" {
-
-acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts, void* stream,
-                          acm_batch** out)
+// checks shared by acm_batch_scratch_bytes and acm_batch_init
+acm_status check_cases(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts, size_t* max_items)
 {
-    set_error("");
-    if (!out || !cases || ncases <= 0) return bfail(ACM_EINVAL, "cases / out / ncases invalid");
-    *out = nullptr;
+    if (!cases || ncases <= 0) return bfail(ACM_EINVAL, "cases / ncases invalid");
     const int prec = cases[0].cfg.precision;
-    const int chunk = (opts && opts->chunk > 0) ? opts->chunk : 500;
-    if (chunk % 2) return bfail(ACM_EINVAL, "chunk must be even");
+    if (opts && opts->chunk > 0 && opts->chunk % 2) return bfail(ACM_EINVAL, "chunk must be even");
     if (opts && opts->mode != 0 && opts->mode != 1) return bfail(ACM_EINVAL, "mode must be 0 or 1");
-    const int mode = opts ? opts->mode : 0;
+    size_t items = 0;
     for (int i = 0; i < ncases; ++i) {
         const acm_batch_case& k = cases[i];
         std::string err;
@@ -310,37 +351,80 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
         if (k.cfg.dim != 2 || k.cfg.two_phase || k.cfg.axisym)
             return bfail(ACM_EINVAL, "batched cases are 2D single-phase planar");
         if (k.cfg.precision != prec) return bfail(ACM_EINVAL, "every case of a batch needs the same precision");
+        if (k.tile < -1 || k.tile >= NTILE2D) return bfail(ACM_EINVAL, "tile must be -1..5");
+        items += case_items(k.cfg.nx, k.cfg.ny, k.tile);
+    }
+    if (max_items) *max_items = items;
+    return ACM_OK;
+}
+}
+
+extern "C" {
+
+size_t acm_batch_scratch_bytes(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts)
+{
+    set_error("");
+    size_t items = 0;
+    if (check_cases(cases, ncases, opts, &items) != ACM_OK) return 0;
+    return batch_layout(ncases, items, cases[0].cfg.precision).total;
+}
+
+acm_status acm_batch_tuned_tile(int32_t nx, int32_t ny, int32_t precision, int32_t mode, int32_t* tile)
+{
+    if (!tile) return bfail(ACM_EINVAL, "tile is NULL");
+    int t = 0;
+    if (!tuned_tile(nx, ny, precision, mode, &t)) return bfail(ACM_ESTATE, "grid shape not tuned");
+    *tile = t;
+    return ACM_OK;
+}
+
+acm_status acm_batch_set_tuned_tile(int32_t nx, int32_t ny, int32_t precision, int32_t mode, int32_t tile)
+{
+    if (nx < 4 || ny < 4 || (precision != ACM_F32 && precision != ACM_F64) || (mode != 0 && mode != 1) || tile < 0 ||
+        tile >= NTILE2D)
+        return bfail(ACM_EINVAL, "set_tuned_tile: bad arguments");
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[std::make_tuple((int)nx, (int)ny, (int)precision, (int)mode)] = tile;
+    return ACM_OK;
+}
+
+acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts, void* scratch,
+                          size_t scratch_bytes, void* stream, acm_batch** out)
+{
+    set_error("");
+    if (!out) return bfail(ACM_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t items_bound = 0;
+    acm_status cst = check_cases(cases, ncases, opts, &items_bound);
+    if (cst != ACM_OK) return cst;
+    const int prec = cases[0].cfg.precision;
+    const int chunk = (opts && opts->chunk > 0) ? opts->chunk : 500;
+    const int mode = opts ? opts->mode : 0;
+    const BatchLayout L = batch_layout(ncases, items_bound, prec);
+    if (!scratch) return bfail(ACM_EINVAL, "scratch is NULL (acm_batch_scratch_bytes gives its size)");
+    if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0) return bfail(ACM_EINVAL, "scratch must be 256-byte aligned");
+    if (scratch_bytes < L.total)
+        return bfail(ACM_EINVAL, "scratch holds " + std::to_string(scratch_bytes) + " bytes, the batch needs " +
+                                     std::to_string(L.total));
+    for (int i = 0; i < ncases; ++i) {
+        const acm_batch_case& k = cases[i];
         if (!k.a.drho || !k.a.u || !k.a.v || !k.b.drho || !k.b.u || !k.b.v)
             return bfail(ACM_EINVAL, "case " + std::to_string(i) + ": missing field pointers");
         if (k.nsteps <= 0) return bfail(ACM_EINVAL, "nsteps must be positive");
-        if (k.tile < -1 || k.tile >= NTILE2D) return bfail(ACM_EINVAL, "tile must be -1..5");
         if (!k.cfg.allow_unstable && api_max_amplification(k.cfg) > 1.0 + 1e-12)
             return bfail(ACM_EUNSTABLE, "case " + std::to_string(i) + " fails the linear stability check");
     }
-    // tile -1: the autotuner's choice for the case's shape (tuned on first use)
+    // tile -1: the autotuner's choice for the case's shape (acm_batch_autotune)
     std::vector<int> tiles(ncases);
     for (int i = 0; i < ncases; ++i) {
         tiles[i] = cases[i].tile;
         if (tiles[i] >= 0) continue;
-        const auto key = std::make_tuple((int)cases[i].cfg.nx, (int)cases[i].cfg.ny, (int)prec, mode);
-        {
-            std::lock_guard<std::mutex> lock(g_tune_mutex);
-            const auto it = g_tune_cache.find(key);
-            if (it != g_tune_cache.end()) {
-                tiles[i] = it->second;
-                continue;
-            }
-        }
-        double ms[NTILE2D];
-        int32_t best = 0;
-        const int nxy = cases[i].cfg.nx * cases[i].cfg.ny;
-        const int copies = std::min(1024, std::max(1, (1 << 22) / nxy));  // about 4 M nodes
-        const acm_status st =
-            autotune_shape(cases[i].cfg.nx, cases[i].cfg.ny, prec, copies, 20, stream, ms, &best, mode);
-        if (st != ACM_OK) return st;
-        std::lock_guard<std::mutex> lock(g_tune_mutex);
-        g_tune_cache[key] = best;
-        tiles[i] = best;
+        int t = 0;
+        if (!tuned_tile(cases[i].cfg.nx, cases[i].cfg.ny, prec, mode, &t))
+            return bfail(ACM_ESTATE, "case " + std::to_string(i) + ": grid shape " + std::to_string(cases[i].cfg.nx) +
+                                         " x " + std::to_string(cases[i].cfg.ny) +
+                                         " is not tuned for this precision and launch mode (acm_batch_autotune)");
+        tiles[i] = t;
     }
     acm_batch* b = new (std::nothrow) acm_batch();
     if (!b) return bfail(ACM_EINVAL, "out of host memory");
@@ -364,26 +448,28 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
         b->nx[i] = cases[i].cfg.nx;
         b->ny[i] = cases[i].cfg.ny;
         b->nsteps[i] = ((cases[i].nsteps + chunk - 1) / chunk) * chunk;
-        const int t = b->tile[i];
-        b->max_items += (size_t)((b->nx[i] + TILE_W[t] - 1) / TILE_W[t]) * ((b->ny[i] + TILE_H[t] - 1) / TILE_H[t]);
+        b->max_items += case_items(b->nx[i], b->ny[i], tiles[i]);
     }
-    hipError_t e = (prec == ACM_F64) ? upload_cases<double>(b, cases) : upload_cases<float>(b, cases);
-    if (e == hipSuccess) e = hipMalloc(&b->ditems, sizeof(int4) * std::max<size_t>(1, b->max_items));
-    if (e == hipSuccess) e = hipMalloc(&b->dnitems, sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&b->dqueue, 2 * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&b->dactive, sizeof(int) * ncases);
-    if (e == hipSuccess) e = hipMalloc(&b->dhealth, 2 * sizeof(double) * ncases);
-    if (e == hipSuccess) e = hipHostMalloc(&b->hitems, sizeof(int4) * std::max<size_t>(1, b->max_items), 0);
-    if (e == hipSuccess) e = hipHostMalloc(&b->hnitems, sizeof(int), 0);
-    if (e == hipSuccess) e = hipHostMalloc(&b->hactive, sizeof(int) * ncases, 0);
-    if (e == hipSuccess) e = hipHostMalloc(&b->hhealth, 2 * sizeof(double) * ncases, 0);
-    if (e == hipSuccess) e = hipMemset(b->dqueue, 0, 2 * sizeof(int));
+    char* base = static_cast<char*>(scratch);
+    b->dcases = base + L.cases;
+    b->ditems = reinterpret_cast<int4*>(base + L.items);
+    b->dnitems = reinterpret_cast<int*>(base + L.nitems);
+    b->dqueue = reinterpret_cast<int*>(base + L.queue);
+    b->dactive = reinterpret_cast<int*>(base + L.active);
+    b->dhealth = reinterpret_cast<double*>(base + L.health);
+    b->hitems.resize(std::max<size_t>(1, b->max_items));
+    b->hactive.resize(ncases);
+    b->hhealth.resize(2 * (size_t)ncases);
+    // queue counters start at zero (outside any graph; the persistent kernel
+    // resets them itself after every launch)
+    hipError_t e = hipMemsetAsync(b->dqueue, 0, 2 * sizeof(int), b->stream);
+    if (e == hipSuccess) e = (prec == ACM_F64) ? upload_cases<double>(b, cases) : upload_cases<float>(b, cases);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&b->ev_start);
     if (e == hipSuccess) e = hipEventCreate(&b->ev_chunk);
     if (e != hipSuccess) {
         acm_batch_destroy(b);
-        return bfail(ACM_EHIP, std::string("batch allocation: ") + hipGetErrorString(e));
+        return bfail(ACM_EHIP, std::string("batch set-up: ") + hipGetErrorString(e));
     }
     b->blocks = (opts && opts->blocks > 0) ? opts->blocks
                                            : (prec == ACM_F64 ? occupancy_blocks<double>() : occupancy_blocks<float>());
@@ -426,18 +512,19 @@ acm_status acm_batch_run(acm_batch* b, int32_t max_chunks, int32_t* active_left)
         }
         if (active_left) *active_left = nact;
         if (nact == 0 || (max_chunks >= 0 && chunks >= max_chunks)) break;
-        *b->hnitems = (int)nit;
-        e = hipMemcpyAsync(b->ditems, b->hitems, sizeof(int4) * nit, hipMemcpyHostToDevice, b->stream);
+        b->hnitems = (int)nit;
+        e = hipMemcpyAsync(b->ditems, b->hitems.data(), sizeof(int4) * nit, hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(b->dnitems, b->hnitems, sizeof(int), hipMemcpyHostToDevice, b->stream);
+            e = hipMemcpyAsync(b->dnitems, &b->hnitems, sizeof(int), hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(b->dactive, b->hactive, sizeof(int) * nact, hipMemcpyHostToDevice, b->stream);
+            e = hipMemcpyAsync(b->dactive, b->hactive.data(), sizeof(int) * nact, hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
         if (e == hipSuccess)
             e = (b->precision == ACM_F64) ? launch_health<double>(b, nact, b->stream)
                                           : launch_health<float>(b, nact, b->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(b->hhealth, b->dhealth, 2 * sizeof(double) * b->n, hipMemcpyDeviceToHost, b->stream);
+            e = hipMemcpyAsync(b->hhealth.data(), b->dhealth, 2 * sizeof(double) * b->n, hipMemcpyDeviceToHost,
+                               b->stream);
         if (e == hipSuccess) e = hipEventRecord(b->ev_chunk, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) return bfail(ACM_EHIP, std::string("batch chunk: ") + hipGetErrorString(e));
@@ -491,41 +578,53 @@ void acm_batch_destroy(acm_batch* b)
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->ev_start) (void)hipEventDestroy(b->ev_start);
     if (b->ev_chunk) (void)hipEventDestroy(b->ev_chunk);
-    (void)hipFree(b->dcases);
-    (void)hipFree(b->ditems);
-    (void)hipFree(b->dnitems);
-    (void)hipFree(b->dqueue);
-    (void)hipFree(b->dactive);
-    (void)hipFree(b->dhealth);
-    if (b->hitems) (void)hipHostFree(b->hitems);
-    if (b->hnitems) (void)hipHostFree(b->hnitems);
-    if (b->hactive) (void)hipHostFree(b->hactive);
-    if (b->hhealth) (void)hipHostFree(b->hhealth);
     delete b;
 }
 
-acm_status acm_batch_autotune(int32_t n, int32_t precision, int32_t copies, int32_t steps, void* stream,
-                              double* ms_per_tile, int32_t* best)
+size_t acm_batch_autotune_scratch_bytes(int32_t nx, int32_t ny, int32_t precision, int32_t copies)
 {
-    if (n < 4 || copies <= 0 || steps <= 0 || steps % 2 || !ms_per_tile || !best)
+    set_error("");
+    if (nx < 4 || ny < 4 || copies <= 0 || (precision != ACM_F32 && precision != ACM_F64)) {
+        set_error("autotune: bad arguments");
+        return 0;
+    }
+    const size_t es = precision == ACM_F64 ? 8 : 4;
+    return align256((size_t)nx * ny * es * 6 * (size_t)copies) +
+           batch_layout(copies, case_items(nx, ny, -1) * (size_t)copies, precision).total;
+}
+
+acm_status acm_batch_autotune(int32_t nx, int32_t ny, int32_t precision, int32_t mode, int32_t copies, int32_t steps,
+                              void* scratch, size_t scratch_bytes, void* stream, double* ms_per_tile, int32_t* best)
+{
+    if (nx < 4 || ny < 4 || copies <= 0 || steps <= 0 || steps % 2 || !ms_per_tile || !best)
         return bfail(ACM_EINVAL, "autotune: bad arguments");
     if (precision != ACM_F32 && precision != ACM_F64) return bfail(ACM_EINVAL, "autotune: precision");
-    return autotune_shape(n, n, precision, copies, steps, stream, ms_per_tile, best, 0);
+    if (mode != 0 && mode != 1) return bfail(ACM_EINVAL, "autotune: mode must be 0 or 1");
+    const size_t need = acm_batch_autotune_scratch_bytes(nx, ny, precision, copies);
+    if (!scratch || reinterpret_cast<uintptr_t>(scratch) % 256 != 0 || scratch_bytes < need)
+        return bfail(ACM_EINVAL, "autotune: scratch must be 256-byte aligned and hold " + std::to_string(need) +
+                                     " bytes");
+    acm_status st = autotune_shape(nx, ny, precision, copies, steps, scratch, scratch_bytes, stream, ms_per_tile, best,
+                                   mode);
+    if (st != ACM_OK) return st;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[std::make_tuple((int)nx, (int)ny, (int)precision, (int)mode)] = *best;
+    return ACM_OK;
 }
 
 }  // extern "C"
 
 namespace {
-acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, void* stream, double* ms_per_tile,
-                          int32_t* best, int mode)
+acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, void* scratch, size_t scratch_bytes,
+                          void* stream, double* ms_per_tile, int32_t* best, int mode)
 {
     const size_t es = precision == ACM_F64 ? 8 : 4;
     const size_t field = (size_t)nx * ny * es;
-    void* mem = nullptr;
-    hipError_t e = hipMalloc(&mem, field * 6 * (size_t)copies);
-    if (e != hipSuccess) return bfail(ACM_EHIP, "autotune allocation");
+    const size_t fields_bytes = align256(field * 6 * (size_t)copies);
+    char* mem = static_cast<char*>(scratch);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    e = hipMemsetAsync(mem, 0, field * 6 * (size_t)copies, s);
+    hipError_t e = hipMemsetAsync(mem, 0, field * 6 * (size_t)copies, s);
+    if (e != hipSuccess) return bfail(ACM_EHIP, std::string("autotune clear: ") + hipGetErrorString(e));
     std::vector<acm_batch_case> cs(copies);
     for (int i = 0; i < copies; ++i) {
         acm_batch_case& k = cs[i];
@@ -540,7 +639,7 @@ acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, 
         k.cfg.sat_rho = k.cfg.sat_mom = 1.0;
         k.cfg.precision = precision;
         k.cfg.allow_unstable = 1;  // nu = 0.05 is inside the linear bound; skip the per-copy check
-        char* base = static_cast<char*>(mem) + (size_t)i * 6 * field;
+        char* base = mem + (size_t)i * 6 * field;
         k.a = acm_fields{base, base + field, base + 2 * field, nullptr, nullptr};
         k.b = acm_fields{base + 3 * field, base + 4 * field, base + 5 * field, nullptr, nullptr};
         k.nsteps = steps;
@@ -554,7 +653,7 @@ acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, 
         o.chunk = steps;
         o.mode = mode;
         acm_batch* b = nullptr;
-        st = acm_batch_init(cs.data(), copies, &o, stream, &b);
+        st = acm_batch_init(cs.data(), copies, &o, mem + fields_bytes, scratch_bytes - fields_bytes, stream, &b);
         if (st != ACM_OK) break;
         st = acm_batch_run(b, 1, nullptr);  // warm-up chunk
         const auto t0 = std::chrono::steady_clock::now();
@@ -571,7 +670,6 @@ acm_status autotune_shape(int nx, int ny, int precision, int copies, int steps, 
         }
     }
     (void)hipStreamSynchronize(s);
-    (void)hipFree(mem);
     return st;
 }
 }  // namespace

@@ -39,11 +39,17 @@ def test_version_string():
     assert b"gfx950" in acm.lib().acm_version()
 
 
-def _init(cfg, a=None, b=None):
+# placeholder device addresses: every call below fails validation before it
+# could launch or capture anything that reads them
+_SCRATCH = 1 << 20
+
+
+def _init(cfg, a=None, b=None, scratch=_SCRATCH, nbytes=1 << 40):
     h = ctypes.c_void_p()
     fa = a if a is not None else acm.Fields(1, 2, 3, 4, 5)
     fb = b if b is not None else acm.Fields(6, 7, 8, 9, 10)
-    return acm.lib().acm_init(ctypes.byref(cfg), ctypes.byref(fa), ctypes.byref(fb), None, None, ctypes.byref(h))
+    return acm.lib().acm_init(ctypes.byref(cfg), ctypes.byref(fa), ctypes.byref(fb), None, ctypes.c_void_p(scratch),
+                              ctypes.c_size_t(nbytes), None, ctypes.byref(h))
 
 
 @pytest.mark.parametrize("mutate,expect", [
@@ -77,12 +83,55 @@ def test_init_grid_size_limits(dims, precision, rejected):
     EINVAL.  acm_init launches nothing, so the placeholder field pointers are
     never dereferenced."""
     cfg = acm.make_config(3, *dims, nu=0.01, precision=precision, allow_unstable=True)
-    h = ctypes.c_void_p()
-    fa, fb = acm.Fields(1, 2, 3, 4, 5), acm.Fields(6, 7, 8, 9, 10)
-    st = acm.lib().acm_init(ctypes.byref(cfg), ctypes.byref(fa), ctypes.byref(fb), None, None, ctypes.byref(h))
-    if st == acm.OK:
-        acm.lib().acm_destroy(h)
-    assert (st == acm.EINVAL) == rejected, (st, acm.lib().acm_last_error())
+    assert (acm.lib().acm_scratch_bytes(ctypes.byref(cfg)) == 0) == rejected
+    if rejected:
+        assert _init(cfg) == acm.EINVAL
+        assert "scratch" not in acm.lib().acm_last_error().decode()
+    else:
+        # a grid within the limits fails only for the (deliberately) NULL scratch
+        assert _init(cfg, scratch=0) == acm.EINVAL
+        assert "scratch" in acm.lib().acm_last_error().decode()
+
+
+def _scratch_model(cfg):
+    """Bytes of the documented scratch layout: diagnostics partials (14
+    doubles per reduction workgroup of 256 nodes, at most 2048 workgroups)
+    and 14 final sums, each part rounded up to 256 bytes, plus four fields
+    for 3D two-phase runs."""
+    a = lambda x: (x + 255) // 256 * 256
+    n = cfg.nx * cfg.ny * (cfg.nz if cfg.dim == 3 else 1)
+    blocks = min(2048, max(1, -(-n // 256)))
+    total = a(8 * 14 * blocks) + a(8 * 14)
+    if cfg.two_phase and cfg.dim == 3:
+        total += a(4 * n * (8 if cfg.precision == acm.F64 else 4))
+    return total
+
+
+@pytest.mark.parametrize("cfg", [
+    acm.make_config(2, 64, 64, nu=0.01, precision="f64"),
+    acm.make_config(2, 13, 7, nu=0.01),
+    acm.make_config(3, 256, 256, 256, nu=0.001),
+    acm.make_config(3, 20, 18, 16, nu=0.05, bc=(2, 2, 2, 2, 1, 1), two_phase=True, sigma=1e-3, width=3.2,
+                    mobility=1.0),
+    acm.make_config(3, 20, 18, 16, nu=0.05, two_phase=True, sigma=1e-3, width=3.2, mobility=1.0, precision="f64"),
+], ids=["2d64-f64", "2d-ragged", "3d256", "3d-twophase-f32", "3d-twophase-f64"])
+def test_scratch_bytes_follow_the_documented_layout(cfg):
+    assert acm.lib().acm_scratch_bytes(ctypes.byref(cfg)) == _scratch_model(cfg)
+
+
+def test_init_rejects_null_short_or_misaligned_scratch():
+    cfg = acm.make_config(2, 32, 32, nu=0.02)
+    need = acm.lib().acm_scratch_bytes(ctypes.byref(cfg))
+    assert need > 0
+    assert _init(cfg, scratch=0, nbytes=need) == acm.EINVAL
+    assert "NULL" in acm.lib().acm_last_error().decode()
+    assert _init(cfg, nbytes=need - 1) == acm.EINVAL
+    assert "needs" in acm.lib().acm_last_error().decode()
+    assert _init(cfg, scratch=_SCRATCH + 128, nbytes=need) == acm.EINVAL
+    assert "aligned" in acm.lib().acm_last_error().decode()
+    bad = acm.make_config(2, 32, 32, nu=-1.0)
+    assert acm.lib().acm_scratch_bytes(ctypes.byref(bad)) == 0
+    assert acm.lib().acm_last_error()
 
 
 def test_init_rejects_missing_fields():
@@ -154,6 +203,12 @@ def test_che_stability_number_matches_capillary_wave_statement():
     assert _init(bad) == acm.EUNSTABLE
 
 
+def _batch_init(arr, n, opts, scratch=_SCRATCH, nbytes=1 << 40):
+    h = ctypes.c_void_p()
+    return acm.lib().acm_batch_init(arr, n, ctypes.byref(opts), ctypes.c_void_p(scratch), ctypes.c_size_t(nbytes),
+                                    None, ctypes.byref(h))
+
+
 def test_batch_init_rejects_bad_cases_without_touching_the_gpu():
     n = 2
     arr = (acm.BatchCase * n)()
@@ -163,22 +218,66 @@ def test_batch_init_rejects_bad_cases_without_touching_the_gpu():
         arr[i].b = acm.Fields(4, 5, 6, 0, 0)
         arr[i].nsteps = 10
         arr[i].tile = -1
-    h = ctypes.c_void_p()
     opts = acm.BatchOpts(20, 0, 0, 0.0)
     arr[1].cfg = acm.make_config(3, 8, 8, 8, nu=0.02)           # 3D case in a 2D batch
-    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(opts), None, ctypes.byref(h)) == acm.EINVAL
+    assert _batch_init(arr, n, opts) == acm.EINVAL
+    assert acm.lib().acm_batch_scratch_bytes(arr, n, ctypes.byref(opts)) == 0
     arr[1].cfg = acm.make_config(2, 16, 16, nu=0.05, precision="f64")  # mixed precision
-    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(opts), None, ctypes.byref(h)) == acm.EINVAL
+    assert _batch_init(arr, n, opts) == acm.EINVAL
     arr[1].cfg = acm.make_config(2, 16, 16, nu=0.5)              # unstable
-    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(opts), None, ctypes.byref(h)) == acm.EUNSTABLE
+    assert _batch_init(arr, n, opts) == acm.EUNSTABLE
     arr[1].cfg = acm.make_config(2, 16, 16, nu=0.05)
     arr[1].tile = 9
-    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(opts), None, ctypes.byref(h)) == acm.EINVAL
+    assert _batch_init(arr, n, opts) == acm.EINVAL
     bad = acm.BatchOpts(21, 0, 0, 0.0)
     arr[1].tile = 0
-    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(bad), None, ctypes.byref(h)) == acm.EINVAL
+    assert _batch_init(arr, n, bad) == acm.EINVAL
     bad_mode = acm.BatchOpts(20, 0, 0, 0.0, 2)                   # launch mode must be 0 or 1
-    assert acm.lib().acm_batch_init(arr, n, ctypes.byref(bad_mode), None, ctypes.byref(h)) == acm.EINVAL
+    assert _batch_init(arr, n, bad_mode) == acm.EINVAL
+    # scratch: NULL, short, misaligned
+    need = acm.lib().acm_batch_scratch_bytes(arr, n, ctypes.byref(opts))
+    assert need > 0
+    assert _batch_init(arr, n, opts, scratch=0, nbytes=need) == acm.EINVAL
+    assert _batch_init(arr, n, opts, nbytes=need - 1) == acm.EINVAL
+    assert _batch_init(arr, n, opts, scratch=_SCRATCH + 64, nbytes=need) == acm.EINVAL
+    # tile -1 on a shape nothing has tuned (or recorded) in this process
+    arr[1].tile = -1
+    arr[1].cfg = acm.make_config(2, 23, 17, nu=0.05)
+    assert _batch_init(arr, n, opts) == acm.ESTATE
+    assert "not tuned" in acm.lib().acm_last_error().decode()
+
+
+def test_batch_scratch_bytes_follow_the_documented_layout():
+    """Case records, item table (tile -1: the variant with the most tiles),
+    item count, two queue counters, active list and health pairs, each part
+    rounded up to 256 bytes."""
+    a = lambda x: (x + 255) // 256 * 256
+    tw, th = [64, 32, 64, 16, 128, 32], [4, 8, 8, 16, 4, 16]
+    shapes = [(32, 32, 0), (48, 64, 3), (256, 256, -1), (17, 9, 5)]
+    arr = (acm.BatchCase * len(shapes))()
+    items = 0
+    for i, (nx, ny, t) in enumerate(shapes):
+        arr[i].cfg = acm.make_config(2, nx, ny, nu=0.05)
+        arr[i].nsteps = 10
+        arr[i].tile = t
+        cand = range(6) if t < 0 else [t]
+        items += max(-(-nx // tw[k]) * -(-ny // th[k]) for k in cand)
+    n = len(shapes)
+    opts = acm.BatchOpts(20, 0, 0, 0.0)
+    rec = ctypes.sizeof(ctypes.c_void_p)  # record size is checked through the total below
+    got = acm.lib().acm_batch_scratch_bytes(arr, n, ctypes.byref(opts))
+    rest = a(16 * items) + 256 + 256 + a(4 * n) + a(16 * n)
+    assert got > rest and (got - rest) % 256 == 0 and (got - rest) // n >= rec
+
+
+def test_tuned_tile_record_and_query():
+    t = ctypes.c_int32()
+    assert acm.lib().acm_batch_tuned_tile(29, 31, acm.F32, 1, ctypes.byref(t)) == acm.ESTATE
+    assert acm.lib().acm_batch_set_tuned_tile(29, 31, acm.F32, 1, 4) == acm.OK
+    assert acm.lib().acm_batch_tuned_tile(29, 31, acm.F32, 1, ctypes.byref(t)) == acm.OK and t.value == 4
+    assert acm.lib().acm_batch_tuned_tile(29, 31, acm.F32, 0, ctypes.byref(t)) == acm.ESTATE
+    assert acm.lib().acm_batch_set_tuned_tile(29, 31, acm.F32, 1, 6) == acm.EINVAL
+    assert acm.lib().acm_batch_autotune_scratch_bytes(64, 64, acm.F32, 8) >= 6 * 8 * 64 * 64 * 4
 
 
 def test_fused_correction_rejects_bad_arguments_without_touching_the_gpu():

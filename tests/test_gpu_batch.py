@@ -1,6 +1,7 @@
 """Batched launch (both modes): every case must be bitwise equal to the same
 case run alone through acm_run, divergence must be isolated to its case,
 and sampled cases of the 512-case sweep must match the CPU oracle."""
+import ctypes
 import math
 
 import numpy as np
@@ -104,9 +105,9 @@ def test_batch_divergence_is_isolated(acm_mod, mode):
 def test_batch_sampled_sweep_cases_match_oracle(acm_mod, orc):
     """Cases of the seeded 512-case sweep (the four smallest of the first
     sixteen), FP32 batched run of their full step counts against the FP64
-    oracle: velocity relative L2 <= 1e-4 and drho relative L2 <= 1e-3
-    (FP32 storage over 1000-2000 steps at Re up to 5000, see the design
-    notes for the bound)."""
+    oracle at the stated FP32 bounds, velocity relative L2 <= 2e-5 and drho
+    relative L2 <= 1e-4 (FP32 storage alone costs ~2e-7 and ~3e-6 on these
+    cases, test_precision_storage.py)."""
     allc = inputs.batch_cases(ncases=16, seed=4)
     pick = sorted(allc, key=lambda c: c.n)[:4]
     cfgs, states = [], []
@@ -127,14 +128,17 @@ def test_batch_sampled_sweep_cases_match_oracle(acm_mod, orc):
         o = orc.run(orc.Params(dim=2, nx=c.n, ny=c.n, nu=c.nu, bc=bc, wall_u=wu), states[i], c.nsteps)
         num = np.sqrt(np.sum((g["u"] - o["u"]) ** 2 + (g["v"] - o["v"]) ** 2))
         den = np.sqrt(np.sum(o["u"] ** 2 + o["v"] ** 2))
-        print(f"case n={c.n} {c.kind} Re={c.re:.0f} steps={c.nsteps}: vel relL2 {num / den:.2e}")
-        assert num / den <= 1e-4
         er = np.linalg.norm(g["drho"] - o["drho"]) / np.linalg.norm(o["drho"])
-        assert er <= 1e-3
+        print(f"case n={c.n} {c.kind} Re={c.re:.0f} steps={c.nsteps}: vel relL2 {num / den:.2e} drho {er:.2e}")
+        assert num / den <= 2e-5
+        assert er <= 1e-4
     b.close()
 
 
 def test_autotune_choice_is_valid_and_result_invariant(acm_mod):
-    best, ms = acm_mod.autotune(64, "f32", copies=64, steps=40)
+    best, ms = acm_mod.autotune(64, 64, "f32", copies=64, steps=40)
     assert 0 <= best < 6 and all(m > 0 for m in ms)
     assert ms[best] == min(ms)
+    t = ctypes.c_int32()
+    assert acm_mod.lib().acm_batch_tuned_tile(64, 64, acm_mod.F32, 0, ctypes.byref(t)) == acm_mod.OK
+    assert t.value == best
