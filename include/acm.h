@@ -372,6 +372,22 @@ acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* c
                         const float* const* target, const float* out_scale, void* grad, double* workspace,
                         double* loss, void* stream);
 
+/* acm_cnn_loss without the workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training or
+ * serving loops, harnesses that forbid allocation): the per-workgroup
+ * partial sums go to a static device array of ACM_LOSS_SCRATCH_DOUBLES
+ * doubles that the library holds on each GPU it runs on until the process
+ * ends, so grids are limited to ACM_LOSS_SCRATCH_DOUBLES * 256 pixels
+ * (ACM_EINVAL beyond).  The array belongs to the device current at the call,
+ * which must be the stream's device.  The call allocates nothing; results
+ * equal acm_cnn_loss's bit for bit.  Every call on one GPU shares that
+ * GPU's array (each call writes every partial it reads, so nothing needs
+ * clearing): calls that overlap on one GPU, e.g. on two streams, race. */
+#define ACM_LOSS_SCRATCH_DOUBLES 8192
+acm_status acm_cnn_loss_noalloc(int32_t nx, int32_t ny, const float* raw, const float* const* base,
+                                const float* const* target, const float* out_scale, void* grad, double* loss,
+                                void* stream);
+
 /* Loss of a state against a target for training through several steps:
  * e_c = (q[c] - target[c]) / out_scale[c] on the channels with
  * out_scale[c] > 0; *loss (device double) += weight * mean(e^2) over pixels

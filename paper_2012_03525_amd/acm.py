@@ -122,6 +122,10 @@ SIGNATURES = {
     "acm_cnn_loss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                     ctypes.POINTER(ctypes.c_float)] + [ctypes.c_void_p] * 4),
+    "acm_cnn_loss_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     "acm_cnn_state_loss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_float),
                                           ctypes.c_float, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,

@@ -20,6 +20,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -871,6 +872,37 @@ bool pixels_ok(int nx, int ny) { return nx > 0 && ny > 0 && (int64_t)nx * ny <= 
 int blocks_for(size_t n) { return (int)((n + 255) / 256); }
 }  // namespace
 
+// Device scratch of acm_cnn_loss_noalloc: the per-workgroup partial sums of
+// the loss, one double per 256 pixels.  Each GPU holds its own copy for the
+// life of the process.  In host code `scratch` names a host-side stand-in,
+// not device memory: kernels get the address that hipGetSymbolAddress
+// returns for the current device, taken once per device.
+static __device__ __align__(256) double scratch[ACM_LOSS_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+acm_status static_scratch_ptr(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return chip(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return cfail(ACM_EINVAL, "device index out of range for the static scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return chip(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return cfail(ACM_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return ACM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 acm_status acm_cnn_layer_shape(int32_t layer, int32_t* cin, int32_t* cout)
@@ -968,11 +1000,10 @@ acm_status acm_cnn_apply(int32_t nx, int32_t ny, const float* raw, const float* 
 
 size_t acm_cnn_loss_workspace(int32_t nx, int32_t ny) { return (size_t)blocks_for((size_t)nx * ny) * sizeof(double); }
 
-acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* const* base, const float* const* target,
-                        const float* out_scale, void* grad, double* workspace, double* loss, void* stream)
+static acm_status loss_impl(int32_t nx, int32_t ny, const float* raw, const float* const* base,
+                            const float* const* target, const float* out_scale, void* grad, double* workspace,
+                            double* loss, void* stream)
 {
-    if (!raw || !base || !target || !out_scale || !grad || !workspace || !loss) return cfail(ACM_EINVAL, "NULL pointer");
-    if (!pixels_ok(nx, ny)) return cfail(ACM_EINVAL, "bad grid");
     const int n = nx * ny;
     const int nb = blocks_for(n);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -990,6 +1021,30 @@ acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* c
     if (st != ACM_OK) return st;
     hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, workspace, nb, (double)lc.nact * n, loss);
     return chip(hipGetLastError(), "loss final launch");
+}
+
+acm_status acm_cnn_loss(int32_t nx, int32_t ny, const float* raw, const float* const* base, const float* const* target,
+                        const float* out_scale, void* grad, double* workspace, double* loss, void* stream)
+{
+    if (!raw || !base || !target || !out_scale || !grad || !workspace || !loss) return cfail(ACM_EINVAL, "NULL pointer");
+    if (!pixels_ok(nx, ny)) return cfail(ACM_EINVAL, "bad grid");
+    return loss_impl(nx, ny, raw, base, target, out_scale, grad, workspace, loss, stream);
+}
+
+acm_status acm_cnn_loss_noalloc(int32_t nx, int32_t ny, const float* raw, const float* const* base,
+                                const float* const* target, const float* out_scale, void* grad, double* loss,
+                                void* stream)
+{
+    if (!raw || !base || !target || !out_scale || !grad || !loss) return cfail(ACM_EINVAL, "NULL pointer");
+    if (!pixels_ok(nx, ny)) return cfail(ACM_EINVAL, "bad grid");
+    if ((size_t)blocks_for((size_t)nx * ny) > ACM_LOSS_SCRATCH_DOUBLES)
+        return cfail(ACM_EINVAL, "grid of " + std::to_string((long long)nx * ny) +
+                                     " pixels exceeds the static scratch (at most " +
+                                     std::to_string((long long)ACM_LOSS_SCRATCH_DOUBLES * 256) + " pixels)");
+    double* ws = nullptr;
+    const acm_status st = static_scratch_ptr(&ws);
+    if (st != ACM_OK) return st;
+    return loss_impl(nx, ny, raw, base, target, out_scale, grad, ws, loss, stream);
 }
 
 acm_status acm_cnn_state_loss(int32_t nx, int32_t ny, const float* const* q, const float* const* target,
