@@ -298,15 +298,22 @@ def main():
     if a.copy_only:
         print(json.dumps({"copy": copy_bandwidth(a.copy_mib)}), flush=True)
         return
-    copy = copy_bandwidth(1024)
-    print(f"[bench] plain copy kernel: {copy['gbs']} GB/s", file=sys.stderr, flush=True)
     if a.workload == "batch512":
+        copy = copy_bandwidth(1024)
+        print(f"[bench] plain copy kernel: {copy['gbs']} GB/s", file=sys.stderr, flush=True)
         run_batch(a, copy)
         return
     chunk = graph_chunk_for(a.steps)
     cfg, st, meta, bpl, kname = workload(a.workload, a.tile, chunk)
     solver = acm.Solver(cfg, st)
     nodes = cfg.nx * cfg.ny * (cfg.nz if cfg.dim == 3 else 1)
+    # The copy-bandwidth calibration runs right before the warm-up steps: a
+    # chip coming out of idle (state upload, graph capture) runs its first
+    # ~200 launches of the step 10-30 % slower while its clocks settle, and
+    # about 0.1 s of sustained HBM traffic brings it to the state the step
+    # then runs in, for the copy ceiling and the step alike.
+    copy = copy_bandwidth(1024, reps=250)
+    print(f"[bench] plain copy kernel: {copy['gbs']} GB/s", file=sys.stderr, flush=True)
     print(f"[bench] {meta['workload']}: warmup {a.warmup}", file=sys.stderr, flush=True)
     solver.run(a.warmup)
     torch.cuda.synchronize()

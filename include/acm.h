@@ -95,7 +95,13 @@ typedef struct acm_config {
                                (else as 2); 14 (FP32) 64x8, 15 32x8: two
                                steps per launch on fully periodic grids with
                                rho0 = 1 (acm_run; each run ends with one
-                               one-step launch), else the default; 0: 13 with 64-plane chunks,
+                               one-step launch), else the default; 16, 17,
+                               19: whole x rows per wave in bands of 4, 6, 2
+                               rows (FP32 fully periodic grids with rho0 = 1,
+                               nx 64, 128 or 256, ny >= band + 4; else the
+                               default); 0: the whole-row kernel with 4-row
+                               bands where it applies (chunk chosen for the
+                               CU count), else 13 with 64-plane chunks,
                                or a smaller shape and chunk when that gives
                                fewer than two workgroups per CU (FP64 accepts
                                3, 4, else 32x8); bits 8+ = z chunk / 16 (0:

@@ -163,6 +163,15 @@ bool step3d_pair_ok(const Coef<T>& c, int tile);
 template <typename T>
 hipError_t launch_step3d_pair(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
                               hipStream_t s);
+// 3D step with whole x rows per wave (kern_step3d_rows.hip): FP32 fully
+// periodic boxes with rho0 = 1 and nx in {64, 128, 256}; shape 16..19
+// selects the band height, zc the planes per chunk.  step3d_rows_ok says
+// whether the configuration allows it.
+template <typename T>
+bool step3d_rows_ok(const Coef<T>& c);
+template <typename T>
+hipError_t launch_step3d_rows(const Coef<T>& c, const State<T>& in, const State<T>& out, int shape, int zc,
+                              hipStream_t s);
 template <typename T>
 hipError_t launch_twophase2d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile,
                              hipStream_t s);

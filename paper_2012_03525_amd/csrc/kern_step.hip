@@ -507,15 +507,52 @@ static int small_grid_tile(int nx, int ny, int nz, bool fp64)
     return 0;
 }
 
+// Chunk length of the default whole-row launch (6-wave, 4-row bands): the
+// march of a chunk of zc planes costs about zc + 4 plane iterations (two
+// planes of lead-in and the halo planes), and the launch takes
+// ceil(workgroups / CUs) such rounds; the chunk with the fewest plane
+// iterations in total wins (64 on 256^3: 256 workgroups, one per CU).
+static int rows_default_chunk(int ny, int nz)
+{
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+    }
+    static const int cand[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
+    const long nby = (ny + 3) / 4;
+    int best = 64;
+    long best_cost = -1;
+    for (int zc : cand) {
+        if (zc > nz && zc != cand[0]) break;
+        const long nb = nby * ((nz + zc - 1) / zc);
+        const long cost = ((nb + ncu - 1) / ncu) * (long)(std::min(zc, nz) + 4);
+        if (best_cost < 0 || cost < best_cost) best_cost = cost, best = zc;
+    }
+    return best;
+}
+
 // tile codes (3D): low byte = in-plane shape, upper bits = z chunk / 16
 template <typename T>
 hipError_t launch_step3d(const Coef<T>& c, const State<T>& in, const State<T>& out, int tile, hipStream_t s)
 {
+    if (tile == 0 && step3d_rows_ok(c) && c.ny >= 8) {
+        // whole x rows per wave: the fastest shape where it applies
+        const hipError_t e = launch_step3d_rows<T>(c, in, out, 16, rows_default_chunk(c.ny, c.nz), s);
+        if (e != hipErrorInvalidValue) return e;
+    }
     if (tile == 0) tile = small_grid_tile(c.nx, c.ny, c.nz, sizeof(T) == 8);
     int zc = (tile >> 8) * 16;
     if (zc <= 0) zc = 64;
     if (zc > c.nz) zc = c.nz;
     int shape = tile & 0xff;
+    if ((shape == 16 || shape == 17 || shape == 19) && step3d_rows_ok(c)) {
+        const hipError_t e = launch_step3d_rows<T>(c, in, out, shape, zc, s);
+        if (e != hipErrorInvalidValue) return e;
+        shape = 0;  // grid too small for the band height: the default shape
+    }
     if constexpr (sizeof(T) == 8) {
         // FP64 keeps one row per thread and moderate tiles (LDS and registers)
         switch (shape) {

@@ -18,20 +18,27 @@ __device__ __forceinline__ T mom3(T r, T u, T rho0)
     else return fmaT(r, u, u);
 }
 
-// drho' at R-index e of plane slot (cur), with the planes below / above.
+// drho' of one node (Eq. 2.10) from drho at the node and its six
+// neighbours and the momentum component of each neighbour along its axis:
+// (u, drho) east / west, (v, drho) north / south, (w, drho) up / down.
 // The momentum differences use the split form of mdiff (tile2d.h).
+template <bool GEN, typename T>
+__device__ __forceinline__ T rho_new_pt(const Coef<T>& c, T rc, T rE, T uE, T rW, T uW, T rN, T vN, T rS, T vS,
+                                        T rUp, T wUp, T rDn, T wDn)
+{
+    const T rho0 = GEN ? c.rho0 : T(1);
+    const T div = (mdiff(rE, uE, rW, uW, rho0) + mdiff(rN, vN, rS, vS, rho0)) + mdiff(rUp, wUp, rDn, wDn, rho0);
+    const T lap = (((rE + rW) + (rN + rS)) + (rUp + rDn)) - T(6) * rc;
+    return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
+}
+
+// drho' at R-index e of plane slot (cur), with the planes below / above.
 template <bool GEN, typename T, int RX>
 __device__ __forceinline__ T rho_new_3d(const Coef<T>& c, const T* r0, const T* u0, const T* v0,
                                         const T* rD, const T* wD, const T* rU, const T* wU, int e)
 {
-    const T rc = r0[e];
-    const T rE = r0[e + 1], rW = r0[e - 1], rN = r0[e + RX], rS = r0[e - RX];
-    const T rUp = rU[e], rDn = rD[e];
-    const T rho0 = GEN ? c.rho0 : T(1);
-    const T div = (mdiff(rE, u0[e + 1], rW, u0[e - 1], rho0) + mdiff(rN, v0[e + RX], rS, v0[e - RX], rho0)) +
-                  mdiff(rUp, wU[e], rDn, wD[e], rho0);
-    const T lap = (((rE + rW) + (rN + rS)) + (rUp + rDn)) - T(6) * rc;
-    return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
+    return rho_new_pt<GEN, T>(c, r0[e], r0[e + 1], u0[e + 1], r0[e - 1], u0[e - 1], r0[e + RX], v0[e + RX],
+                              r0[e - RX], v0[e - RX], rU[e], wU[e], rD[e], wD[e]);
 }
 
 // Buffer-resource access for the z-march: 32-bit lane byte offsets within a

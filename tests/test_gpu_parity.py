@@ -190,14 +190,14 @@ def tgv3d_64_oracle_1000(orc):
     return st, nu, orc.run(orc.Params(dim=3, nx=n, ny=n, nz=n, nu=nu), st, 1000)
 
 
-@pytest.mark.parametrize("tile", [0, 13 | (4 << 8), 13 | (1 << 8)],
-                         ids=["default", "tile13-chunk64", "tile13-chunk16"])
+@pytest.mark.parametrize("tile", [0, 13 | (4 << 8), 13 | (1 << 8), 16 | (2 << 8), 17 | (1 << 8)],
+                         ids=["default", "tile13-chunk64", "tile13-chunk16", "rows4-chunk32", "rows6-chunk16"])
 def test_tgv3d_fp32_parity_64_1000_steps(acm_mod, tgv3d_64_oracle_1000, tile):
     """The stated FP32 bounds after 1000 steps (u <= 2e-5, drho <= 1e-4
     relative L2) for the 3D Taylor-Green case at 64^3: the default launch
-    shape for this grid, and the benchmark's periodic fast path (64 x 8
+    shape for this grid, the periodic fast path of the column kernel (64 x 8
     tile, two rows per thread, three-plane LDS ring) forced with 64- and
-    16-plane z chunks."""
+    16-plane z chunks, and the whole-row kernel with 4- and 6-row bands."""
     n = 64
     st, nu, o = tgv3d_64_oracle_1000
     cfg = acm_mod.make_config(3, n, n, n, nu=nu, precision="f32", tile=tile, graph_chunk=100)
