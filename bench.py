@@ -89,7 +89,7 @@ def workload(name, tile, chunk=100):
         meta = {"workload": "3D periodic Taylor-Green vortex 256^3, FP32 drho storage",
                 "grid": [n, n, n], "u0": u0, "Re": 1600, "nu_lattice": nu, "steps_of_case": 2000}
         bytes_per_lup = 32  # read drho,u,v,w + write drho,u,v,w (FP32)
-        kernel = "step3d_kernel"
+        kernel = "step3d_rows_kernel"
     elif name == "tgv2d_64":
         n = 64
         cfg = acm.make_config(2, n, n, nu=0.01, precision="f64", tile=tile, graph_chunk=chunk)

@@ -121,11 +121,19 @@ static void fill_scalar(const orc_params* p, const pgrid* g, double* f)
 /* Ghost order parameter across a wall face (Sec. 2 wetting condition):
  * (phi_m - phi_g)/dx = -(2/W) cos(theta) (1 - phi_w^2), phi_w = (phi_g + phi_m)/2.
  * With b = dx (2/W) cos(theta) and s = phi_w this is b s^2 + 2 s - (2 phi_m + b) = 0,
- * whose root that tends to phi_m as b -> 0 is s = (2 phi_m + b) / (1 + sqrt(1 + b (2 phi_m + b))). */
+ * whose root that tends to phi_m as b -> 0 is s = (2 phi_m + b) / (1 + sqrt(1 + b (2 phi_m + b))),
+ * and phi_g = 2 s - phi_m = phi_m + 2 (s - phi_m).
+ * The factor 1 - phi_w^2 is built on the bulk values +-1: the offset s - phi_m
+ * is taken at phi_m clamped to [-1, 1] (it vanishes at +-1), so the ghost of a
+ * value beyond +-1 is its mirror, b = 0 mirrors every value, and the root
+ * stays real for |b| <= 1 (W >= 2 dx) where an overshoot of phi past 1 next to
+ * a wall with cos(theta) near -1 would otherwise leave the quadratic without
+ * a real root. */
 static double wet_ghost(double m, double b)
 {
-    double s = (2.0 * m + b) / (1.0 + sqrt(1.0 + b * (2.0 * m + b)));
-    return 2.0 * s - m;
+    double mc = m > 1.0 ? 1.0 : (m < -1.0 ? -1.0 : m);
+    double s = (2.0 * mc + b) / (1.0 + sqrt(1.0 + b * (2.0 * mc + b)));
+    return m + 2.0 * (s - mc);
 }
 
 /* Fill the ghost layer of the order parameter: periodic wrap or mirror,

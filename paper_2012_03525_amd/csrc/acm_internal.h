@@ -104,12 +104,17 @@ __device__ __forceinline__ double recipT(double x) { return 1.0 / x; }
 // the value at the halfway wall.  With b = dx (2/W) cos(theta) the wall value
 // solves b s^2 + 2 s - (2 phi_m + b) = 0; the root that tends to phi_m as
 // b -> 0 is taken in the cancellation-free form below; b = 0 gives phi_m.
+// The ghost is phi_m + 2 (s - phi_m) with the offset s - phi_m taken at phi_m
+// clamped to the bulk values [-1, 1] (the offset vanishes there): a value
+// beyond +-1 is mirrored, b = 0 mirrors every value, and the root stays real
+// for |b| <= 1 when phi overshoots 1 next to a wall with cos(theta) near -1.
 template <typename T>
 __device__ __forceinline__ T wet_ghost(T m, T b)
 {
-    const T q = fmaT(T(2), m, b);
+    const T mc = fmin(fmax(m, T(-1)), T(1));
+    const T q = fmaT(T(2), mc, b);
     const T s = q / (T(1) + sqrt(fmaT(b, q, T(1))));
-    return fmaT(T(2), s, -m);
+    return fmaT(T(2), s - mc, m);
 }
 
 // wb of the crossed face f (per-lane value: selected, not indexed)

@@ -423,6 +423,48 @@ def test_twophase_3d_fp32(acm_mod, orc):
     assert rel_l2(g["drho"], o["drho"]) <= 1e-3
 
 
+def jumping_case(acm, NL, precision):
+    """The coalescence geometry of Sec. 3.7 at NL nodes per drop radius: the
+    quarter domain [0, 3] x [0, 3] x [0, 5] R with symmetry planes at the
+    four sides (the plane x = 0 mirrors the drop into its coalescing
+    partner), a non-wetting wall (contact angle 180 degrees) at z = 0 and a
+    wall at z = 5R; one drop of radius R centred at (R, 0, R).  Lattice
+    parameters: capillary-inertial speed 1/40, Oh = 0.119, W = 3, Pe = 2000
+    (the Sec. 3.7 values c = 10, Cn = 0.1, Pe = 8000 leave the run unstable
+    at this resolution)."""
+    U = 1.0 / 40
+    sigma = NL * U * U
+    nu = 0.119 * U * NL
+    M = U * NL * NL / (2000.0 * sigma)
+    wet = [0.0] * 6
+    wet[4] = -1.0
+    cfg = acm.make_config(3, 3 * NL, 3 * NL, 5 * NL, nu=nu, precision=precision, bc=(2, 2, 2, 2, 1, 1),
+                          two_phase=True, sigma=sigma, width=3.0, mobility=M, wet_cos=wet)
+    st = inputs.drop_on_wall_3d(3 * NL, 3 * NL, 5 * NL, float(NL), 3.0, center=(float(NL), 0.0, float(NL)))
+    return cfg, st
+
+
+def test_twophase_3d_nonwetting_coalescence_fp64(acm_mod, orc):
+    """Sec. 3.7 geometry at 10 nodes per radius (30 x 30 x 50), contact angle
+    180 degrees, 150 steps: FP64 against the oracle at 1e-12 (the wall value
+    of the wetting condition with the mirror value clamped to +-1 on both
+    sides)."""
+    cfg, st = jumping_case(acm_mod, 10, "f64")
+    g, o = run_both(acm_mod, orc, cfg, st, 150)
+    for k in ("drho", "u", "v", "w", "phi"):
+        assert rel_l2(g[k], o[k]) <= 1e-12, (k, rel_l2(g[k], o[k]))
+    assert np.abs(o["w"]).max() > 1e-4  # the drops are moving
+
+
+def test_twophase_3d_nonwetting_coalescence_fp32(acm_mod, orc):
+    cfg, st = jumping_case(acm_mod, 10, "f32")
+    st = to_f32(st)
+    g, o = run_both(acm_mod, orc, cfg, st, 150)
+    assert rel_l2(g["phi"], o["phi"]) <= 1e-5
+    assert rel_l2_vec(g, o, ("u", "v", "w")) <= 1e-4
+    assert rel_l2(g["drho"], o["drho"]) <= 1e-3
+
+
 def test_twophase_3d_full_size_one_step(acm_mod, orc):
     """96^3 drop spreading (N_L = 32, Cn = 0.1, the bench workload), FP32:
     one step node by node against the oracle."""
