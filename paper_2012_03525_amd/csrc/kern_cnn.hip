@@ -1,5 +1,5 @@
 // Learned-closure network on gfx950: per-layer 3x3 convolutions as implicit
-// GEMMs on the bf16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32
+// GEMMs on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
 // accumulation) for training, the weight gradient as an MFMA reduction over
 // pixels, a one-launch whole-network inference kernel (16x16x32 bf16 MFMA,
 // all layers of a tile in LDS) for the closure run, and the element-wise
@@ -12,9 +12,12 @@
 //   weights      bf16 [9][C_out][C_in], tap t = (dy+1)*3 + (dx+1)
 //   bias, grads  fp32
 // Convolution: y[p][o] = b[o] + sum_{t,i} w[t][o][i] x[p + off(t)][i] with
-// circular (periodic) wrap.  MFMA operand mapping (16x16x16): A[i][k] in lane
-// i + 16*(k/4), element k%4; B[k][n] in lane n + 16*(k/4); D[i][n] in lane
-// n + 16*(i/4), element i%4.  Here i = pixel (forward) and k, n = channels.
+// circular (periodic) wrap.  MFMA operand mapping: v_mfma_f32_16x16x32_bf16
+// has A[i][k] in lane i + 16*(k/8), element k%8, and B[k][n] in lane
+// n + 16*(k/8); v_mfma_f32_16x16x16_bf16 (used where K is only 16) has
+// A[i][k] in lane i + 16*(k/4), element k%4, and B[k][n] in lane
+// n + 16*(k/4); both give D[i][n] in lane n + 16*(i/4), element i%4.  Both
+// issue at the same rate, so K = 32 halves the instruction count.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -23,6 +26,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 
 #include "../../include/acm.h"
 #include "acm_internal.h"
@@ -31,6 +35,8 @@
 namespace acm {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16_t;
 
@@ -60,28 +66,49 @@ enum : int { CONV_RELU = 0, CONV_RAW = 1, CONV_MASK = 2 };
 //       CONV_RAW    y = fp32(conv + b)
 //       CONV_MASK   y = bf16(conv * (mask > 0))   (data gradient through ReLU)
 // ---------------------------------------------------------------------------
+// Operands of the K = 32 (CIN a multiple of 32) or K = 16 (CIN = 16) product:
+// KW channels per lane, lane group lg holding channels KW lg .. KW lg + KW - 1
+// of a block of 4 KW.
+template <int CIN>
+struct ConvK {
+    static constexpr int KW = CIN % 32 == 0 ? 8 : 4;  // channels per lane
+    static constexpr int KB = 4 * KW;                 // channels per product
+    static constexpr int KS = CIN / KB;               // products per tap
+    typedef typename std::conditional<KW == 8, bf16x8s, bf16x4>::type op;
+    static __device__ __forceinline__ f32x4 mfma(const op& a, const op& b, const f32x4& c)
+    {
+        if constexpr (KW == 8)
+            return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, a),
+                                                           __builtin_bit_cast(bf16x8v, b), c, 0, 0, 0);
+        else
+            return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+};
+
 template <int CIN, int COUT, int MODE, int TR = 4>
 __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t* __restrict__ x,
                                                       const bf16_t* __restrict__ w, const float* __restrict__ bias,
                                                       const bf16_t* __restrict__ mask, void* __restrict__ y)
 {
+    using K = ConvK<CIN>;
+    using op = typename K::op;
     constexpr int TC = 32, IR = TR + 2, IC = TC + 2;
-    constexpr int KS = CIN / 16, NH = COUT / 16, CH4 = CIN / 4;
+    constexpr int KS = K::KS, KB = K::KB, KW = K::KW, NH = COUT / 16, CH4 = CIN / 4;
     constexpr int NG = TR / 2;  // 16-pixel groups per wave
     __shared__ __align__(16) bf16_t sx[IR * IC * CIN];
     const int tiles_x = W / TC;
     const int x0 = (blockIdx.x % tiles_x) * TC, y0 = (blockIdx.x / tiles_x) * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lg = lane >> 4;
-    bf16x4 bw[9][KS][NH];
+    op bw[9][KS][NH];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int nh = 0; nh < NH; ++nh)
-                bw[t][ks][nh] = *reinterpret_cast<const bf16x4*>(w + ((size_t)(t * COUT + nh * 16 + l16) * CIN +
-                                                                      ks * 16 + lg * 4));
+                bw[t][ks][nh] = *reinterpret_cast<const op*>(w + ((size_t)(t * COUT + nh * 16 + l16) * CIN +
+                                                                 ks * KB + lg * KW));
     {
         constexpr int TOT = IR * IC * CH4;
         constexpr int NIT = (TOT + 255) / 256;
@@ -114,18 +141,17 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t
         const int dy = t / 3 - 1, dx = t % 3 - 1;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            bf16x4 a[NG];
+            op a[NG];
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                 const int r = (TR / 4) * wave + (g >> 1), c0 = (g & 1) * 16;
                 const int pix = (r + 1 + dy) * IC + (c0 + l16 + 1 + dx);
-                a[g] = *reinterpret_cast<const bf16x4*>(sx + pix * CIN + ks * 16 + lg * 4);
+                a[g] = *reinterpret_cast<const op*>(sx + pix * CIN + ks * KB + lg * KW);
             }
 #pragma unroll
             for (int g = 0; g < NG; ++g)
 #pragma unroll
-                for (int nh = 0; nh < NH; ++nh)
-                    acc[g][nh] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g], bw[t][ks][nh], acc[g][nh], 0, 0, 0);
+                for (int nh = 0; nh < NH; ++nh) acc[g][nh] = K::mfma(a[g], bw[t][ks][nh], acc[g][nh]);
         }
     }
 #pragma unroll
@@ -158,10 +184,13 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const bf16_t
 // ---------------------------------------------------------------------------
 // weight gradient: dW[t][o][i] = sum_p g[p][o] x[p + off(t)][i], db[o] = sum_p g[p][o]
 // Workgroup tile 4 rows x 64 columns; x (with halo) and g are staged in LDS
-// channel-major so that four consecutive pixels of one channel are one
-// MFMA operand.  Each wave owns a quarter of the (tap, o-block, i-block)
-// 16x16 output tiles and accumulates over the tile's pixels; the partial
-// sums of every workgroup go to a workspace reduced in a fixed order.
+// channel-major so that eight consecutive pixels of one channel are one
+// operand of a K = 32 product over pixels.  The 16x16 output tiles
+// (tap, o-block, i-block) are dealt to the waves by tap row: a wave owns the
+// three taps dx = -1, 0, 1 of a (dy, o-block, i-block), whose x operands are
+// the same 10 halfwords of a channel row shifted by 0, 1 and 2, so one
+// 16-byte and one 4-byte load serve all three.  The partial sums of every
+// workgroup go to a workspace reduced in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int WG_TR = 4, WG_TC = 64;
 
@@ -169,9 +198,11 @@ template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void conv_wgrad_kernel(int H, int W, const bf16_t* __restrict__ x,
                                                          const bf16_t* __restrict__ g, float* __restrict__ partial)
 {
-    constexpr int XR = WG_TR + 2, XC = WG_TC + 4;  // columns x0-1 .. x0+64 (+1 pad), 8-byte aligned rows
+    // channel rows of x: columns x0-1 .. x0+64 and padding; of g: columns x0 .. x0+63
+    // and padding (row strides of 144 bytes)
+    constexpr int XR = WG_TR + 2, XC = WG_TC + 8, GC = WG_TC + 8;
     __shared__ __align__(16) bf16_t sxT[XR][CIN][XC];
-    __shared__ __align__(16) bf16_t sgT[WG_TR][COUT][WG_TC];
+    __shared__ __align__(16) bf16_t sgT[WG_TR][COUT][GC];
     const int tiles_x = W / WG_TC;
     const int x0 = (blockIdx.x % tiles_x) * WG_TC, y0 = (blockIdx.x / tiles_x) * WG_TR;
     for (int q = threadIdx.x; q < XR * (WG_TC + 2) * CIN; q += 256) {
@@ -189,33 +220,37 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(int H, int W, const bf1
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lg = lane >> 4;
     constexpr int OB = COUT / 16, IB = CIN / 16;
-    constexpr int NTILE = 9 * OB * IB;
-    constexpr int PER = (NTILE + 3) / 4;
-    f32x4 acc[PER];
+    constexpr int NTRI = 3 * OB * IB;      // (dy, o-block, i-block) triples
+    constexpr int PER = (NTRI + 3) / 4;    // triples per wave
+    f32x4 acc[PER][3];
 #pragma unroll
-    for (int s = 0; s < PER; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < PER; ++s)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) acc[s][dx] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int r = 0; r < WG_TR; ++r) {
 #pragma unroll 1
-        for (int kc = 0; kc < WG_TC / 16; ++kc) {
+        for (int kc = 0; kc < WG_TC / 32; ++kc) {
+            const int c0 = kc * 32 + 8 * lg;  // this lane's eight pixels: columns c0 .. c0 + 7
 #pragma unroll
             for (int s = 0; s < PER; ++s) {
-                const int t = wave + 4 * s;
-                if (t < NTILE) {
-                    const int tap = t / (OB * IB), rem = t % (OB * IB);
+                const int tr = wave + 4 * s;
+                if (tr < NTRI) {
+                    const int dy = tr / (OB * IB) - 1, rem = tr % (OB * IB);
                     const int ob = rem / IB, ib = rem % IB;
-                    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
                     // A[i = o][k = pixel]
-                    const bf16x4 a =
-                        *reinterpret_cast<const bf16x4*>(&sgT[r][ob * 16 + l16][kc * 16 + lg * 4]);
-                    // B[k = pixel][n = i]: x at (row r + dy, column + dx); unaligned, read element-wise
-                    const bf16_t* src = &sxT[r + 1 + dy][ib * 16 + l16][kc * 16 + lg * 4 + 1 + dx];
-                    bf16x4 b;
-                    b[0] = (short)src[0];
-                    b[1] = (short)src[1];
-                    b[2] = (short)src[2];
-                    b[3] = (short)src[3];
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s], 0, 0, 0);
+                    const bf16x8v a = *reinterpret_cast<const bf16x8v*>(&sgT[r][ob * 16 + l16][c0]);
+                    // B[k = pixel][n = i] for dx = -1, 0, 1: x columns c0 + dx .. c0 + dx + 7,
+                    // i.e. halfwords 0..7, 1..8 and 2..9 of the row from column c0 - 1
+                    const bf16_t* row = &sxT[r + 1 + dy][ib * 16 + l16][c0];
+                    const uint4 lo = *reinterpret_cast<const uint4*>(row);
+                    const unsigned hi = *reinterpret_cast<const unsigned*>(row + 8);
+                    const uint4 mid = {__builtin_amdgcn_alignbyte(lo.y, lo.x, 2), __builtin_amdgcn_alignbyte(lo.z, lo.y, 2),
+                                       __builtin_amdgcn_alignbyte(lo.w, lo.z, 2), __builtin_amdgcn_alignbyte(hi, lo.w, 2)};
+                    const uint4 up = {lo.y, lo.z, lo.w, hi};
+                    acc[s][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8v, lo), acc[s][0], 0, 0, 0);
+                    acc[s][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8v, mid), acc[s][1], 0, 0, 0);
+                    acc[s][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8v, up), acc[s][2], 0, 0, 0);
                 }
             }
         }
@@ -223,14 +258,18 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(int H, int W, const bf1
     float* part = partial + (size_t)blockIdx.x * (9 * COUT * CIN + COUT);
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
-        const int t = wave + 4 * s;
-        if (t < NTILE) {
-            const int tap = t / (OB * IB), rem = t % (OB * IB);
+        const int tr = wave + 4 * s;
+        if (tr < NTRI) {
+            const int dyi = tr / (OB * IB), rem = tr % (OB * IB);
             const int ob = rem / IB, ib = rem % IB;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int o = ob * 16 + 4 * lg + j, i = ib * 16 + l16;
-                part[((size_t)tap * COUT + o) * CIN + i] = acc[s][j];
+            for (int dx = 0; dx < 3; ++dx) {
+                const int tap = 3 * dyi + dx;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int o = ob * 16 + 4 * lg + j, i = ib * 16 + l16;
+                    part[((size_t)tap * COUT + o) * CIN + i] = acc[s][dx][j];
+                }
             }
         }
     }
@@ -532,34 +571,53 @@ hipError_t conv_dispatch(int H, int W, int cin, int cout, int mode, const void* 
 //   q_out = q_in + D f(N q_in).
 // Layer l (0..4) is evaluated on the tile grown by 4 - l nodes on every side,
 // so the five-node receptive field is covered without exchanging data between
-// workgroups (the ring is recomputed by the neighbours: 1.6x the tile's own
-// work).  Weights of every layer and two activation buffers live in LDS.
+// workgroups (the ring is recomputed by the neighbours).  Weights of every
+// layer and two activation buffers live in LDS.
 // The MFMA roles are transposed with respect to conv3x3_kernel: A = weights
 // (16 output channels x 32 inputs), B = activations (32 inputs x 16 pixels),
 // so each lane's accumulator holds four consecutive output channels of one
 // pixel and is written back as one 8-byte LDS store.  v_mfma_f32_16x16x32_bf16
 // pairs element e of lane (i, g) in A with element e of lane (n, g) in B, so
 // loading A and B with the same k order gives the product for any layout of
-// k inside a lane.  The first layer is one im2col product with K = 27
-// (9 taps x 3 channels, zero-padded to 32) instead of nine K = 16 products.
+// k inside a lane.  The first layer is an im2col product: taps 0..7 with
+// their 3 channels and a zero pad make K = 32, tap 8 a K = 16 product,
+// instead of nine K = 16 products.
+//
+// LDS layout.  Every activation buffer has the row pitch of layer 0's output
+// (P = 24 slots of 32 channels, 64 bytes): layer l's output position (y, x)
+// is slot q = 24 y + x, and its input for tap (dy, dx) is slot q + 25 + 24 dy
+// + dx of the previous buffer, so a group of 16 consecutive slots reads 16
+// consecutive slots for every tap.  Layer l >= 1 computes whole pitch rows,
+// the columns past its width included (their values are never read by a
+// column inside the width: 1.17x the MFMA work of layers 1..4 in exchange for
+// reads without row breaks).  The four 16-byte chunks of a 64-byte row
+// (slot, or weight row) are stored in the order c ^ ((row >> 1) & 3): on
+// gfx950 sixteen lanes reading chunk lg of 16 consecutive rows then hit
+// distinct banks (measured: 4.7 cycles per ds_read_b128 per CU against 8.3
+// unswizzled, and 12 with a row break inside the group).
 // ---------------------------------------------------------------------------
 namespace fused {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 constexpr int T = 16;                     // output tile side
 constexpr int NT = 512;                   // threads per workgroup
 constexpr int NW = NT / 64;               // waves
-constexpr int AS = 40;                    // activation pixel stride (halfwords): 32 channels + 8, 16-byte aligned
+constexpr int P = T + 8;                  // slot pitch of every activation buffer (layer 0's output side, 24)
 constexpr int SI = T + 10;                // staged input side (26)
-constexpr int S0 = T + 8, S1 = T + 6;     // output sides of layers 0 and 1 (24, 22); then 20, 18, 16
-constexpr int W0 = 32 * 32;               // layer 0 as im2col: [o][k], k = 3 t + c
+constexpr int SLOT = 32;                  // halfwords per slot (32 channels)
+constexpr int W0A = 32 * 32;              // layer 0, taps 0..7 as im2col: [o][k], k = 4 t + c
+constexpr int W0 = W0A + 32 * 4;          // then tap 8: [o][c]
 constexpr int WL = 9 * 32 * 32;           // layers 1..3: [t][o][i]
 constexpr int W4 = 9 * 16 * 32;           // layer 4: [t][o][i]
 constexpr int OW1 = W0, OW2 = OW1 + WL, OW3 = OW2 + WL, OW4 = OW3 + WL, WTOT = OW4 + W4;
-constexpr int BA = S0 * S0 * AS;          // outputs of layers 0 and 2
-constexpr int BB = S1 * S1 * AS;          // outputs of layers 1 and 3; the staged input before them
-constexpr int LDS_HALF = WTOT + BA + BB;  // 151,360 bytes
+constexpr int PAD = 16;                   // slots past a buffer's last row, read by the last columns only
+constexpr int BA = (P * P + PAD) * SLOT;        // outputs of layers 0 and 2
+constexpr int BB = ((P - 2) * P + PAD) * SLOT;  // outputs of layers 1 and 3; the staged input before them
+constexpr int LDS_HALF = WTOT + BA + BB;
+constexpr int NBIAS = 4 * 32 + 16;        // biases of the five layers, in order
 static_assert(SI * SI * 4 <= BB, "input fits in buffer B");
-static_assert(WTOT % 8 == 0 && BA % 8 == 0, "16-byte aligned buffers");
+// 256-byte aligned buffers: the bank pattern of a swizzled row depends on the address modulo 256
+static_assert(OW1 % 128 == 0 && WTOT % 128 == 0 && BA % 128 == 0, "256-byte aligned buffers");
 
 struct Args {
     const float* qi[3];  // state after the coarse step (read only)
@@ -569,96 +627,143 @@ struct Args {
     const float* b[ACM_CNN_LAYERS];
 };
 
+// halfword offset of 16-byte chunk c (channels 8 c .. 8 c + 7) of 64-byte row r
+__device__ __forceinline__ int chunk_at(int r, int c) { return r * SLOT + 8 * (c ^ ((r >> 1) & 3)); }
+
 __device__ __forceinline__ bf16x8 lds8(const bf16_t* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
 __device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) { return uint2{f2bf2(a, b), f2bf2(c, d)}; }
 
-// One 32-input-channel layer: output side SO (input side SO + 2), NH blocks
-// of 16 output channels.  RELU: bias + ReLU into `out`; otherwise the lanes
-// holding channels 0..3 of the last layer apply the correction.
-template <int SO, int NH, bool LAST>
-__device__ __forceinline__ void layer32(const bf16_t* __restrict__ wl, const float* __restrict__ bias,
-                                        const bf16_t* __restrict__ in, bf16_t* __restrict__ out, const Args& a,
-                                        int gx0, int gy0, int H, int W, const float* sq = nullptr)
+// bf16(relu(x)) of four values: rounding keeps the sign, so the ReLU is
+// taken after the conversion, as a signed 16-bit maximum with 0 on each
+// half (a negative value or -0 has its top bit set).  Equal to converting
+// relu(x) for every value but NaN.
+__device__ __forceinline__ unsigned relu2(float a, float b)
 {
-    constexpr int SN = SO + 2, NP = SO * SO, NG = (NP + 15) / 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int l16 = lane & 15, lg = lane >> 4;
-    bf16x8 wa[9][NH];
+    const s16x2 h = __builtin_bit_cast(s16x2, f2bf2(a, b));
+    return __builtin_bit_cast(unsigned, __builtin_elementwise_max(h, s16x2{0, 0}));
+}
+__device__ __forceinline__ uint2 relu4(const f32x4& v) { return uint2{relu2(v[0], v[1]), relu2(v[2], v[3])}; }
+
+// Offset (halfwords) of the 8-byte store of output channels 16 nh + 4 lg ..
+// + 3 of slot l16 (a group starts at a multiple of 16 slots, which leaves
+// (slot >> 1) & 3 unchanged).
+__device__ __forceinline__ int store_off(int l16, int lg, int nh)
+{
+    return chunk_at(l16, 2 * nh + (lg >> 1)) + 4 * (lg & 1);
+}
+
+// Weights of a 32-input-channel layer with NH blocks of 16 output channels
+// as MFMA A operands: wa[t][nh] holds output channel 16 nh + l16, inputs
+// 8 lg .. 8 lg + 7 of tap t.
+template <int NH>
+__device__ __forceinline__ void load_weights(const bf16_t* wl, bf16x8 (&wa)[9][NH])
+{
+    const int lane = threadIdx.x & 63, l16 = lane & 15, lg = lane >> 4;
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int nh = 0; nh < NH; ++nh) wa[t][nh] = lds8(wl + ((t * NH * 16 + nh * 16 + l16) * 32 + 8 * lg));
-    float bb[NH][4];
-#pragma unroll
-    for (int nh = 0; nh < NH; ++nh)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bb[nh][j] = bias[nh * 16 + 4 * lg + j];
+        for (int nh = 0; nh < NH; ++nh) wa[t][nh] = lds8(wl + chunk_at((t * NH + nh) * 16 + l16, lg));
+}
 
-    // the accumulators start from the bias, so acc = conv + b
-    auto finish = [&](int g, const f32x4* acc) {
-        const int p = 16 * g + l16;
-        if (p >= NP) return;
+// One 32-input-channel layer with output width SO (rows of P slots, SO of
+// them computed), NH blocks of 16 output channels, weights in wa.  Not LAST:
+// bias + ReLU into `out`; LAST: the lanes holding channels 0..3 of a slot
+// inside the tile apply the correction, to the uncorrected state read from
+// sq in LDS (SQ) or from a.qi.  bias is in LDS.  Wave w takes the groups w,
+// w + NW, ...; the operands of the next group are loaded before the products
+// of the current one.  After its last group the wave loads the weights of
+// the next layer (wl_next, NHN blocks) into wn, while slower waves finish.
+template <int SO, int NH, bool LAST, bool SQ, int NHN>
+__device__ __forceinline__ void layer32(const bf16x8 (&wa)[9][NH], const float* bias,
+                                        const bf16_t* __restrict__ in, bf16_t* __restrict__ out, const Args& a,
+                                        int gx0, int gy0, int W, const float* sq, const bf16_t* wl_next,
+                                        bf16x8 (&wn)[9][NHN > 0 ? NHN : 1])
+{
+    constexpr int NG = SO * P / 16, KMAX = (NG + NW - 1) / NW;
+    static_assert(SO * P % 16 == 0, "whole groups");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lg = lane >> 4;
+    const int K = (NG - wave + NW - 1) / NW;  // groups of this wave
+    f32x4 bb[NH];
+#pragma unroll
+    for (int nh = 0; nh < NH; ++nh) bb[nh] = *reinterpret_cast<const f32x4*>(bias + nh * 16 + 4 * lg);
+    // per-tap input offsets of this lane, relative to the group's first slot
+    int kt[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) kt[t] = chunk_at(l16 + (P + 1) + (t / 3 - 1) * P + (t % 3 - 1), lg);
+    auto load = [&](int g, bf16x8(&x)[9]) {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) x[t] = lds8(in + g * 16 * SLOT + kt[t]);
+    };
+    // products and epilogue of group g
+    auto group = [&](int g, const bf16x8(&x)[9]) {
         if constexpr (!LAST) {
+            // the accumulators start from the bias, so acc = conv + b
+            f32x4 acc[NH];
+#pragma unroll
+            for (int nh = 0; nh < NH; ++nh) acc[nh] = bb[nh];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+#pragma unroll
+                for (int nh = 0; nh < NH; ++nh)
+                    acc[nh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nh], x[t], acc[nh], 0, 0, 0);
+            }
 #pragma unroll
             for (int nh = 0; nh < NH; ++nh)
-                *reinterpret_cast<uint2*>(out + p * AS + nh * 16 + 4 * lg) =
-                    pack4(fmaxf(acc[nh][0], 0.f), fmaxf(acc[nh][1], 0.f), fmaxf(acc[nh][2], 0.f),
-                          fmaxf(acc[nh][3], 0.f));
+                *reinterpret_cast<uint2*>(out + g * 16 * SLOT + store_off(l16, lg, nh)) = relu4(acc[nh]);
         } else {
-            if (lg == 0) {
-                const int py = p / SO, px = p - py * SO;
-                const size_t o = (size_t)(gy0 + py) * W + (gx0 + px);
+            static_assert(NH == 1 && NHN == 0, "one block of output channels in the last layer");
+            // two independent chains (taps 0..4 from the bias, taps 5..8 from 0)
+            f32x4 c0 = bb[0], c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+                c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][0], x[t], c0, 0, 0, 0);
+                if (t + 5 < 9) c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t + 5][0], x[t + 5], c1, 0, 0, 0);
+            }
+            const int q = 16 * g + l16, y = q / P, xq = q - y * P;
+            if (lg == 0 && xq < T) {
+                const size_t o = (size_t)(gy0 + y) * W + (gx0 + xq);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     // the uncorrected state: from LDS when the kernel ran the step itself
-                    const float q = sq ? sq[c * T * T + p] : a.qi[c][o];
-                    a.qo[c][o] = a.d[c] != 0.f ? fmaf(a.d[c], acc[0][c], q) : q;
+                    const float v = SQ ? sq[c * T * T + y * T + xq] : a.qi[c][o];
+                    a.qo[c][o] = a.d[c] != 0.f ? fmaf(a.d[c], c0[c] + c1[c], v) : v;
                 }
             }
         }
     };
-    auto base_of = [&](int g) {
-        const int p = min(16 * g + l16, NP - 1);
-        const int py = p / SO, px = p - py * SO;
-        return ((py + 1) * SN + (px + 1)) * AS + 8 * lg;
-    };
-    // groups wave, wave + NW, ...: two at a time so consecutive MFMAs are independent
-    int g = wave;
-    for (; g + NW < NG; g += 2 * NW) {
-        const int b0 = base_of(g), b1 = base_of(g + NW);
-        f32x4 a0[NH], a1[NH];
+    bf16x8 xb[2][9];
+    load(wave, xb[0]);
 #pragma unroll
-        for (int nh = 0; nh < NH; ++nh) a0[nh] = a1[nh] = f32x4{bb[nh][0], bb[nh][1], bb[nh][2], bb[nh][3]};
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int off = ((t / 3 - 1) * SN + (t % 3 - 1)) * AS;
-            const bf16x8 x0 = lds8(in + b0 + off), x1 = lds8(in + b1 + off);
-#pragma unroll
-            for (int nh = 0; nh < NH; ++nh) {
-                a0[nh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nh], x0, a0[nh], 0, 0, 0);
-                a1[nh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nh], x1, a1[nh], 0, 0, 0);
-            }
+    for (int k = 0; k < KMAX; ++k) {
+        if (k < K) {
+            // all loads of the next group are issued before this group's products
+            if (k + 1 < KMAX && k + 1 < K) load(wave + (k + 1) * NW, xb[(k + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            group(wave + k * NW, xb[k & 1]);
         }
-        finish(g, a0);
-        finish(g + NW, a1);
     }
-    if (g < NG) {
-        const int b0 = base_of(g);
-        f32x4 a0[NH];
-#pragma unroll
-        for (int nh = 0; nh < NH; ++nh) a0[nh] = f32x4{bb[nh][0], bb[nh][1], bb[nh][2], bb[nh][3]};
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int off = ((t / 3 - 1) * SN + (t % 3 - 1)) * AS;
-            const bf16x8 x0 = lds8(in + b0 + off);
-#pragma unroll
-            for (int nh = 0; nh < NH; ++nh)
-                a0[nh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nh], x0, a0[nh], 0, 0, 0);
-        }
-        finish(g, a0);
-    }
+    if constexpr (NHN > 0) load_weights<NHN>(wl_next, wn);
 }
+
+// Layer 0 on one group of 16 output slots (all inside the 24-wide output):
+// staged input (side SI, 4 halfwords per node: 3 channels and a zero) ->
+// slots of buffer A.  Lane group lg holds k = 8 lg .. 8 lg + 7, i.e. taps
+// 2 lg and 2 lg + 1 with their four halfwords, two 8-byte loads; tap 8 is a
+// K = 16 product whose weights are zero outside lane group 0.
+struct Layer0 {
+    bf16x8 wa0, wa1;
+    bf16x4 wc0, wc1;
+    f32x4 bb0, bb1;
+    int offa, offb, l16, lg;
+    __device__ __forceinline__ f32x4 mfma(const bf16x8& w, const bf16x4& wc, const bf16x8& x, const bf16x4& x8,
+                                          const f32x4& b) const
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wc, x8, __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, b, 0, 0, 0),
+                                                          0, 0, 0);
+    }
+};
 
 // STEP: the kernel first runs the SMAME step itself (fully periodic grids):
 // it stages the state before the step on the (SI + 4)^2 region in the space
@@ -672,39 +777,28 @@ constexpr int DS = SI + 2, NDS = DS * DS;  // drho' region (28^2)
 static_assert((3 * NRS + NDS) * 4 <= BA * 2, "step staging fits in buffer A");
 constexpr int SQ_HALF = 3 * T * T * 2;     // centre values, FP32, in halfwords
 
+// One workgroup per CU (LDS), i.e. two waves per SIMD: up to 256 VGPRs a lane.
 template <bool STEP>
-__global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a, Coef<float> cf, State<float> qs)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void cnn_fused_kernel(
+    int H, int W, Args a, Coef<float> cf, State<float> qs)
 {
     __shared__ __align__(16) bf16_t lds[LDS_HALF + (STEP ? SQ_HALF : 0)];
+    // biases of the five layers, then the per-row force of the SI input rows
+    __shared__ __align__(16) float sbf[NBIAS + 32];
     bf16_t* const sw = lds;
     bf16_t* const sa = lds + WTOT;
     bf16_t* const sb = sa + BA;
+    float* const sfx = sbf + NBIAS;
     const int tiles_x = W / T;
     const int gx0 = (blockIdx.x % tiles_x) * T, gy0 = (blockIdx.x / tiles_x) * T;
     const int tid = threadIdx.x;
 
-    // ---- staging: weights of layers 1..4 (straight copies), the layer-0
-    // im2col weights and the normalised input region; all loads are issued
-    // before the first LDS store.
-    constexpr int NV = WL / 8, NV4 = W4 / 8;  // uint4 per layer
-    constexpr int IW = (NV + NT - 1) / NT, IW4 = (NV4 + NT - 1) / NT;
-    uint4 wv[3][IW], wv4[IW4];
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-        for (int i = 0; i < IW; ++i)
-            wv[l][i] = reinterpret_cast<const uint4*>(a.w[l + 1])[min(tid + i * NT, NV - 1)];
-#pragma unroll
-    for (int i = 0; i < IW4; ++i) wv4[i] = reinterpret_cast<const uint4*>(a.w[4])[min(tid + i * NT, NV4 - 1)];
-    constexpr int I0 = W0 / NT;  // layer-0 entries per thread
-    static_assert(W0 % NT == 0, "layer-0 staging covers the im2col weights exactly");
-    bf16_t w0v[I0];
-#pragma unroll
-    for (int i = 0; i < I0; ++i) {
-        const int e = tid + i * NT, o = e / 32, k = e % 32;
-        w0v[i] = k < 27 ? a.w[0][((k / 3) * 32 + o) * 16 + (k % 3)] : bf16_t(0);
-    }
-    constexpr int NI = SI * SI, II = (NI + NT - 1) / NT;
+    // ---- staging.  Loads in the order they are needed: the input region
+    // (the state), the force rows, the biases and the layer-0 im2col weights,
+    // then the weights of layers 1..4 (straight copies).  The latter stay in
+    // registers until layer 0 has been computed, so their latency hides
+    // behind the step and layer 0.
+    constexpr int NI = SI * SI;
     constexpr int NQ = STEP ? NRS : NI, IQ = (NQ + NT - 1) / NT;
     constexpr int QS = STEP ? RS : SI, QH = STEP ? 7 : 5;  // staged side and halo
     const float* const q0p = STEP ? qs.r : a.qi[0];
@@ -720,16 +814,49 @@ __global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a, Coe
         q1[i] = q1p[src];
         q2[i] = q2p[src];
     }
+    const int fr = tid - NBIAS;  // force row handled by this thread
+    float fv = 0.f;
+    if (STEP && cf.fx && fr >= 0 && fr < SI) fv = cf.fx[wrap(gy0 - 5 + fr, H)];
+    float bv = 0.f;
+    if (tid < NBIAS) {
+        // per-lane layer index: select the pointer instead of indexing the argument array
+        const int l = tid >> 5;
+        const float* bp = l == 0 ? a.b[0] : l == 1 ? a.b[1] : l == 2 ? a.b[2] : l == 3 ? a.b[3] : a.b[4];
+        bv = bp[tid - 32 * l];
+    }
+    constexpr int I0 = (W0 + NT - 1) / NT;  // layer-0 entries per thread
+    bf16_t w0v[I0];
 #pragma unroll
-    for (int l = 0; l < 3; ++l)
+    for (int i = 0; i < I0; ++i) {
+        const int e = tid + i * NT;
+        // taps 0..7: [o][4 t + c]; tap 8: [o][c]; c = 3 is the zero padding
+        const int o = e < W0A ? e >> 5 : (e - W0A) >> 2;
+        const int t = e < W0A ? (e & 31) >> 2 : 8, c = e & 3;
+        w0v[i] = e < W0 && c < 3 ? a.w[0][(t * 32 + o) * 16 + c] : bf16_t(0);
+    }
+    // layers 1..4 are contiguous in LDS: chunk e (16 bytes) of that span
+    // comes from layer 1 + e / NV; thread tid moves chunks tid + j NT.  The
+    // chunks are named values, not an array, so that they stay in registers
+    // across the loops in between.
+    constexpr int NV = WL / 8, NVT = (3 * WL + W4) / 8;  // 16-byte chunks per layer 1..3, in total
+    static_assert(NVT <= 8 * NT && NVT > 7 * NT, "eight chunks per thread");
+    auto wchunk = [&](int j) {
+        const int e = min(tid + j * NT, NVT - 1), l = e / NV;
+        const bf16_t* src = l == 0 ? a.w[1] : l == 1 ? a.w[2] : l == 2 ? a.w[3] : a.w[4];
+        return reinterpret_cast<const uint4*>(src)[e - l * NV];
+    };
+    const uint4 wc0 = wchunk(0), wc1 = wchunk(1), wc2 = wchunk(2), wc3 = wchunk(3);
+    const uint4 wc4 = wchunk(4), wc5 = wchunk(5), wc6 = wchunk(6), wc7 = wchunk(7);
 #pragma unroll
-        for (int i = 0; i < IW; ++i)
-            if (tid + i * NT < NV) reinterpret_cast<uint4*>(sw + OW1 + l * WL)[tid + i * NT] = wv[l][i];
-#pragma unroll
-    for (int i = 0; i < IW4; ++i)
-        if (tid + i * NT < NV4) reinterpret_cast<uint4*>(sw + OW4)[tid + i * NT] = wv4[i];
-#pragma unroll
-    for (int i = 0; i < I0; ++i) sw[tid + i * NT] = w0v[i];
+    for (int i = 0; i < I0; ++i) {
+        const int e = tid + i * NT;
+        if (e < W0A)
+            sw[chunk_at(e >> 5, (e & 31) >> 3) + (e & 7)] = w0v[i];
+        else if (e < W0)
+            sw[e] = w0v[i];
+    }
+    if (tid < NBIAS) sbf[tid] = bv;
+    if (STEP && fr >= 0 && fr < SI) sfx[fr] = fv;
     if constexpr (STEP) {
         float* const sr = reinterpret_cast<float*>(sa);
         float* const su = sr + NRS;
@@ -746,22 +873,45 @@ __global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a, Coe
             }
         }
         __syncthreads();
-        for (int q = tid; q < NDS; q += NT) {
-            const int ly = q / DS, lx = q - ly * DS;
-            srn[q] = rho_new_2d<float, RS>(cf, sr, su, sv, (ly + 1) * RS + (lx + 1));
+        // nodes tid and tid + NT: the second one at a clamped (valid) index
+        // and stored only when inside the region, so both are computed in
+        // straight-line code and their LDS reads overlap
+        static_assert(NDS <= 2 * NT && NI <= 2 * NT, "two nodes per thread");
+        {
+            float rn2[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int q = min(tid + i * NT, NDS - 1);
+                const int ly = q / DS, lx = q - ly * DS;
+                rn2[i] = rho_new_2d<float, RS>(cf, sr, su, sv, (ly + 1) * RS + (lx + 1));
+            }
+            srn[tid] = rn2[0];
+            if (tid + NT < NDS) srn[tid + NT] = rn2[1];
         }
         __syncthreads();
-        for (int q = tid; q < NI; q += NT) {
+        // the force of input row ly from LDS (same values as the step kernels read)
+        Coef<float> cl = cf;
+        if (cf.fx) cl.fx = sfx;
+        float rn[2], un[2], vn[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int q = min(tid + i * NT, NI - 1);
             const int ly = q / SI, lx = q - ly * SI;
-            float rn, un, vn;
-            momentum_node2d<float, RS, DS>(cf, sr, su, sv, srn, (ly + 2) * RS + (lx + 2), (ly + 1) * DS + (lx + 1),
-                                           wrap(gy0 - 5 + ly, H), rn, un, vn);
-            *reinterpret_cast<uint2*>(sb + 4 * q) = pack4(rn * a.s[0], un * a.s[1], vn * a.s[2], 0.f);
-            const int cy = ly - 5, cx = lx - 5;
-            if (cy >= 0 && cy < T && cx >= 0 && cx < T) {
-                sq[cy * T + cx] = rn;
-                sq[T * T + cy * T + cx] = un;
-                sq[2 * T * T + cy * T + cx] = vn;
+            momentum_node2d<float, RS, DS>(cl, sr, su, sv, srn, (ly + 2) * RS + (lx + 2), (ly + 1) * DS + (lx + 1),
+                                           ly, rn[i], un[i], vn[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int q = tid + i * NT;
+            if (q < NI) {
+                const int ly = q / SI, lx = q - ly * SI;
+                *reinterpret_cast<uint2*>(sb + 4 * q) = pack4(rn[i] * a.s[0], un[i] * a.s[1], vn[i] * a.s[2], 0.f);
+                const int cy = ly - 5, cx = lx - 5;
+                if (cy >= 0 && cy < T && cx >= 0 && cx < T) {
+                    sq[cy * T + cx] = rn[i];
+                    sq[T * T + cy * T + cx] = un[i];
+                    sq[2 * T * T + cy * T + cx] = vn[i];
+                }
             }
         }
     } else {
@@ -774,52 +924,85 @@ __global__ __launch_bounds__(NT) void cnn_fused_kernel(int H, int W, Args a, Coe
     }
     __syncthreads();
 
-    // ---- layer 0 (im2col, K = 27): staged input (side 26, 4 halfwords per
-    // node) -> buffer A (side 24)
+    // ---- layer 0: staged input (buffer B) -> buffer A, 36 groups
     {
-        constexpr int NP = S0 * S0, NG = NP / 16;
-        const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lg = lane >> 4;
-        // offsets of the lane's eight k = 8 lg + j taps/channels (k >= 27 is padding)
-        int koff[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = min(8 * lg + j, 26), t = k / 3, c = k - 3 * t;
-            koff[j] = ((t / 3 - 1) * SI + (t % 3 - 1)) * 4 + c;
-        }
-        const bf16x8 wa0 = lds8(sw + l16 * 32 + 8 * lg), wa1 = lds8(sw + (16 + l16) * 32 + 8 * lg);
-        float bb[2][4];
-#pragma unroll
-        for (int nh = 0; nh < 2; ++nh)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bb[nh][j] = a.b[0][nh * 16 + 4 * lg + j];
-        for (int g = wave; g < NG; g += NW) {
-            const int p = 16 * g + l16, py = p / S0, px = p - py * S0;
+        constexpr int NG = P * P / 16;
+        static_assert(P * P % 16 == 0, "layer 0 has whole groups");
+        const int lane = tid & 63, wave = tid >> 6;
+        Layer0 L;
+        L.l16 = lane & 15;
+        L.lg = lane >> 4;
+        const int ta = 2 * L.lg, tb = 2 * L.lg + 1;
+        L.offa = ((ta / 3 - 1) * SI + (ta % 3 - 1)) * 4;
+        L.offb = ((tb / 3 - 1) * SI + (tb % 3 - 1)) * 4;
+        constexpr int off8 = (SI + 1) * 4;
+        L.wa0 = lds8(sw + chunk_at(L.l16, L.lg));
+        L.wa1 = lds8(sw + chunk_at(16 + L.l16, L.lg));
+        const bf16x4 zero4 = {0, 0, 0, 0};
+        L.wc0 = L.lg == 0 ? *reinterpret_cast<const bf16x4*>(sw + W0A + L.l16 * 4) : zero4;
+        L.wc1 = L.lg == 0 ? *reinterpret_cast<const bf16x4*>(sw + W0A + (16 + L.l16) * 4) : zero4;
+        L.bb0 = *reinterpret_cast<const f32x4*>(sbf + 4 * L.lg);
+        L.bb1 = *reinterpret_cast<const f32x4*>(sbf + 16 + 4 * L.lg);
+        const int so0 = store_off(L.l16, L.lg, 0), so1 = store_off(L.l16, L.lg, 1);
+        auto input = [&](int g, bf16x8& x, bf16x4& x8) {
+            const int p = 16 * g + L.l16, py = p / P, px = p - py * P;
             const int base = ((py + 1) * SI + (px + 1)) * 4;
-            bf16x8 x;
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                x[j] = 8 * lg + j < 27 ? __builtin_bit_cast(__bf16, sb[base + koff[j]]) : __bf16(0.f);
-            // accumulators start from the bias
-            f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, x, f32x4{bb[0][0], bb[0][1], bb[0][2], bb[0][3]},
-                                                              0, 0, 0);
-            f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, x, f32x4{bb[1][0], bb[1][1], bb[1][2], bb[1][3]},
-                                                              0, 0, 0);
-            *reinterpret_cast<uint2*>(sa + p * AS + 4 * lg) =
-                pack4(fmaxf(c0[0], 0.f), fmaxf(c0[1], 0.f), fmaxf(c0[2], 0.f), fmaxf(c0[3], 0.f));
-            *reinterpret_cast<uint2*>(sa + p * AS + 16 + 4 * lg) =
-                pack4(fmaxf(c1[0], 0.f), fmaxf(c1[1], 0.f), fmaxf(c1[2], 0.f), fmaxf(c1[3], 0.f));
+            const uint2 xa = *reinterpret_cast<const uint2*>(sb + base + L.offa);
+            const uint2 xb = *reinterpret_cast<const uint2*>(sb + base + L.offb);
+            x8 = *reinterpret_cast<const bf16x4*>(sb + base + off8);
+            x = __builtin_bit_cast(bf16x8, uint4{xa.x, xa.y, xb.x, xb.y});
+        };
+        // two groups at a time, so the two products of one group do not wait on each other
+        int g = wave;
+        for (; g + NW < NG; g += 2 * NW) {
+            bf16x8 x0, x1;
+            bf16x4 y0, y1;
+            input(g, x0, y0);
+            input(g + NW, x1, y1);
+            const f32x4 c00 = L.mfma(L.wa0, L.wc0, x0, y0, L.bb0), c01 = L.mfma(L.wa1, L.wc1, x0, y0, L.bb1);
+            const f32x4 c10 = L.mfma(L.wa0, L.wc0, x1, y1, L.bb0), c11 = L.mfma(L.wa1, L.wc1, x1, y1, L.bb1);
+            *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so0) = relu4(c00);
+            *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so1) = relu4(c01);
+            *reinterpret_cast<uint2*>(sa + (g + NW) * 16 * SLOT + so0) = relu4(c10);
+            *reinterpret_cast<uint2*>(sa + (g + NW) * 16 * SLOT + so1) = relu4(c11);
+        }
+        if (g < NG) {
+            bf16x8 x0;
+            bf16x4 y0;
+            input(g, x0, y0);
+            const f32x4 c00 = L.mfma(L.wa0, L.wc0, x0, y0, L.bb0), c01 = L.mfma(L.wa1, L.wc1, x0, y0, L.bb1);
+            *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so0) = relu4(c00);
+            *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so1) = relu4(c01);
         }
     }
+    {
+        // weights of layers 1..4, chunk e of row e / 4 at its swizzled place
+        uint4* const d = reinterpret_cast<uint4*>(sw + OW1);
+        auto put = [&](int j, const uint4& v) {
+            const int e = tid + j * NT;
+            if (e < NVT) d[(e & ~3) | ((e & 3) ^ ((e >> 3) & 3))] = v;
+        };
+        put(0, wc0);
+        put(1, wc1);
+        put(2, wc2);
+        put(3, wc3);
+        put(4, wc4);
+        put(5, wc5);
+        put(6, wc6);
+        put(7, wc7);
+    }
     __syncthreads();
-    layer32<S1, 2, false>(sw + OW1, a.b[1], sa, sb, a, gx0, gy0, H, W);
+    const float* const sq = reinterpret_cast<const float*>(lds + LDS_HALF);
+    bf16x8 w1[9][2], w2[9][2], w3[9][2], w4[9][1], wnone[9][1];
+    load_weights<2>(sw + OW1, w1);
+    layer32<P - 2, 2, false, false, 2>(w1, sbf + 32, sa, sb, a, gx0, gy0, W, sq, sw + OW2, w2);
     __syncthreads();
-    layer32<S1 - 2, 2, false>(sw + OW2, a.b[2], sb, sa, a, gx0, gy0, H, W);
+    layer32<P - 4, 2, false, false, 2>(w2, sbf + 64, sb, sa, a, gx0, gy0, W, sq, sw + OW3, w3);
     __syncthreads();
-    layer32<S1 - 4, 2, false>(sw + OW3, a.b[3], sa, sb, a, gx0, gy0, H, W);
+    layer32<P - 6, 2, false, false, 1>(w3, sbf + 96, sa, sb, a, gx0, gy0, W, sq, sw + OW4, w4);
     __syncthreads();
-    // last layer: output side 16 = the tile; (gx0, gy0) is its origin
-    layer32<T, 1, true>(sw + OW4, a.b[4], sb, nullptr, a, gx0, gy0, H, W,
-                        STEP ? reinterpret_cast<const float*>(lds + LDS_HALF) : nullptr);
+    // last layer: output width 16 = the tile; (gx0, gy0) is its origin
+    layer32<T, 1, true, STEP, 0>(w4, sbf + 128, sb, nullptr, a, gx0, gy0, W, sq, nullptr, wnone);
 }
 }  // namespace fused
 
