@@ -282,17 +282,38 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(int H, int W, const bf1
 }
 
 // fixed-order sum of the per-workgroup partials: out[e] = sum_b partial[b][e]
-// (acc: out[e] += that sum)
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ partial, int nblk, int n,
-                                                              float* __restrict__ dw, float* __restrict__ db, int nw,
-                                                              int acc)
+// (acc: out[e] += that sum).  A workgroup takes 64 consecutive elements;
+// wave s of its RP_SEG waves sums the blocks b = s, s + RP_SEG, ... in
+// increasing b (64 consecutive floats of a partial row per load), and the
+// RP_SEG segment sums are added in increasing s: a fixed order for any
+// launch, with RP_SEG independent load streams per element.
+constexpr int RP_SEG = 16;
+__global__ __launch_bounds__(64 * RP_SEG) void reduce_partials_kernel(const float* __restrict__ partial, int nblk,
+                                                                      int n, float* __restrict__ dw,
+                                                                      float* __restrict__ db, int nw, int acc)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= n) return;
+    __shared__ float seg[RP_SEG][64];
+    const int lane = threadIdx.x & 63, sgi = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * n + e];
-    float* dst = e < nw ? &dw[e] : &db[e - nw];
-    *dst = acc ? *dst + s : s;
+    if (e < n) {
+        int b = sgi;
+        // four loads in flight per lane; the sum stays in increasing b
+        for (; b + 3 * RP_SEG < nblk; b += 4 * RP_SEG) {
+            const float v0 = partial[(size_t)b * n + e], v1 = partial[(size_t)(b + RP_SEG) * n + e];
+            const float v2 = partial[(size_t)(b + 2 * RP_SEG) * n + e], v3 = partial[(size_t)(b + 3 * RP_SEG) * n + e];
+            s = (((s + v0) + v1) + v2) + v3;
+        }
+        for (; b < nblk; b += RP_SEG) s += partial[(size_t)b * n + e];
+    }
+    seg[sgi][lane] = s;
+    __syncthreads();
+    if (sgi == 0 && e < n) {
+        float t = seg[0][lane];
+        for (int k = 1; k < RP_SEG; ++k) t += seg[k][lane];
+        float* dst = e < nw ? &dw[e] : &db[e - nw];
+        *dst = acc ? *dst + t : t;
+    }
 }
 
 // wt[t][i][o] = w[8 - t][o][i]: weights of the transposed convolution
@@ -378,12 +399,20 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(int n, const float* __re
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void loss_final_kernel(const double* __restrict__ partial, int nblk, double count, double* __restrict__ out)
+// out = sum_b partial[b] / count: thread t sums b = t, t + 64, ... in
+// increasing b, then thread 0 adds the 64 sums in increasing t (fixed order)
+__global__ __launch_bounds__(64) void loss_final_kernel(const double* __restrict__ partial, int nblk, double count,
+                                                        double* __restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double part[64];
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[b];
-    out[0] = s / count;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += partial[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double t = part[0];
+    for (int k = 1; k < 64; ++k) t += part[k];
+    out[0] = t / count;
 }
 
 // loss of a state against its target, for training through several steps:
@@ -1135,8 +1164,8 @@ static acm_status wgrad_impl(int32_t nx, int32_t ny, int32_t cin, int32_t cout, 
     acm_status st = chip(hipGetLastError(), "wgrad launch");
     if (st != ACM_OK) return st;
     const int n = 9 * cout * cin + cout;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(n)), dim3(256), 0, s, workspace, nblk, n, dw, db,
-                       9 * cout * cin, acc);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 63) / 64), dim3(64 * RP_SEG), 0, s, workspace, nblk, n, dw,
+                       db, 9 * cout * cin, acc);
     return chip(hipGetLastError(), "reduce launch");
 }
 
