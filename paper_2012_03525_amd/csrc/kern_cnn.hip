@@ -789,8 +789,8 @@ struct Layer0 {
     __device__ __forceinline__ f32x4 mfma(const bf16x8& w, const bf16x4& wc, const bf16x8& x, const bf16x4& x8,
                                           const f32x4& b) const
     {
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wc, x8, __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, b, 0, 0, 0),
-                                                          0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wc, x8, b, 0, 0, 0),
+                                                       0, 0, 0);
     }
 };
 
@@ -819,7 +819,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     bf16_t* const sb = sa + BA;
     float* const sfx = sbf + NBIAS;
     const int tiles_x = W / T;
-    const int gx0 = (blockIdx.x % tiles_x) * T, gy0 = (blockIdx.x / tiles_x) * T;
+    // each XCD takes a contiguous run of tiles, so most halo nodes were written through its own L2
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int gx0 = (lb % tiles_x) * T, gy0 = (lb / tiles_x) * T;
     const int tid = threadIdx.x;
 
     // ---- staging.  Loads in the order they are needed: the input region
@@ -902,37 +904,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
             }
         }
         __syncthreads();
-        // nodes tid and tid + NT: the second one at a clamped (valid) index
-        // and stored only when inside the region, so both are computed in
-        // straight-line code and their LDS reads overlap
+        // nodes tid and tid + NT.  Waves with a second node compute both in
+        // straight-line code (the second at a clamped index, stored only when
+        // inside the region) so their LDS reads overlap; the others one.
         static_assert(NDS <= 2 * NT && NI <= 2 * NT, "two nodes per thread");
+        const int wave = tid >> 6;
         {
-            float rn2[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int q = min(tid + i * NT, NDS - 1);
+            auto node = [&](int q) {
+                q = min(q, NDS - 1);
                 const int ly = q / DS, lx = q - ly * DS;
-                rn2[i] = rho_new_2d<float, RS>(cf, sr, su, sv, (ly + 1) * RS + (lx + 1));
+                return rho_new_2d<float, RS>(cf, sr, su, sv, (ly + 1) * RS + (lx + 1));
+            };
+            if (64 * wave + NT < NDS) {
+                const float r0 = node(tid), r1 = node(tid + NT);
+                srn[tid] = r0;
+                if (tid + NT < NDS) srn[tid + NT] = r1;
+            } else {
+                srn[tid] = node(tid);
             }
-            srn[tid] = rn2[0];
-            if (tid + NT < NDS) srn[tid + NT] = rn2[1];
         }
         __syncthreads();
         // the force of input row ly from LDS (same values as the step kernels read)
         Coef<float> cl = cf;
         if (cf.fx) cl.fx = sfx;
         float rn[2], un[2], vn[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int q = min(tid + i * NT, NI - 1);
+        auto mnode = [&](int q, int i) {
+            q = min(q, NI - 1);
             const int ly = q / SI, lx = q - ly * SI;
             momentum_node2d<float, RS, DS>(cl, sr, su, sv, srn, (ly + 2) * RS + (lx + 2), (ly + 1) * DS + (lx + 1),
                                            ly, rn[i], un[i], vn[i]);
+        };
+        const bool two = 64 * wave + NT < NI;  // wave-uniform
+        if (two) {
+            mnode(tid, 0);
+            mnode(tid + NT, 1);
+        } else {
+            mnode(tid, 0);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int q = tid + i * NT;
-            if (q < NI) {
+            if (q < NI && (i == 0 || two)) {
                 const int ly = q / SI, lx = q - ly * SI;
                 *reinterpret_cast<uint2*>(sb + 4 * q) = pack4(rn[i] * a.s[0], un[i] * a.s[1], vn[i] * a.s[2], 0.f);
                 const int cy = ly - 5, cx = lx - 5;
