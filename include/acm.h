@@ -214,9 +214,11 @@ acm_status acm_set_current(acm_handle* h, int32_t which, int64_t step);
  * vector-Jacobian product adj_q = (dS/dq)^T adj_s.  q, s, adj_s, adj_q: device
  * fields drho, u, v of the handle's grid and precision, caller-owned; s must
  * hold S(q) (its density and velocity enter the derivative of u' = m'/rho').
- * adj_q must not alias the other three (ACM_EINVAL).  Covers 2D single-phase
- * handles on fully periodic grids (ACM_EINVAL otherwise).  Asynchronous on
- * the handle's stream; the handle's own sets are not touched. */
+ * adj_q must not alias the other three (ACM_EINVAL).  Covers planar 2D
+ * single-phase handles with any mix of periodic, wall (moving or not) and
+ * symmetry faces, whose ghost rules enter the derivative (ACM_EINVAL for 3D,
+ * two-phase or axisymmetric handles).  Asynchronous on the handle's stream;
+ * the handle's own sets are not touched. */
 acm_status acm_step_adjoint(acm_handle* h, const acm_fields* q, const acm_fields* s, const acm_fields* adj_s,
                             const acm_fields* adj_q);
 

@@ -6,14 +6,19 @@ The step is written once more, here with PyTorch CPU tensors in FP64, from
 the continuity update (2.10) and the momentum update (2.11) with the
 centred first derivative (2.12), the five-point Laplacian (2.13) and the
 body force of Sec. 2 (rho^{n+1} g, g per row for a forcing profile), on a
-fully periodic grid:
+grid whose four faces are each periodic, a wall or a symmetry plane:
 
   rho'  = rho - dt G_a(rho u_a) + s_rho 1/2 cs^2 dt^2 L(rho)
   m'_a  = m_a - dt G_b(Pi_ab) + nu dt L(m_a)
           - s_m (nu + 1/2 cs^2 dt) [G_a(rho') - G_a(rho)] + dt rho' g_a
   Pi_ab = rho u_a u_b + cs^2 drho delta_ab,   u'_a = m'_a / rho'
 
-(drho = rho - rho0 is the stored density variable).  Its adjoint, the
+(drho = rho - rho0 is the stored density variable).  The stencils read one
+layer of ghost nodes: a periodic face wraps; a wall (halfway between nodes)
+gives the ghost the mirror node's drho and the velocity 2 u_wall - u of the
+mirror node; a symmetry plane mirrors drho and the tangential velocity and
+negates the normal one; the ghosts of rho^{n+1} are filled by the same
+scalar rule (the boundary readings of the C oracle).  Its adjoint, the
 vector-Jacobian product adj_q = (dS/dq)^T adj_s, is taken from this forward
 by torch.autograd, which is the definition of that product; no hand-derived
 transposed stencil is involved.
@@ -58,42 +63,92 @@ def _S(f):  # f[j - 1, i]
     return torch.roll(f, 1, dims=0)
 
 
+PERIODIC, WALL, SYMMETRY = 0, 1, 2
+
+
 def _check(p: Params):
-    if p.dim != 2 or p.two_phase or any(int(b) != 0 for b in p.bc[:4]):
-        raise ValueError("the adjoint oracle covers the 2D single-phase step on periodic grids")
+    if p.dim != 2 or p.two_phase or getattr(p, "axisym", False):
+        raise ValueError("the adjoint oracle covers the planar 2D single-phase step")
+    for lo, hi in ((0, 1), (2, 3)):
+        if (int(p.bc[lo]) == PERIODIC) != (int(p.bc[hi]) == PERIODIC):
+            raise ValueError("a periodic axis has both faces periodic")
+
+
+def _ghost(p: Params, face: int, m: torch.Tensor, comp: Optional[int]) -> torch.Tensor:
+    """Ghost value across `face` (0..3: -x, +x, -y, +y) of the mirror values m:
+    a scalar (comp None) is mirrored; velocity component comp is 2 u_w - m at
+    a wall, -m for the normal component at a symmetry plane, m otherwise."""
+    kind = int(p.bc[face])
+    if comp is None or kind == SYMMETRY and comp != face // 2:
+        return m
+    if kind == WALL:
+        return 2.0 * float(p.wall_u[face][comp]) - m
+    return -m
+
+
+def _pad(p: Params, f: torch.Tensor, comp: Optional[int] = None) -> torch.Tensor:
+    """f [ny, nx] with one ghost layer on every side (corners unused)."""
+    if int(p.bc[0]) == PERIODIC:
+        lo, hi = f[:, -1:], f[:, :1]
+    else:
+        lo, hi = _ghost(p, 0, f[:, :1], comp), _ghost(p, 1, f[:, -1:], comp)
+    f = torch.cat([lo, f, hi], dim=1)
+    if int(p.bc[2]) == PERIODIC:
+        lo, hi = f[-1:, :], f[:1, :]
+    else:
+        lo, hi = _ghost(p, 2, f[:1, :], comp), _ghost(p, 3, f[-1:, :], comp)
+    return torch.cat([lo, f, hi], dim=0)
 
 
 def step2d(p: Params, r: torch.Tensor, u: torch.Tensor, v: torch.Tensor,
            force_x_row: Optional[torch.Tensor] = None):
-    """One step (2.10)-(2.13) with the body force on a periodic 2D grid;
-    differentiable torch FP64 tensors [ny, nx] in, (drho', u', v') out."""
+    """One step (2.10)-(2.13) with the body force on a planar 2D grid with
+    periodic, wall or symmetry faces; differentiable torch FP64 tensors
+    [ny, nx] in, (drho', u', v') out."""
     _check(p)
     dx, dt, nu, cs2, rho0 = p.dx, p.dt, p.nu, p.cs * p.cs, p.rho0
-    rho = rho0 + r
-    mx, my = rho * u, rho * v
+    # level-n fields with their ghosts
+    rp, up, vp = _pad(p, r), _pad(p, u, 0), _pad(p, v, 1)
+    rhop = rho0 + rp
+    mxp, myp = rhop * up, rhop * vp
+    C = (slice(1, -1), slice(1, -1))
+    mx, my = mxp[C], myp[C]
+
+    def E(f):
+        return f[1:-1, 2:]
+
+    def W(f):
+        return f[1:-1, :-2]
+
+    def N(f):
+        return f[2:, 1:-1]
+
+    def S(f):
+        return f[:-2, 1:-1]
 
     def G_x(f):
-        return (_E(f) - _W(f)) / (2.0 * dx)
+        return (E(f) - W(f)) / (2.0 * dx)
 
     def G_y(f):
-        return (_N(f) - _S(f)) / (2.0 * dx)
+        return (N(f) - S(f)) / (2.0 * dx)
 
     def L(f):
-        return (_E(f) + _W(f) + _N(f) + _S(f) - 4.0 * f) / (dx * dx)
+        return (E(f) + W(f) + N(f) + S(f) - 4.0 * f[C]) / (dx * dx)
 
-    rn = r - dt * (G_x(mx) + G_y(my)) + p.sat_rho * 0.5 * cs2 * dt * dt * L(r)
-    pxx = mx * u + cs2 * r
-    pxy = mx * v
-    pyx = my * u
-    pyy = my * v + cs2 * r
+    rn = r - dt * (G_x(mxp) + G_y(myp)) + p.sat_rho * 0.5 * cs2 * dt * dt * L(rp)
+    rnp = _pad(p, rn)  # ghosts of rho^{n+1}
+    pxx = mxp * up + cs2 * rp
+    pxy = mxp * vp
+    pyx = myp * up
+    pyy = myp * vp + cs2 * rp
     rho_n = rho0 + rn
     kd = nu + 0.5 * cs2 * dt
     gx = p.g[0] + (force_x_row[:, None] if force_x_row is not None else 0.0)
     gy = p.g[1]
-    mxn = (mx - dt * (G_x(pxx) + G_y(pxy)) + nu * dt * L(mx)
-           - p.sat_mom * kd * (G_x(rn) - G_x(r)) + dt * rho_n * gx)
-    myn = (my - dt * (G_x(pyx) + G_y(pyy)) + nu * dt * L(my)
-           - p.sat_mom * kd * (G_y(rn) - G_y(r)) + dt * rho_n * gy)
+    mxn = (mx - dt * (G_x(pxx) + G_y(pxy)) + nu * dt * L(mxp)
+           - p.sat_mom * kd * (G_x(rnp) - G_x(rp)) + dt * rho_n * gx)
+    myn = (my - dt * (G_x(pyx) + G_y(pyy)) + nu * dt * L(myp)
+           - p.sat_mom * kd * (G_y(rnp) - G_y(rp)) + dt * rho_n * gy)
     return rn, mxn / rho_n, myn / rho_n
 
 

@@ -529,8 +529,8 @@ acm_status acm_step_adjoint(acm_handle* h, const acm_fields* q, const acm_fields
                             const acm_fields* adj_q)
 {
     if (!h || !q || !s || !adj_s || !adj_q) return fail(ACM_EINVAL, "NULL argument");
-    if (h->cfg.dim != 2 || h->cfg.two_phase || h->cf.nonperiodic)
-        return fail(ACM_EINVAL, "the adjoint step covers 2D single-phase runs on fully periodic grids");
+    if (h->cfg.dim != 2 || h->cfg.two_phase || h->cfg.axisym)
+        return fail(ACM_EINVAL, "the adjoint step covers planar 2D single-phase runs");
     const acm_fields* all[4] = {q, s, adj_s, adj_q};
     for (const acm_fields* f : all)
         if (!f->drho || !f->u || !f->v) return fail(ACM_EINVAL, "NULL field");

@@ -1,6 +1,7 @@
 """GPU parity of training through the solver: the adjoint step kernel
 against the FP64 oracle's vector-Jacobian product (FP64 and FP32, ragged
-and multi-tile grids, the 256^2 closure grid), its argument checks, the
+and multi-tile grids, the 256^2 closure grid, periodic faces and walls,
+moving walls and symmetry planes), its argument checks, the
 state loss, the accumulating weight gradient, and the whole k-step
 unrolled gradient against the oracle's autograd of the same composition."""
 import ctypes
@@ -31,12 +32,30 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_adjoint(env, nx, ny, precision, seed, nu=0.04, g=(2e-5, -1e-5), force=True):
+# boundary sets: faces (-x, +x, -y, +y) and wall velocities (face: (u, v))
+WALL_CASES = {
+    "channel": ((0, 0, 1, 1), {3: (0.02, 0.0)}),
+    "cavity": ((1, 1, 1, 1), {3: (0.03, 0.0), 0: (0.0, -0.01)}),
+    "symmetry": ((2, 1, 2, 2), {1: (0.0, 0.015)}),
+    "mixed": ((1, 2, 0, 0), {}),
+}
+
+
+def wall_setup(case):
+    bc, moving = WALL_CASES[case]
+    wall_u = [[0.0] * 3 for _ in range(6)]
+    for f, (a, b) in moving.items():
+        wall_u[f][0], wall_u[f][1] = a, b
+    return tuple(bc) + (0, 0), wall_u
+
+
+def run_adjoint(env, nx, ny, precision, seed, nu=0.04, g=(2e-5, -1e-5), force=True, case=None):
     torch, acm, _, oracle, adjoint = env
     dtype = torch.float64 if precision == "f64" else torch.float32
     dev = torch.device("cuda:0")
     fx = 3e-5 * np.sin(2 * np.pi * 3 * np.arange(ny) / ny + 0.2) if force else None
-    cfg = acm.make_config(2, nx, ny, nu=nu, precision=precision, g=(g[0], g[1], 0.0))
+    bc, wall_u = wall_setup(case) if case else ((0,) * 6, None)
+    cfg = acm.make_config(2, nx, ny, nu=nu, precision=precision, g=(g[0], g[1], 0.0), bc=bc, wall_u=wall_u)
     q = inputs.seeded_state((ny, nx), seed=seed, scale_u=0.05, scale_r=2e-3)
     if precision == "f32":
         q = {k: v.astype(np.float32).astype(np.float64) for k, v in q.items()}
@@ -45,7 +64,7 @@ def run_adjoint(env, nx, ny, precision, seed, nu=0.04, g=(2e-5, -1e-5), force=Tr
     if precision == "f32":
         a = {k: v.astype(np.float32).astype(np.float64) for k, v in a.items()}
     sol = acm.Solver(cfg, q, force_x=fx)
-    print(f"adjoint {precision} {nx}x{ny} seed {seed}", flush=True)
+    print(f"adjoint {precision} {nx}x{ny} seed {seed} boundaries {case or 'periodic'}", flush=True)
     qd = {k: sol.sets[0][k].clone() for k in KEYS}
     sol.step()
     sd = sol.tensors()
@@ -54,7 +73,8 @@ def run_adjoint(env, nx, ny, precision, seed, nu=0.04, g=(2e-5, -1e-5), force=Tr
     sol.adjoint(qd, sd, ad, out)
     torch.cuda.synchronize()
     got = {k: out[k].double().cpu().numpy() for k in KEYS}
-    p = oracle.Params(dim=2, nx=nx, ny=ny, nu=nu, g=(g[0], g[1], 0.0))
+    p = oracle.Params(dim=2, nx=nx, ny=ny, nu=nu, g=(g[0], g[1], 0.0), bc=bc,
+                      wall_u=wall_u if wall_u is not None else [[0.0] * 3 for _ in range(6)])
     ref = adjoint.step2d_vjp(p, q, a, force_x_row=fx)
     sol.close()
     return got, ref
@@ -80,15 +100,33 @@ def test_adjoint_without_force_or_body_force(env):
         assert rel(got[k], ref[k]) <= 1e-12, k
 
 
+@pytest.mark.parametrize("case", sorted(WALL_CASES))
+@pytest.mark.parametrize("nx,ny", [(100, 37), (20, 12)])
+def test_adjoint_walls_f64_matches_oracle(env, case, nx, ny):
+    """Walls (resting and moving) and symmetry planes: the kernel's
+    transposed ghost rules against the oracle's autograd of the step with
+    ghosts, on ragged grids of several tiles and of less than one."""
+    got, ref = run_adjoint(env, nx, ny, "f64", seed=nx + 2 * ny, case=case)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) <= 1e-12, (case, k, rel(got[k], ref[k]))
+
+
+@pytest.mark.parametrize("case", ["cavity", "symmetry"])
+def test_adjoint_walls_f32_matches_oracle(env, case):
+    got, ref = run_adjoint(env, 128, 64, "f32", seed=5, case=case)
+    for k in KEYS:
+        assert rel(got[k], ref[k]) <= 1e-5, (case, k, rel(got[k], ref[k]))
+
+
 def test_adjoint_rejects_unsupported(env):
     torch, acm, _, _, _ = env
     dev = torch.device("cuda:0")
     st = inputs.seeded_state((16, 16), seed=1)
-    walls = acm.Solver(acm.make_config(2, 16, 16, nu=0.05, precision="f64", bc=(0, 0, 1, 1, 0, 0)), st)
     t = [{k: torch.zeros((16, 16), dtype=torch.float64, device=dev) for k in KEYS} for _ in range(4)]
-    with pytest.raises(acm.AcmError):
-        walls.adjoint(*t)
-    walls.close()
+    axi = acm.Solver(acm.make_config(2, 16, 16, nu=0.05, precision="f64", bc=(1, 1, 2, 1, 0, 0), axisym=True), st)
+    with pytest.raises(acm.AcmError):   # the axisymmetric step has its own terms
+        axi.adjoint(*t)
+    axi.close()
     per = acm.Solver(acm.make_config(2, 16, 16, nu=0.05, precision="f64"), st)
     with pytest.raises(acm.AcmError):   # output aliases the cotangent
         per.adjoint(t[0], t[1], t[2], t[2])
