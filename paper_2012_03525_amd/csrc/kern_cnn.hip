@@ -639,7 +639,7 @@ constexpr int W0 = W0A + 32 * 4;          // then tap 8: [o][c]
 constexpr int WL = 9 * 32 * 32;           // layers 1..3: [t][o][i]
 constexpr int W4 = 9 * 16 * 32;           // layer 4: [t][o][i]
 constexpr int OW1 = W0, OW2 = OW1 + WL, OW3 = OW2 + WL, OW4 = OW3 + WL, WTOT = OW4 + W4;
-constexpr int PAD = 16;                   // slots past a buffer's last row, read by the last columns only
+constexpr int PAD = 32;                   // slots past a buffer's last row, read by the last columns only
 constexpr int BA = (P * P + PAD) * SLOT;        // outputs of layers 0 and 2
 constexpr int BB = ((P - 2) * P + PAD) * SLOT;  // outputs of layers 1 and 3; the staged input before them
 constexpr int LDS_HALF = WTOT + BA + BB;
@@ -703,14 +703,17 @@ __device__ __forceinline__ void load_weights(const bf16_t* wl, bf16x8 (&wa)[9][N
 // w + NW, ...; the operands of the next group are loaded before the products
 // of the current one.  After its last group the wave loads the weights of
 // the next layer (wl_next, NHN blocks) into wn, while slower waves finish.
-template <int SO, int NH, bool LAST, bool SQ, int NHN>
+template <int SO, int PI, int NH, bool LAST, bool SQ, int NHN>
 __device__ __forceinline__ void layer32(const bf16x8 (&wa)[9][NH], const float* bias,
                                         const bf16_t* __restrict__ in, bf16_t* __restrict__ out, const Args& a,
                                         int gx0, int gy0, int W, const float* sq, const bf16_t* wl_next,
                                         bf16x8 (&wn)[9][NHN > 0 ? NHN : 1])
 {
-    constexpr int NG = SO * P / 16, KMAX = (NG + NW - 1) / NW;
-    static_assert(SO * P % 16 == 0, "whole groups");
+    // slots q = PI y + x of the input's pitch; the last group may pass the
+    // last row (those slots, like the columns x >= SO, are not stored)
+    constexpr int NG = (SO * PI + 15) / 16, KMAX = (NG + NW - 1) / NW;
+    static_assert(PI == SO + 2, "the input is the previous layer's compact output");
+    static_assert(16 * NG + 2 * PI + 2 <= (SO + 2) * PI + PAD, "reads stay inside the input buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l16 = lane & 15, lg = lane >> 4;
     const int K = (NG - wave + NW - 1) / NW;  // groups of this wave
@@ -720,13 +723,14 @@ __device__ __forceinline__ void layer32(const bf16x8 (&wa)[9][NH], const float* 
     // per-tap input offsets of this lane, relative to the group's first slot
     int kt[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) kt[t] = chunk_at(l16 + (P + 1) + (t / 3 - 1) * P + (t % 3 - 1), lg);
+    for (int t = 0; t < 9; ++t) kt[t] = chunk_at(l16 + (PI + 1) + (t / 3 - 1) * PI + (t % 3 - 1), lg);
     auto load = [&](int g, bf16x8(&x)[9]) {
 #pragma unroll
         for (int t = 0; t < 9; ++t) x[t] = lds8(in + g * 16 * SLOT + kt[t]);
     };
     // products and epilogue of group g
     auto group = [&](int g, const bf16x8(&x)[9]) {
+        const int q = 16 * g + l16, y = q / PI, xq = q - y * PI;
         if constexpr (!LAST) {
             // the accumulators start from the bias, so acc = conv + b
             f32x4 acc[NH];
@@ -738,9 +742,13 @@ __device__ __forceinline__ void layer32(const bf16x8 (&wa)[9][NH], const float* 
                 for (int nh = 0; nh < NH; ++nh)
                     acc[nh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][nh], x[t], acc[nh], 0, 0, 0);
             }
+            // compact output: slot SO y + x, the pitch of the next layer's input
+            if (xq < SO && y < SO) {
+                const int so = SO * y + xq;
 #pragma unroll
-            for (int nh = 0; nh < NH; ++nh)
-                *reinterpret_cast<uint2*>(out + g * 16 * SLOT + store_off(l16, lg, nh)) = relu4(acc[nh]);
+                for (int nh = 0; nh < NH; ++nh)
+                    *reinterpret_cast<uint2*>(out + chunk_at(so, 2 * nh + (lg >> 1)) + 4 * (lg & 1)) = relu4(acc[nh]);
+            }
         } else {
             static_assert(NH == 1 && NHN == 0, "one block of output channels in the last layer");
             // two independent chains (taps 0..4 from the bias, taps 5..8 from 0)
@@ -750,8 +758,7 @@ __device__ __forceinline__ void layer32(const bf16x8 (&wa)[9][NH], const float* 
                 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][0], x[t], c0, 0, 0, 0);
                 if (t + 5 < 9) c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t + 5][0], x[t + 5], c1, 0, 0, 0);
             }
-            const int q = 16 * g + l16, y = q / P, xq = q - y * P;
-            if (lg == 0 && xq < T) {
+            if (lg == 0 && xq < T && y < T) {
                 const size_t o = (size_t)(gy0 + y) * W + (gx0 + xq);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -1036,14 +1043,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     const float* const sq = reinterpret_cast<const float*>(lds + LDS_HALF);
     bf16x8 w1[9][2], w2[9][2], w3[9][2], w4[9][1], wnone[9][1];
     load_weights<2>(sw + OW1, w1);
-    layer32<P - 2, 2, false, false, 2>(w1, sbf + 32, sa, sb, a, gx0, gy0, W, sq, sw + OW2, w2);
+    layer32<P - 2, P, 2, false, false, 2>(w1, sbf + 32, sa, sb, a, gx0, gy0, W, sq, sw + OW2, w2);
     __syncthreads();
-    layer32<P - 4, 2, false, false, 2>(w2, sbf + 64, sb, sa, a, gx0, gy0, W, sq, sw + OW3, w3);
+    layer32<P - 4, P - 2, 2, false, false, 2>(w2, sbf + 64, sb, sa, a, gx0, gy0, W, sq, sw + OW3, w3);
     __syncthreads();
-    layer32<P - 6, 2, false, false, 1>(w3, sbf + 96, sa, sb, a, gx0, gy0, W, sq, sw + OW4, w4);
+    layer32<P - 6, P - 4, 2, false, false, 1>(w3, sbf + 96, sa, sb, a, gx0, gy0, W, sq, sw + OW4, w4);
     __syncthreads();
     // last layer: output width 16 = the tile; (gx0, gy0) is its origin
-    layer32<T, 1, true, STEP, 0>(w4, sbf + 128, sb, nullptr, a, gx0, gy0, W, sq, nullptr, wnone);
+    layer32<T, P - 6, 1, true, STEP, 0>(w4, sbf + 128, sb, nullptr, a, gx0, gy0, W, sq, nullptr, wnone);
 }
 }  // namespace fused
 
