@@ -242,6 +242,7 @@ def main(argv=None):
     ap.add_argument("--preset", choices=sorted(PRESETS), default="full")
     ap.add_argument("--out", default=None, help="write the JSON report here")
     ap.add_argument("--timing", action="store_true", help="only time fine steps and closure steps")
+    ap.add_argument("--steps", type=int, default=2000, help="timed steps of each kind with --timing")
     ap.add_argument("--calibrate", action="store_true",
                     help="only check grid convergence and predictability of the fine reference")
     args = ap.parse_args(argv)
@@ -251,7 +252,7 @@ def main(argv=None):
         print(msg, flush=True)
 
     if args.timing:
-        step_timing(args.preset, log=log)
+        step_timing(args.preset, steps=args.steps, log=log)
         return 0
     if args.calibrate:
         summary = calibrate(args.preset, log=log)

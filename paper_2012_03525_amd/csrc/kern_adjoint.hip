@@ -92,7 +92,8 @@ __device__ __forceinline__ void fold_ghost(const Coef<T>& c, T r, T u, T v, T bx
     av = fmaT(sv, avg, av);
 }
 
-template <typename T>
+// NP: some face is a wall or a symmetry plane (the periodic build skips those checks)
+template <typename T, bool NP>
 __global__ __launch_bounds__(ANT) void step2d_adjoint_kernel(Coef<T> c, State<T> q, State<T> s, State<T> as,
                                                              State<T> aq, int nbx)
 {
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(ANT) void step2d_adjoint_kernel(Coef<T> c, State<T>
     const int tby = lb / nbx, tbx = lb - tby * nbx;
     const int x0 = tbx * ATX, y0 = tby * ATY;
     const T rho0 = c.rho0;
-    const bool px = c.bc[0] == BC_PERIODIC, py = c.bc[2] == BC_PERIODIC;
+    const bool px = !NP || c.bc[0] == BC_PERIODIC, py = !NP || c.bc[2] == BC_PERIODIC;
     // a position outside the grid across a wall or symmetry face holds no output
     auto outside = [&](int gx, int gy) {
         return (!px && (gx < 0 || gx >= c.nx)) || (!py && (gy < 0 || gy >= c.ny));
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(ANT) void step2d_adjoint_kernel(Coef<T> c, State<T>
         }
         const T dbx = sbx[e + 1] - sbx[e - 1], dby = sby[e + RX] - sby[e - RX];
         T A = fmaT(c.ks, dbx + dby, sp[e]);
-        if (c.nonperiodic) {
+        if (NP) {
             // rho' of a ghost is read by the SAT term of the node it mirrors
             if (!px && rx == 0) A = fmaT(c.ks, sbx[e], A);
             if (!px && rx == c.nx - 1) A = fmaT(-c.ks, sbx[e], A);
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(ANT) void step2d_adjoint_kernel(Coef<T> c, State<T>
                                                fmaT(-c.ks, (bxE - bxW) + (byN - byS), fmaT(c.kr, la, aC)))));
         T au = fmaT(pyx, my, fmaT(pxx, mx, rho * amx));
         T av = fmaT(pyy, my, fmaT(pxy, mx, rho * amy));
-        if (c.nonperiodic) {
+        if (NP) {
             // the ghosts that mirror this node, face by face (-x, +x, -y, +y)
             if (!px && gx == 0) fold_ghost<0>(c, r, u, v, bxC, byC, aC, ar, au, av);
             if (!px && gx == c.nx - 1) fold_ghost<1>(c, r, u, v, bxC, byC, aC, ar, au, av);
@@ -194,7 +195,10 @@ hipError_t launch_adjoint2d(const Coef<T>& c, const State<T>& q, const State<T>&
                             const State<T>& aq, hipStream_t st)
 {
     const int nbx = (c.nx + ATX - 1) / ATX, nby = (c.ny + ATY - 1) / ATY;
-    hipLaunchKernelGGL((step2d_adjoint_kernel<T>), dim3(nbx * nby), dim3(ANT), 0, st, c, q, s, as, aq, nbx);
+    if (c.nonperiodic)
+        hipLaunchKernelGGL((step2d_adjoint_kernel<T, true>), dim3(nbx * nby), dim3(ANT), 0, st, c, q, s, as, aq, nbx);
+    else
+        hipLaunchKernelGGL((step2d_adjoint_kernel<T, false>), dim3(nbx * nby), dim3(ANT), 0, st, c, q, s, as, aq, nbx);
     return hipGetLastError();
 }
 
