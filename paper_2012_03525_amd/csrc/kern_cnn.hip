@@ -609,8 +609,8 @@ hipError_t conv_dispatch(int H, int W, int cin, int cout, int mode, const void* 
 // pairs element e of lane (i, g) in A with element e of lane (n, g) in B, so
 // loading A and B with the same k order gives the product for any layout of
 // k inside a lane.  The first layer is an im2col product: taps 0..7 with
-// their 3 channels and a zero pad make K = 32, tap 8 a K = 16 product,
-// instead of nine K = 16 products.
+// their 3 channels and a zero pad make K = 32, tap 8 a second K = 32 product
+// with zero weights past its channels, instead of nine K = 16 products.
 //
 // LDS layout.  Every activation buffer has the row pitch of layer 0's output
 // (P = 24 slots of 32 channels, 64 bytes): layer l's output position (y, x)
@@ -787,16 +787,20 @@ __device__ __forceinline__ void layer32(const bf16x8 (&wa)[9][NH], const float* 
 // staged input (side SI, 4 halfwords per node: 3 channels and a zero) ->
 // slots of buffer A.  Lane group lg holds k = 8 lg .. 8 lg + 7, i.e. taps
 // 2 lg and 2 lg + 1 with their four halfwords, two 8-byte loads; tap 8 is a
-// K = 16 product whose weights are zero outside lane group 0.
+// second product (below).
+// Tap 8 is a second K = 32 product whose weights are zero outside elements
+// 0..3 of lane group 0: a chain of v_mfma_f32_16x16x16_bf16 and
+// v_mfma_f32_16x16x32_bf16 on one accumulator issued back to back gives
+// wrong accumulators on gfx950 (measured; the compiler inserts no wait
+// states between them), while same-instruction chains are forwarded.
 struct Layer0 {
-    bf16x8 wa0, wa1;
-    bf16x4 wc0, wc1;
+    bf16x8 wa0, wa1, wc0, wc1;
     f32x4 bb0, bb1;
     int offa, offb, l16, lg;
-    __device__ __forceinline__ f32x4 mfma(const bf16x8& w, const bf16x4& wc, const bf16x8& x, const bf16x4& x8,
+    __device__ __forceinline__ f32x4 mfma(const bf16x8& w, const bf16x8& wc, const bf16x8& x, const bf16x8& x8,
                                           const f32x4& b) const
     {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wc, x8, b, 0, 0, 0),
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, __builtin_amdgcn_mfma_f32_16x16x32_bf16(wc, x8, b, 0, 0, 0),
                                                        0, 0, 0);
     }
 };
@@ -986,58 +990,71 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         constexpr int off8 = (SI + 1) * 4;
         L.wa0 = lds8(sw + chunk_at(L.l16, L.lg));
         L.wa1 = lds8(sw + chunk_at(16 + L.l16, L.lg));
-        const bf16x4 zero4 = {0, 0, 0, 0};
-        L.wc0 = L.lg == 0 ? *reinterpret_cast<const bf16x4*>(sw + W0A + L.l16 * 4) : zero4;
-        L.wc1 = L.lg == 0 ? *reinterpret_cast<const bf16x4*>(sw + W0A + (16 + L.l16) * 4) : zero4;
+        // tap-8 weights: elements 0..3 of lane group 0 (channels 0..2 and the zero pad), zero elsewhere
+        auto w8 = [&](int o) {
+            const uint2 h = *reinterpret_cast<const uint2*>(sw + W0A + o * 4);
+            return __builtin_bit_cast(bf16x8, L.lg == 0 ? uint4{h.x, h.y, 0u, 0u} : uint4{0u, 0u, 0u, 0u});
+        };
+        L.wc0 = w8(L.l16);
+        L.wc1 = w8(16 + L.l16);
         L.bb0 = *reinterpret_cast<const f32x4*>(sbf + 4 * L.lg);
         L.bb1 = *reinterpret_cast<const f32x4*>(sbf + 16 + 4 * L.lg);
         const int so0 = store_off(L.l16, L.lg, 0), so1 = store_off(L.l16, L.lg, 1);
-        auto input = [&](int g, bf16x8& x, bf16x4& x8) {
+        auto input = [&](int g, bf16x8& x, bf16x8& x8) {
             const int p = 16 * g + L.l16, py = p / P, px = p - py * P;
             const int base = ((py + 1) * SI + (px + 1)) * 4;
             const uint2 xa = *reinterpret_cast<const uint2*>(sb + base + L.offa);
             const uint2 xb = *reinterpret_cast<const uint2*>(sb + base + L.offb);
-            x8 = *reinterpret_cast<const bf16x4*>(sb + base + off8);
+            const uint2 xc = *reinterpret_cast<const uint2*>(sb + base + off8);
             x = __builtin_bit_cast(bf16x8, uint4{xa.x, xa.y, xb.x, xb.y});
+            x8 = __builtin_bit_cast(bf16x8, uint4{xc.x, xc.y, xc.x, xc.y});  // elements 4..7 meet zero weights
         };
-        // two groups at a time, so the two products of one group do not wait on each other
-        int g = wave;
-        for (; g + NW < NG; g += 2 * NW) {
-            bf16x8 x0, x1;
-            bf16x4 y0, y1;
-            input(g, x0, y0);
-            input(g + NW, x1, y1);
-            const f32x4 c00 = L.mfma(L.wa0, L.wc0, x0, y0, L.bb0), c01 = L.mfma(L.wa1, L.wc1, x0, y0, L.bb1);
-            const f32x4 c10 = L.mfma(L.wa0, L.wc0, x1, y1, L.bb0), c11 = L.mfma(L.wa1, L.wc1, x1, y1, L.bb1);
-            *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so0) = relu4(c00);
-            *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so1) = relu4(c01);
-            *reinterpret_cast<uint2*>(sa + (g + NW) * 16 * SLOT + so0) = relu4(c10);
-            *reinterpret_cast<uint2*>(sa + (g + NW) * 16 * SLOT + so1) = relu4(c11);
-        }
-        if (g < NG) {
-            bf16x8 x0;
-            bf16x4 y0;
-            input(g, x0, y0);
-            const f32x4 c00 = L.mfma(L.wa0, L.wc0, x0, y0, L.bb0), c01 = L.mfma(L.wa1, L.wc1, x0, y0, L.bb1);
-            *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so0) = relu4(c00);
-            *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so1) = relu4(c01);
-        }
-    }
-    {
-        // weights of layers 1..4, chunk e of row e / 4 at its swizzled place
-        uint4* const d = reinterpret_cast<uint4*>(sw + OW1);
-        auto put = [&](int j, const uint4& v) {
-            const int e = tid + j * NT;
-            if (e < NVT) d[(e & ~3) | ((e & 3) ^ ((e >> 3) & 3))] = v;
+        // the wave's groups (wave, wave + NW, ...) in pairs: the operands of
+        // the next pair are loaded before the products of this one, and the
+        // weight stores of layers 1..4 go between the first loads and the
+        // first products (LDS is idle otherwise)
+        constexpr int KMAX = (NG + NW - 1) / NW, PM = (KMAX + 1) / 2;
+        const int K = (NG - wave + NW - 1) / NW;
+        bf16x8 x[2][2], y[2][2];
+        auto in_pair = [&](int pr, int buf) {
+            input(wave + 2 * pr * NW, x[buf][0], y[buf][0]);
+            if (2 * pr + 1 < K) input(wave + (2 * pr + 1) * NW, x[buf][1], y[buf][1]);
         };
-        put(0, wc0);
-        put(1, wc1);
-        put(2, wc2);
-        put(3, wc3);
-        put(4, wc4);
-        put(5, wc5);
-        put(6, wc6);
-        put(7, wc7);
+        in_pair(0, 0);
+        {
+            // weights of layers 1..4, chunk e of row e / 4 at its swizzled place
+            uint4* const d = reinterpret_cast<uint4*>(sw + OW1);
+            auto put = [&](int j, const uint4& v) {
+                const int e = tid + j * NT;
+                if (e < NVT) d[(e & ~3) | ((e & 3) ^ ((e >> 3) & 3))] = v;
+            };
+            put(0, wc0);
+            put(1, wc1);
+            put(2, wc2);
+            put(3, wc3);
+            put(4, wc4);
+            put(5, wc5);
+            put(6, wc6);
+            put(7, wc7);
+        }
+#pragma unroll
+        for (int pr = 0; pr < PM; ++pr) {
+            if (2 * pr < K) {
+                const int bf = pr & 1;
+                if (pr + 1 < PM && 2 * (pr + 1) < K) in_pair(pr + 1, bf ^ 1);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (2 * pr + h < K) {
+                        const int g = wave + (2 * pr + h) * NW;
+                        const f32x4 c0 = L.mfma(L.wa0, L.wc0, x[bf][h], y[bf][h], L.bb0);
+                        const f32x4 c1 = L.mfma(L.wa1, L.wc1, x[bf][h], y[bf][h], L.bb1);
+                        *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so0) = relu4(c0);
+                        *reinterpret_cast<uint2*>(sa + g * 16 * SLOT + so1) = relu4(c1);
+                    }
+                }
+            }
+        }
     }
     __syncthreads();
     const float* const sq = reinterpret_cast<const float*>(lds + LDS_HALF);
