@@ -233,7 +233,7 @@ const char* acm_last_error(void);
 /* ------------------------------------------------------------------------ */
 /* Hundreds of independent single-phase 2D cases of uneven size advance
  * together: each step is ONE launch over the active (case, tile) items,
- * either persistent workgroups popping them from an atomic work queue or one
+ * either persistent workgroups claiming them from atomic work queues or one
  * workgroup per item (acm_batch_opts.mode), applying the same per-node
  * arithmetic as acm_step (results are bitwise equal to running each case
  * alone).  Steps are captured in HIP graphs of `chunk` steps; after every
@@ -254,12 +254,16 @@ typedef struct acm_batch_opts {
     int32_t chunk;         /* steps per captured graph, even; 0 = 500        */
     int32_t blocks;        /* mode 1: persistent workgroups; 0 = CUs x
                               occupancy                                      */
-    int32_t grab;          /* mode 1: queue items taken per atomic; 0 = 4    */
+    int32_t grab;          /* mode 1: items per claim on the work queue once
+                              a workgroup's fixed share is done; 0 = 1       */
     double umax_limit;     /* max |u| above this marks divergence; 0 = 0.3   */
     int32_t mode;          /* 0: one workgroup per (case, tile) item,
                               launched over the item capacity; 1: persistent
-                              workgroups popping the work queue (blocks,
-                              grab).  Results do not depend on the mode.     */
+                              workgroups (blocks) in eight XCD groups, each
+                              group over a contiguous range of the items: a
+                              fixed share per workgroup, then claims of
+                              `grab` items from the group's atomic counter.
+                              Results do not depend on the mode.             */
 } acm_batch_opts;
 
 typedef struct acm_batch_case_status {
@@ -272,7 +276,8 @@ typedef struct acm_batch_case_status {
 
 /* Bytes of device scratch acm_batch_init needs for these cases and options:
  * the case records, the item table (for a case with tile -1 sized for the
- * variant with the most tiles), the item count, two queue counters, the
+ * variant with the most tiles), the item count, the queue counters (eight
+ * group counters 128 bytes apart and a done counter: 1028 bytes), the
  * active list and the health pairs, each part 256-byte aligned.  Returns 0
  * and sets acm_last_error when a case or option is invalid.  Pure host call. */
 size_t acm_batch_scratch_bytes(const acm_batch_case* cases, int32_t ncases, const acm_batch_opts* opts);

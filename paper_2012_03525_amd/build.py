@@ -4,7 +4,10 @@
 
 Flags: -O3, no floating-point contraction (every fma in the kernels is
 written out, which keeps per-node results independent of tile shape and
-calling kernel), packed-FP32 instructions disabled.
+calling kernel), packed-FP32 instructions disabled, and the compiler's
+atomic optimizer off: it turns the batch work queue's one-lane claim into a
+wave-wide form that reads the returned value at once, so a claim issued one
+range ahead would stall its wave for the atomic's full latency.
 """
 from __future__ import annotations
 
@@ -37,6 +40,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(objdir, exist_ok=True)
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
              "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
     procs, objs = [], []
     for src in sources():

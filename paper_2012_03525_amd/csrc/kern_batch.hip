@@ -4,12 +4,14 @@
 // (default): one workgroup per item slot (the item capacity), slots past the
 // active count exit at once, and the hardware dispatcher keeps as many items
 // in flight as occupancy allows.  Mode 1: a persistent grid (CUs x occupancy
-// workgroups) pops items `grab` at a time from an atomic counter; the last
-// workgroup to finish resets the counter for the next launch.  A persistent
-// workgroup waits out each item's load latency in turn, which the dispatcher
-// hides in mode 0 (1.5x faster on the 512-case sweep).  Both run
-// the same tile function as the single-case kernel (tile2d.h), so each
-// case's result is bitwise equal to running it alone.  A
+// workgroups) pops ranges of `grab` items from an atomic counter, one range
+// ahead, and loads the next item's fields into registers while it computes
+// the current one, so its own load latency overlaps its arithmetic; the tile
+// shape is a run-time value there, so one loop serves every case.  The last
+// workgroup to finish resets the counter for the next launch.  Both modes
+// apply the node updates of the single-case kernel (tile2d.h) to the same
+// staged values, so each case's result is bitwise equal to running it
+// alone.  A
 // chunk of steps is captured once as a HIP graph (the item table and its
 // length live in device memory, so the graph survives changes of the active
 // set); after each chunk a health kernel reduces max|u| and a non-finite
@@ -38,12 +40,32 @@ struct BatchCaseDev {
     Coef<T> c;
     State<T> s[2];
     int tile;
+    int tw, th;          // tile width (a power of two) and height
+    unsigned mrx, mdx;   // division by the staged and drho' row strides (div_magic)
 };
 
 // tile shapes of the 2D kernels (same numbering as launch_step2d)
 constexpr int NTILE2D = 6;
 constexpr int TILE_W[NTILE2D] = {64, 32, 64, 16, 128, 32};
 constexpr int TILE_H[NTILE2D] = {4, 8, 8, 16, 4, 16};
+
+// q / d == (q * div_magic(d)) >> 20 for every index q of a staged region:
+// with m = ceil(2^20 / d) the product overshoots q / d by less than
+// q / 2^20 < 1 / d, which never reaches the next integer.  Checked at compile
+// time for every tile shape below.
+constexpr unsigned div_magic(int d) { return ((1u << 20) + (unsigned)d - 1u) / (unsigned)d; }
+constexpr bool div_magic_exact()
+{
+    for (int t = 0; t < NTILE2D; ++t) {
+        const int rx = TILE_W[t] + 4, rxy = rx * (TILE_H[t] + 4), dx = TILE_W[t] + 2;
+        for (int q = 0; q < rxy; ++q) {
+            if ((int)((q * div_magic(rx)) >> 20) != q / rx) return false;
+            if ((int)((q * div_magic(dx)) >> 20) != q / dx) return false;
+        }
+    }
+    return true;
+}
+static_assert(div_magic_exact(), "row division by multiply and shift");
 
 template <typename T>
 constexpr size_t batch_lds_bytes()
@@ -72,33 +94,346 @@ __device__ __forceinline__ void batch_item(const BatchCaseDev<T>& bc, int4 it, i
     }
 }
 
+// ---- mode 1: the tile shape as run-time values --------------------------
+
+// One item's tile; every member is wave-uniform.
+struct ItemTile {
+    int x0, y0, tx, ty;  // origin and size of the tile
+    int rx, rxy;         // staged region: halo 2, row stride rx, rxy values
+    int dx, dxy;         // drho' region: halo 1
+    unsigned mrx, mdx;
+    int interior;        // no node of the staged region is a ghost
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void batch_step_kernel(const BatchCaseDev<T>* __restrict__ cases,
-                                                          const int4* __restrict__ items,
+__device__ __forceinline__ ItemTile item_tile(const BatchCaseDev<T>& bc, int4 it)
+{
+    ItemTile g;
+    g.tx = bc.tw;
+    g.ty = bc.th;
+    g.x0 = it.y * g.tx;
+    g.y0 = it.z * g.ty;
+    g.rx = g.tx + 4;
+    g.rxy = g.rx * (g.ty + 4);
+    g.dx = g.tx + 2;
+    g.dxy = g.dx * (g.ty + 2);
+    g.mrx = bc.mrx;
+    g.mdx = bc.mdx;
+    g.interior = (g.x0 >= 2) && (g.x0 + g.tx + 2 <= bc.c.nx) && (g.y0 >= 2) && (g.y0 + g.ty + 2 <= bc.c.ny);
+    return g;
+}
+
+// Source node of staged index q, with the wall / symmetry face it crosses
+// in x and in y (-1: none), as stage2d maps it.
+template <typename T>
+__device__ __forceinline__ size_t stage_source(const Coef<T>& c, const ItemTile& g, int q, int& fx, int& fy)
+{
+    const int ly = (int)(((unsigned)q * g.mrx) >> 20), lx = q - ly * g.rx;
+    if (g.interior) {
+        fx = fy = -1;
+        return (size_t)(g.y0 + ly - 2) * c.nx + (g.x0 + lx - 2);
+    }
+    const int sx = map_coord(g.x0 + lx - 2, c.nx, c.bc[0], 0, fx);
+    const int sy = map_coord(g.y0 + ly - 2, c.ny, c.bc[2], 2, fy);
+    return (size_t)sy * c.nx + sx;
+}
+
+// A value known to be the same in every lane, held in scalar registers: a
+// per-lane choice between such values stays a register select (the
+// compiler would otherwise turn a choice between two loads into one vector
+// load from a per-lane address, whose wait would also cover the prefetch).
+__device__ __forceinline__ float uni(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uni(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// The ghost rule u_g = fs u + fo of the crossed x face (0, 1) and y face
+// (2, 3), as stage2d applies it.
+template <typename T>
+struct GhostUV {
+    T s[4][2], o[4][2];
+};
+template <typename T>
+__device__ __forceinline__ GhostUV<T> ghost_factors(const Coef<T>& c)
+{
+    GhostUV<T> h;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            h.s[f][a] = uni(c.fs[f][a]);
+            h.o[f][a] = uni(c.fo[f][a]);
+        }
+    return h;
+}
+template <typename T>
+__device__ __forceinline__ void ghost_uv(const GhostUV<T>& h, int fx, int fy, T& u, T& v)
+{
+    if (fx >= 0) {
+        const int f = fx == 0 ? 0 : 1;
+        u = fmaT(f == 0 ? h.s[0][0] : h.s[1][0], u, f == 0 ? h.o[0][0] : h.o[1][0]);
+        v = fmaT(f == 0 ? h.s[0][1] : h.s[1][1], v, f == 0 ? h.o[0][1] : h.o[1][1]);
+    }
+    if (fy >= 0) {
+        const int f = fy == 2 ? 2 : 3;
+        u = fmaT(f == 2 ? h.s[2][0] : h.s[3][0], u, f == 2 ? h.o[2][0] : h.o[3][0]);
+        v = fmaT(f == 2 ? h.s[2][1] : h.s[3][1], v, f == 2 ? h.o[2][1] : h.o[3][1]);
+    }
+}
+
+// Staged values held in registers between their loads and their LDS
+// stores: NPF per thread cover regions of up to 1024 values; the rest (only
+// the 128 x 4 tile has more) are loaded when the item is stored.
+constexpr int NPF = 4;
+template <typename T>
+struct ItemRegs {
+    T r[NPF], u[NPF], v[NPF];
+};
+
+template <typename T>
+__device__ __forceinline__ void item_load(const Coef<T>& c, const State<T>& in, const ItemTile& g, ItemRegs<T>& p)
+{
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+        if (i * 256 >= g.rxy) break;  // wave-uniform
+        const int q = min((int)threadIdx.x + i * 256, g.rxy - 1);
+        int fx, fy;
+        const size_t s = stage_source(c, g, q, fx, fy);
+        p.r[i] = in.r[s];
+        p.u[i] = in.u[s];
+        p.v[i] = in.v[s];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void item_store(const Coef<T>& c, const State<T>& in, const ItemTile& g,
+                                           const ItemRegs<T>& p, T* sr, T* su, T* sv)
+{
+    const GhostUV<T> h = ghost_factors(c);
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+        const int q = threadIdx.x + i * 256;
+        if (q < g.rxy) {
+            T u = p.u[i], v = p.v[i];
+            if (!g.interior) {
+                int fx, fy;
+                (void)stage_source(c, g, q, fx, fy);
+                ghost_uv(h, fx, fy, u, v);
+            }
+            sr[q] = p.r[i];
+            su[q] = u;
+            sv[q] = v;
+        }
+    }
+    for (int q = threadIdx.x + NPF * 256; q < g.rxy; q += 256) {
+        int fx, fy;
+        const size_t s = stage_source(c, g, q, fx, fy);
+        const T r = in.r[s];
+        T u = in.u[s], v = in.v[s];
+        ghost_uv(h, fx, fy, u, v);
+        sr[q] = r;
+        su[q] = u;
+        sv[q] = v;
+    }
+}
+
+// drho' on the tile plus a one-node ring (as rho_ring2d), then the momentum
+// update and stores of the tile's nodes (as momentum2d).
+template <typename T>
+__device__ __forceinline__ void item_ring(const Coef<T>& c, const ItemTile& g, const T* sr, const T* su,
+                                          const T* sv, T* srn)
+{
+    for (int q = threadIdx.x; q < g.dxy; q += 256) {
+        const int ly = (int)(((unsigned)q * g.mdx) >> 20), lx = q - ly * g.dx;
+        int ex = lx + 1, ey = ly + 1;
+        if (!g.interior && c.nonperiodic) {
+            const int gx = mirror_coord(g.x0 + lx - 1, c.nx, c.bc[0]);
+            const int gy = mirror_coord(g.y0 + ly - 1, c.ny, c.bc[2]);
+            ex = min(max(gx - g.x0 + 2, 1), g.dx);
+            ey = min(max(gy - g.y0 + 2, 1), g.ty + 2);
+        }
+        srn[q] = rho_new_2d_at<T>(c, sr, su, sv, ey * g.rx + ex, g.rx);
+    }
+}
+
+// Momentum update of the tile's nodes (as momentum2d), at most two per
+// thread (every tile has at most 512 nodes).  The results stay in registers
+// and are stored during the next item, before that item's successor is
+// prefetched: stores count on the same in-order counter as loads, so stores
+// issued after the prefetch would make the wait for the prefetched values
+// wait for them as well.
+constexpr int max_tile_nodes()
+{
+    int m = 0;
+    for (int t = 0; t < NTILE2D; ++t) m = TILE_W[t] * TILE_H[t] > m ? TILE_W[t] * TILE_H[t] : m;
+    return m;
+}
+static_assert(max_tile_nodes() <= 2 * 256, "two nodes per thread");
+
+template <typename T>
+struct ItemOut {
+    T r[2], u[2], v[2];
+    int o[2];  // grid index of the node, -1: none
+};
+
+template <typename T>
+__device__ __forceinline__ void item_momentum(const Coef<T>& c, const ItemTile& g, const T* sr, const T* su,
+                                              const T* sv, const T* srn, ItemOut<T>& res)
+{
+    const int sh = __builtin_ctz((unsigned)g.tx);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int q = threadIdx.x + i * 256;
+        const int ly = q >> sh, lx = q & (g.tx - 1);
+        const int gx = g.x0 + lx, gy = g.y0 + ly;
+        res.o[i] = -1;
+        if (q < g.tx * g.ty && gx < c.nx && gy < c.ny) {
+            momentum_node2d_at<T>(c, sr, su, sv, srn, (ly + 2) * g.rx + (lx + 2), (ly + 1) * g.dx + (lx + 1), gy,
+                                  g.rx, g.dx, res.r[i], res.u[i], res.v[i]);
+            res.o[i] = gy * c.nx + gx;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void item_write(const State<T>& out, const ItemOut<T>& res)
+{
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (res.o[i] >= 0) {
+            out.r[res.o[i]] = res.r[i];
+            out.u[res.o[i]] = res.u[i];
+            out.v[res.o[i]] = res.v[i];
+        }
+    }
+}
+
+// Mode 1: persistent workgroups.  The active items are split into one
+// contiguous range per XCD group (workgroup b runs on XCD b mod 8, so
+// neighbouring tiles of a case meet in that XCD's L2).  Within its group's
+// range a workgroup first takes a fixed share, every Gx-th item from its
+// own index (Gx workgroups in the group), and then claims the rest `grab`
+// items at a time from the group's counter.  A claim is issued one range
+// ahead (register `pend` of thread 0) and published through LDS when the
+// current range runs out; the next item's fields are loaded into registers
+// while the current item computes, and each item's results are stored
+// during the item after it.  Counters sit 128 bytes apart
+// (QSTRIDE ints); queue[QDONE] counts the workgroups that have left, and the
+// last one resets every counter for the next launch.
+constexpr int QGROUPS = 8, QSTRIDE = 32, QDONE = QGROUPS * QSTRIDE;
+constexpr size_t QUEUE_BYTES = (QDONE + 1) * sizeof(int);
+
+// The case records and the item table do not change during a launch; read
+// through the constant address space they stay scalar loads inside the loop
+// (through a generic pointer the compiler cannot rule out that this
+// launch's stores reach them, and reads them with vector loads whose waits
+// would also wait for the prefetched fields).  The host pass, which only
+// checks the kernel body, has no such address space.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using ConstCases = const __attribute__((address_space(4))) BatchCaseDev<T>*;
+using ConstItems = const __attribute__((address_space(4))) int4*;
+#else
+template <typename T>
+using ConstCases = const BatchCaseDev<T>*;
+using ConstItems = const int4*;
+#endif
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_step_kernel(const BatchCaseDev<T>* __restrict__ cases_g,
+                                                          const int4* __restrict__ items_g,
                                                           const int* __restrict__ nitems, int* queue, int parity,
                                                           int grab)
 {
     __shared__ __align__(16) char smem[batch_lds_bytes<T>()];
-    __shared__ int s_first;
+    __shared__ int s_first, s_next;
+    const ConstCases<T> cases = (ConstCases<T>)cases_g;
+    const ConstItems items = (ConstItems)items_g;
     const int n = *nitems;
-    for (;;) {
-        if (threadIdx.x == 0) s_first = atomicAdd(&queue[0], grab);
+    const int tid = threadIdx.x;
+    const int G = gridDim.x, b = blockIdx.x;
+    const int ng = min(QGROUPS, G), x = b % ng, j = b / ng;
+    const int gx = (G - x + ng - 1) / ng;                   // workgroups in group x
+    const int lo = (int)((long long)n * x / ng), hi = (int)((long long)n * (x + 1) / ng);
+    const int k = (hi - lo) / gx;                            // fixed share per workgroup
+    const int tb = lo + k * gx;                              // first claimed item
+    int* const qx = queue + x * QSTRIDE;
+    int t = lo + j, stride = gx, end = tb;
+    int pend = 0;
+    if (tid == 0) pend = atomicAdd(qx, grab);
+    if (t >= end) {  // no fixed share: take the first claim now
+        if (tid == 0) s_first = pend;
         __syncthreads();
-        const int first = s_first;
-        __syncthreads();
-        if (first >= n) break;
-        const int last = min(first + grab, n);
-        for (int t = first; t < last; ++t) {
-            const int4 it = items[t];
-            batch_item<T>(cases[it.x], it, parity, smem);
-            __syncthreads();  // the next item reuses the LDS tile
-        }
+        t = tb + __builtin_amdgcn_readfirstlane(s_first);
+        stride = 1;
+        end = min(t + grab, hi);
+        if (t < hi && tid == 0) pend = atomicAdd(qx, grab);
     }
-    if (threadIdx.x == 0) {
-        const int d = atomicAdd(&queue[1], 1);
-        if (d == (int)gridDim.x - 1) {  // every workgroup has left the loop: reset for the next launch
-            queue[0] = 0;
-            queue[1] = 0;
+    if (t < end) {
+        const BatchCaseDev<T>* bc = cases + items[t].x;
+        ItemTile g = item_tile(*bc, items[t]);
+        ItemRegs<T> p;
+        item_load(bc->c, bc->s[parity], g, p);
+        const BatchCaseDev<T>* bcw = bc;  // case of the results held in `res`
+        ItemOut<T> res;
+        res.o[0] = res.o[1] = -1;
+        for (;;) {
+            const bool inrange = t + stride < end;
+            int tn = t + stride;
+            const BatchCaseDev<T>* bcn = bc;
+            ItemTile gn = g;
+            if (inrange) {  // the next item is known: read its records while this one's values arrive
+                const int4 itn = items[tn];
+                bcn = cases + itn.x;
+                gn = item_tile(*bcn, itn);
+            } else if (tid == 0) {
+                s_next = pend;
+            }
+            T* sr = reinterpret_cast<T*>(smem);
+            T* su = sr + g.rxy;
+            T* sv = su + g.rxy;
+            T* srn = sv + g.rxy;
+            item_store(bc->c, bc->s[parity], g, p, sr, su, sv);
+            __syncthreads();
+            if (!inrange) {
+                tn = tb + __builtin_amdgcn_readfirstlane(s_next);
+                stride = 1;
+                end = min(tn + grab, hi);
+                if (tn < hi) {
+                    if (tid == 0) pend = atomicAdd(qx, grab);
+                    const int4 itn = items[tn];
+                    bcn = cases + itn.x;
+                    gn = item_tile(*bcn, itn);
+                }
+            }
+            const bool more = tn < end;
+            item_write(bcw->s[parity ^ 1], res);  // the previous item's results
+            if (more)  // the next item's loads are in flight during this item's arithmetic
+                item_load(bcn->c, bcn->s[parity], gn, p);
+            item_ring(bc->c, g, sr, su, sv, srn);
+            __syncthreads();
+            item_momentum(bc->c, g, sr, su, sv, srn, res);
+            bcw = bc;
+            if (!more) break;
+            __syncthreads();  // the next item reuses the LDS tile
+            t = tn;
+            bc = bcn;
+            g = gn;
+        }
+        item_write(bcw->s[parity ^ 1], res);
+    }
+    if (tid == 0) {
+        const int d = atomicAdd(&queue[QDONE], 1);
+        if (d == G - 1) {  // every workgroup has left the loop: reset for the next launch
+            for (int q = 0; q < QGROUPS; ++q) queue[q * QSTRIDE] = 0;
+            queue[QDONE] = 0;
         }
     }
 }
@@ -181,7 +516,7 @@ struct acm_batch {
     int precision = ACM_F32;
     int chunk = 500;
     int blocks = 0;
-    int grab = 4;
+    int grab = 1;
     int mode = 0;   // 0 one workgroup per item, 1 persistent work queue
     double umax_limit = 0.3;
     hipStream_t stream = nullptr;
@@ -240,7 +575,7 @@ BatchLayout batch_layout(int ncases, size_t max_items, int precision)
     L.items = L.cases + align256(rec * (size_t)ncases);
     L.nitems = L.items + align256(sizeof(int4) * std::max<size_t>(1, max_items));
     L.queue = L.nitems + 256;
-    L.active = L.queue + 256;
+    L.active = L.queue + align256(QUEUE_BYTES);
     L.health = L.active + align256(sizeof(int) * (size_t)ncases);
     L.total = L.health + align256(2 * sizeof(double) * (size_t)ncases);
     return L;
@@ -257,6 +592,10 @@ hipError_t upload_cases(acm_batch* b, const acm_batch_case* cases)
             h[i].s[s] = State<T>{static_cast<T*>(f[s]->drho), static_cast<T*>(f[s]->u), static_cast<T*>(f[s]->v),
                                  nullptr, nullptr};
         h[i].tile = b->tile[i];
+        h[i].tw = TILE_W[b->tile[i]];
+        h[i].th = TILE_H[b->tile[i]];
+        h[i].mrx = div_magic(TILE_W[b->tile[i]] + 4);
+        h[i].mdx = div_magic(TILE_W[b->tile[i]] + 2);
     }
     hipError_t e = hipMemcpyAsync(b->dcases, h.data(), sizeof(BatchCaseDev<T>) * b->n, hipMemcpyHostToDevice,
                                   b->stream);
@@ -431,7 +770,7 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
     b->n = ncases;
     b->precision = prec;
     b->chunk = chunk;
-    b->grab = (opts && opts->grab > 0) ? opts->grab : 4;
+    b->grab = (opts && opts->grab > 0) ? opts->grab : 1;
     b->mode = mode;
     b->umax_limit = (opts && opts->umax_limit > 0) ? opts->umax_limit : 0.3;
     b->stream = static_cast<hipStream_t>(stream);
@@ -462,7 +801,7 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
     b->hhealth.resize(2 * (size_t)ncases);
     // queue counters start at zero (outside any graph; the persistent kernel
     // resets them itself after every launch)
-    hipError_t e = hipMemsetAsync(b->dqueue, 0, 2 * sizeof(int), b->stream);
+    hipError_t e = hipMemsetAsync(b->dqueue, 0, QUEUE_BYTES, b->stream);
     if (e == hipSuccess) e = (prec == ACM_F64) ? upload_cases<double>(b, cases) : upload_cases<float>(b, cases);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&b->ev_start);

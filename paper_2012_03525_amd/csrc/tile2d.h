@@ -1,6 +1,6 @@
 // 2D fused SMAME tile (continuity then momentum) shared by the single-case
-// kernel and the batched persistent kernel, so both produce identical bits
-// for every node.  See kern_step.hip for the arithmetic.
+// kernel and the batched kernels, so all produce identical bits for every
+// node.  See kern_step.hip for the arithmetic.
 #pragma once
 
 #include "acm_internal.h"
@@ -32,15 +32,20 @@ __device__ __forceinline__ T mdiff(T rp, T up, T rm, T um, T rho0)
     return fmaT(rho0, up - um, fmaT(rp, up, -(rm * um)));
 }
 
-// Continuity update at R-region index e (2D).
-template <typename T, int RX>
-__device__ __forceinline__ T rho_new_2d(const Coef<T>& c, const T* sr, const T* su, const T* sv, int e)
+// Continuity update at R-region index e (2D), R-region row stride RX.
+template <typename T>
+__device__ __forceinline__ T rho_new_2d_at(const Coef<T>& c, const T* sr, const T* su, const T* sv, int e, int RX)
 {
     const T rc = sr[e];
     const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
     const T div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) + mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0);
     const T lap = ((rE + rW) + (rN + rS)) - T(4) * rc;
     return fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
+}
+template <typename T, int RX>
+__device__ __forceinline__ T rho_new_2d(const Coef<T>& c, const T* sr, const T* su, const T* sv, int e)
+{
+    return rho_new_2d_at<T>(c, sr, su, sv, e, RX);
 }
 
 // Stage fields (drho, u, v) of the (TX+4)x(TY+4) region into LDS.  Every
@@ -120,12 +125,14 @@ __device__ __forceinline__ void rho_ring2d(const Coef<T>& c, int x0, int y0, boo
     }
 }
 
-// Momentum update of one node: R-region index e, drho'-region index d, grid
-// row gy (for the per-row force).  Returns drho', u', v'.  Shared by the tile
-// kernels and by the fused closure kernel, so all give identical bits.
-template <typename T, int RX, int DX>
-__device__ __forceinline__ void momentum_node2d(const Coef<T>& c, const T* sr, const T* su, const T* sv,
-                                                const T* srn, int e, int d, int gy, T& rn_out, T& u_out, T& v_out)
+// Momentum update of one node: R-region index e (row stride RX), drho'-region
+// index d (row stride DX), grid row gy (for the per-row force).  Returns
+// drho', u', v'.  Shared by the tile kernels, the batched kernels and the
+// fused closure kernel, so all give identical bits.
+template <typename T>
+__device__ __forceinline__ void momentum_node2d_at(const Coef<T>& c, const T* sr, const T* su, const T* sv,
+                                                   const T* srn, int e, int d, int gy, int RX, int DX, T& rn_out,
+                                                   T& u_out, T& v_out)
 {
     const T rc = sr[e], uc = su[e], vc = sv[e];
     const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
@@ -157,6 +164,12 @@ __device__ __forceinline__ void momentum_node2d(const Coef<T>& c, const T* sr, c
     u_out = fmaT(fmaT(-uc, drn, dmx), inv, uc);
     v_out = fmaT(fmaT(-vc, drn, dmy), inv, vc);
 }
+template <typename T, int RX, int DX>
+__device__ __forceinline__ void momentum_node2d(const Coef<T>& c, const T* sr, const T* su, const T* sv,
+                                                const T* srn, int e, int d, int gy, T& rn_out, T& u_out, T& v_out)
+{
+    momentum_node2d_at<T>(c, sr, su, sv, srn, e, d, gy, RX, DX, rn_out, u_out, v_out);
+}
 
 // Momentum update and store for the nodes of the tile.
 template <typename T, int TX, int TY, int NT>
@@ -180,7 +193,7 @@ __device__ __forceinline__ void momentum2d(const Coef<T>& c, const State<T>& out
 
 // One 2D tile: stage, drho' ring, momentum.  smem must hold
 // tile2d_lds_bytes<T,TX,TY>() bytes.  Called by the single-case kernel and
-// by the batched persistent kernel.
+// by the batched per-item kernel.
 template <typename T, int TX, int TY, int NT>
 __device__ __forceinline__ void tile2d(const Coef<T>& c, const State<T>& in, const State<T>& out,
                                        int x0, int y0, char* smem)

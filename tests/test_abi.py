@@ -249,8 +249,9 @@ def test_batch_init_rejects_bad_cases_without_touching_the_gpu():
 
 def test_batch_scratch_bytes_follow_the_documented_layout():
     """Case records, item table (tile -1: the variant with the most tiles),
-    item count, two queue counters, active list and health pairs, each part
-    rounded up to 256 bytes."""
+    item count, queue counters (eight group counters 128 bytes apart and a
+    done counter), active list and health pairs, each part rounded up to
+    256 bytes."""
     a = lambda x: (x + 255) // 256 * 256
     tw, th = [64, 32, 64, 16, 128, 32], [4, 8, 8, 16, 4, 16]
     shapes = [(32, 32, 0), (48, 64, 3), (256, 256, -1), (17, 9, 5)]
@@ -266,7 +267,7 @@ def test_batch_scratch_bytes_follow_the_documented_layout():
     opts = acm.BatchOpts(20, 0, 0, 0.0)
     rec = ctypes.sizeof(ctypes.c_void_p)  # record size is checked through the total below
     got = acm.lib().acm_batch_scratch_bytes(arr, n, ctypes.byref(opts))
-    rest = a(16 * items) + 256 + 256 + a(4 * n) + a(16 * n)
+    rest = a(16 * items) + 256 + a(4 * (8 * 32 + 1)) + a(4 * n) + a(16 * n)
     assert got > rest and (got - rest) % 256 == 0 and (got - rest) // n >= rec
 
 

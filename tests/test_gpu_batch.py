@@ -56,11 +56,19 @@ def spec_state(nx, ny, seed):
     return f32(inputs.seeded_state((ny, nx), seed=seed, scale_u=0.03, scale_r=1e-3))
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_batch_bitwise_equals_single_runs(acm_mod, mode):
-    cfgs = [case_cfg(acm_mod, nx, ny, kind, 0.04) for nx, ny, kind, _, _ in SPECS]
+@pytest.mark.parametrize("mode,grab,blocks,prec", [(0, 0, 0, "f32"), (1, 0, 0, "f32"), (1, 4, 0, "f32"),
+                                                  (1, 3, 0, "f32"), (1, 2, 5, "f32"), (1, 1, 13, "f32"),
+                                                  (0, 0, 0, "f64"), (1, 3, 0, "f64")])
+def test_batch_bitwise_equals_single_runs(acm_mod, mode, grab, blocks, prec):
+    """Every tile shape, walls, symmetry planes and ragged grids.  Mode 1 with
+    the default grid (most workgroups get no fixed share and claim at once),
+    claims of three or four items (ranges that end inside a case), five
+    workgroups (five groups of one, hundreds of items each in fixed shares)
+    and thirteen (eight groups of one or two workgroups)."""
+    cfgs = [case_cfg(acm_mod, nx, ny, kind, 0.04, precision=prec) for nx, ny, kind, _, _ in SPECS]
     states = [spec_state(nx, ny, 100 + i) for i, (nx, ny, _, _, _) in enumerate(SPECS)]
-    b = acm_mod.Batch(cfgs, states, [s[4] for s in SPECS], tiles=[s[3] for s in SPECS], chunk=20, mode=mode)
+    b = acm_mod.Batch(cfgs, states, [s[4] for s in SPECS], tiles=[s[3] for s in SPECS], chunk=20, mode=mode,
+                      grab=grab, blocks=blocks)
     left = b.run()
     assert left == 0
     for i, (nx, ny, kind, tile, nsteps) in enumerate(SPECS):
