@@ -255,14 +255,14 @@ typedef struct acm_batch_opts {
     int32_t blocks;        /* mode 1: persistent workgroups; 0 = CUs x
                               occupancy                                      */
     int32_t grab;          /* mode 1: items per claim on the work queue once
-                              a workgroup's fixed share is done; 0 = 1       */
+                              a workgroup's fixed share is done; 0 = 2       */
     double umax_limit;     /* max |u| above this marks divergence; 0 = 0.3   */
     int32_t mode;          /* 0: one workgroup per (case, tile) item,
                               launched over the item capacity; 1: persistent
                               workgroups (blocks) in eight XCD groups, each
-                              group over a contiguous range of the items: a
-                              fixed share per workgroup, then claims of
-                              `grab` items from the group's atomic counter.
+                              group over a contiguous range of the items:
+                              fixed shares over half the range, then claims
+                              of `grab` items from the group's counter.
                               Results do not depend on the mode.             */
 } acm_batch_opts;
 

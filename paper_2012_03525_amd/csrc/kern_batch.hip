@@ -319,8 +319,10 @@ __device__ __forceinline__ void item_write(const State<T>& out, const ItemOut<T>
 // contiguous range per XCD group (workgroup b runs on XCD b mod 8, so
 // neighbouring tiles of a case meet in that XCD's L2).  Within its group's
 // range a workgroup first takes a fixed share, every Gx-th item from its
-// own index (Gx workgroups in the group), and then claims the rest `grab`
-// items at a time from the group's counter.  A claim is issued one range
+// own index (Gx workgroups in the group; the shares cover half the range),
+// and then claims the rest `grab` items at a time from the group's counter:
+// workgroups of one launch run at unequal speeds (later-dispatched waves
+// lose issue priority), which only the claimed half can even out.  A claim is issued one range
 // ahead (register `pend` of thread 0) and published through LDS when the
 // current range runs out; the next item's fields are loaded into registers
 // while the current item computes, and each item's results are stored
@@ -346,8 +348,12 @@ using ConstCases = const BatchCaseDev<T>*;
 using ConstItems = const int4*;
 #endif
 
+// Registers capped for eight (FP32) or four (FP64) waves per SIMD: at 69
+// VGPRs the occupancy query reported seven FP32 workgroups per CU while the
+// hardware kept six resident, so a grid sized from the query ran its last
+// workgroups as a second round.
 template <typename T>
-__global__ __launch_bounds__(256) void batch_step_kernel(const BatchCaseDev<T>* __restrict__ cases_g,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void batch_step_kernel(const BatchCaseDev<T>* __restrict__ cases_g,
                                                           const int4* __restrict__ items_g,
                                                           const int* __restrict__ nitems, int* queue, int parity,
                                                           int grab)
@@ -362,7 +368,7 @@ __global__ __launch_bounds__(256) void batch_step_kernel(const BatchCaseDev<T>* 
     const int ng = min(QGROUPS, G), x = b % ng, j = b / ng;
     const int gx = (G - x + ng - 1) / ng;                   // workgroups in group x
     const int lo = (int)((long long)n * x / ng), hi = (int)((long long)n * (x + 1) / ng);
-    const int k = (hi - lo) / gx;                            // fixed share per workgroup
+    const int k = (hi - lo) / (2 * gx);                      // fixed share: half the range
     const int tb = lo + k * gx;                              // first claimed item
     int* const qx = queue + x * QSTRIDE;
     int t = lo + j, stride = gx, end = tb;
@@ -516,7 +522,7 @@ struct acm_batch {
     int precision = ACM_F32;
     int chunk = 500;
     int blocks = 0;
-    int grab = 1;
+    int grab = 2;
     int mode = 0;   // 0 one workgroup per item, 1 persistent work queue
     double umax_limit = 0.3;
     hipStream_t stream = nullptr;
@@ -770,7 +776,7 @@ acm_status acm_batch_init(const acm_batch_case* cases, int32_t ncases, const acm
     b->n = ncases;
     b->precision = prec;
     b->chunk = chunk;
-    b->grab = (opts && opts->grab > 0) ? opts->grab : 1;
+    b->grab = (opts && opts->grab > 0) ? opts->grab : 2;
     b->mode = mode;
     b->umax_limit = (opts && opts->umax_limit > 0) ? opts->umax_limit : 0.3;
     b->stream = static_cast<hipStream_t>(stream);
