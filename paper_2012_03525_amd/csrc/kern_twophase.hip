@@ -22,6 +22,10 @@
 // intermediate take the value at their mirror node for walls and symmetry
 // planes, so they are computed there; phi and phi* ghosts across a wall
 // then take the wetting rule of Sec. 2 (identity for a 90 degree angle).
+// LDS: phi^n and mu^n are last read in the phi* phase (which also takes
+// each output node's phi^n and surface-tension force into registers), so
+// mu* and drho' are written over them afterwards; 18.7 KB per 32 x 16 tile
+// lets eight workgroups share a CU.
 #include "acm_internal.h"
 #include "kern_axisym.h"
 #include "tile2d.h"
@@ -37,6 +41,7 @@ struct Shape2P {
     static constexpr int MX = TX + 6, MY = TY + 6, MXY = MX * MY;   // mu, halo 3
     static constexpr int RX = TX + 4, RY = TY + 4, RXY = RX * RY;   // flow fields / phi*, halo 2
     static constexpr int DX = TX + 2, DY = TY + 2, DXY = DX * DY;   // mu*, drho', halo 1
+    static_assert(DXY <= PXY && DXY <= MXY, "mu* and drho' fit in the phi and mu regions");
 };
 
 // isotropic Laplacian numerator: 4 (E+W+N+S) + (NE+NW+SE+SW) - 20 C
@@ -105,12 +110,14 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
 {
     using S = Shape2P<TX, TY>;
     constexpr int PX = S::PX, MX = S::MX, RX = S::RX, DX = S::DX;
-    __shared__ T sp[S::PXY];                          // phi^n
-    __shared__ T smu[S::MXY];                         // mu^n
+    __shared__ T sp[S::PXY];                          // phi^n, then mu*
+    __shared__ T smu[S::MXY];                         // mu^n, then drho'
     __shared__ T sr[S::RXY], su[S::RXY], sv[S::RXY];  // drho, u, v
     __shared__ T sps[S::RXY];                         // phi*
-    __shared__ T sms[S::DXY];                         // mu*
-    __shared__ T srn[S::DXY];                         // drho'
+    T* const sms = sp;
+    T* const srn = smu;
+    constexpr int NQ = (TX * TY + NT - 1) / NT;       // output nodes per thread
+    T pcq[NQ], fsx[NQ], fsy[NQ];                      // phi^n and surface-tension force there
 
     const int lb = [&] {
         constexpr int NX = 8;
@@ -132,29 +139,48 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         constexpr int NP = (S::PXY + NT - 1) / NT, NR = (S::RXY + NT - 1) / NT;
         T pv[NP], rv[NR], uv[NR], vv[NR];
         int fxs[NR], fys[NR];
+        if (interior) {  // no ghost in either region: plain offsets
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            const int q = min(tid + i * NT, S::PXY - 1);
-            const int ly = q / PX, lx = q - ly * PX;
-            int fx, fy;
-            const int sx = map_coord(x0 + lx - 4, nx, c.bc[0], 0, fx);
-            const int sy = map_coord(y0 + ly - 4, ny, c.bc[2], 2, fy);
-            pv[i] = in.phi[(size_t)sy * nx + sx];
-            if (c.wet) {  // wetting rule across wall faces, x then y
-                if (fx >= 0) pv[i] = wet_ghost(pv[i], wet_b(c, fx));
-                if (fy >= 0) pv[i] = wet_ghost(pv[i], wet_b(c, fy));
+            for (int i = 0; i < NP; ++i) {
+                const int q = min(tid + i * NT, S::PXY - 1);
+                const int ly = q / PX, lx = q - ly * PX;
+                pv[i] = in.phi[(size_t)(y0 + ly - 4) * nx + (x0 + lx - 4)];
             }
-        }
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const int q = min(tid + i * NT, S::RXY - 1);
-            const int ly = q / RX, lx = q - ly * RX;
-            const int sx = map_coord(x0 + lx - 2, nx, c.bc[0], 0, fxs[i]);
-            const int sy = map_coord(y0 + ly - 2, ny, c.bc[2], 2, fys[i]);
-            const size_t s = (size_t)sy * nx + sx;
-            rv[i] = in.r[s];
-            uv[i] = in.u[s];
-            vv[i] = in.v[s];
+            for (int i = 0; i < NR; ++i) {
+                const int q = min(tid + i * NT, S::RXY - 1);
+                const int ly = q / RX, lx = q - ly * RX;
+                const size_t s = (size_t)(y0 + ly - 2) * nx + (x0 + lx - 2);
+                rv[i] = in.r[s];
+                uv[i] = in.u[s];
+                vv[i] = in.v[s];
+                fxs[i] = fys[i] = -1;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const int q = min(tid + i * NT, S::PXY - 1);
+                const int ly = q / PX, lx = q - ly * PX;
+                int fx, fy;
+                const int sx = map_coord(x0 + lx - 4, nx, c.bc[0], 0, fx);
+                const int sy = map_coord(y0 + ly - 4, ny, c.bc[2], 2, fy);
+                pv[i] = in.phi[(size_t)sy * nx + sx];
+                if (c.wet) {  // wetting rule across wall faces, x then y
+                    if (fx >= 0) pv[i] = wet_ghost(pv[i], wet_b(c, fx));
+                    if (fy >= 0) pv[i] = wet_ghost(pv[i], wet_b(c, fy));
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int q = min(tid + i * NT, S::RXY - 1);
+                const int ly = q / RX, lx = q - ly * RX;
+                const int sx = map_coord(x0 + lx - 2, nx, c.bc[0], 0, fxs[i]);
+                const int sy = map_coord(y0 + ly - 2, ny, c.bc[2], 2, fys[i]);
+                const size_t s = (size_t)sy * nx + sx;
+                rv[i] = in.r[s];
+                uv[i] = in.u[s];
+                vv[i] = in.v[s];
+            }
         }
 #pragma unroll
         for (int i = 0; i < NP; ++i)
@@ -181,7 +207,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
     }
     __syncthreads();
 
-    // ---- mu^n on tile+3, drho' on tile+1
+    // ---- mu^n on tile+3
     for (int q = tid; q < S::MXY; q += NT) {
         const int ly = q / MX, lx = q - ly * MX;
         int ex = lx + 1, ey = ly + 1;  // phi-region coordinates
@@ -190,26 +216,6 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
             ey = ghost_src(ly, 3, y0, ny, c.bc[2], 0, S::MY - 1) + 1;
         }
         smu[q] = chem_a<T, PX, AXI>(c, sp, ey * PX + ex, inv_radius<AXI, T>(y0 + ey - 4));
-    }
-    for (int q = tid; q < S::DXY; q += NT) {
-        const int ly = q / DX, lx = q - ly * DX;
-        int ex = lx + 1, ey = ly + 1;  // flow-region coordinates
-        if (mirror) {
-            ex = ghost_src(lx, 1, x0, nx, c.bc[0], 0, DX - 1) + 1;
-            ey = ghost_src(ly, 1, y0, ny, c.bc[2], 0, S::DY - 1) + 1;
-        }
-        const int e = ey * RX + ex;
-        const T rc = sr[e];
-        const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
-        T div, lap;
-        if constexpr (AXI) {  // cylindrical flux forms (kern_axisym.h)
-            axi_continuity(c.rho0, T(y0 + ey - 2), inv_radius<AXI, T>(y0 + ey - 2), rc, rE, rW, rN, rS, su[e + 1],
-                           su[e - 1], sv[e], sv[e + RX], sv[e - RX], div, lap);
-        } else {
-            div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) + mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0);
-            lap = ((rE + rW) + (rN + rS)) - T(4) * rc;
-        }
-        srn[q] = fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
     }
     __syncthreads();
 
@@ -237,9 +243,22 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         }
         sps[q] = val;
     }
+    // phi^n and the surface-tension force -dt phi G_iso mu at this thread's
+    // output nodes, while phi^n and mu^n are still in LDS
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int q = min(tid + k * NT, TX * TY - 1);
+        const int ly = q / TX, lx = q - ly * TX;
+        const int ep = (ly + 4) * PX + (lx + 4);  // phi region
+        const int em = (ly + 3) * MX + (lx + 3);  // mu region
+        const T pc = sp[ep];
+        pcq[k] = pc;
+        fsx[k] = -c.dt * pc * (gisox_num<T, MX>(smu, em) * c.gi);
+        fsy[k] = -c.dt * pc * (gisoy_num<T, MX>(smu, em) * c.gi);
+    }
     __syncthreads();
 
-    // ---- mu* on tile+1
+    // ---- mu* on tile+1 (over phi^n) and drho' on tile+1 (over mu^n)
     for (int q = tid; q < S::DXY; q += NT) {
         const int ly = q / DX, lx = q - ly * DX;
         int ex = lx + 1, ey = ly + 1;  // phi*-region coordinates
@@ -249,18 +268,39 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         }
         sms[q] = chem_a<T, RX, AXI>(c, sps, ey * RX + ex, inv_radius<AXI, T>(y0 + ey - 2));
     }
+    for (int q = tid; q < S::DXY; q += NT) {
+        const int ly = q / DX, lx = q - ly * DX;
+        int ex = lx + 1, ey = ly + 1;  // flow-region coordinates
+        if (mirror) {
+            ex = ghost_src(lx, 1, x0, nx, c.bc[0], 0, DX - 1) + 1;
+            ey = ghost_src(ly, 1, y0, ny, c.bc[2], 0, S::DY - 1) + 1;
+        }
+        const int e = ey * RX + ex;
+        const T rc = sr[e];
+        const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
+        T div, lap;
+        if constexpr (AXI) {  // cylindrical flux forms (kern_axisym.h)
+            axi_continuity(c.rho0, T(y0 + ey - 2), inv_radius<AXI, T>(y0 + ey - 2), rc, rE, rW, rN, rS, su[e + 1],
+                           su[e - 1], sv[e], sv[e + RX], sv[e - RX], div, lap);
+        } else {
+            div = mdiff(rE, su[e + 1], rW, su[e - 1], c.rho0) + mdiff(rN, sv[e + RX], rS, sv[e - RX], c.rho0);
+            lap = ((rE + rW) + (rN + rS)) - T(4) * rc;
+        }
+        srn[q] = fmaT(-c.cg, div, fmaT(c.kr, lap, rc));
+    }
     __syncthreads();
 
     // ---- outputs on the tile
     const T rho0 = c.rho0, cs2 = c.cs2;
-    for (int q = tid; q < TX * TY; q += NT) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int q = tid + k * NT;
+        if (q >= TX * TY) break;
         const int ly = q / TX, lx = q - ly * TX;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= nx || gy >= ny) continue;
         const int e = (ly + 2) * RX + (lx + 2);   // flow / phi* region
         const int d = (ly + 1) * DX + (lx + 1);   // drho' / mu* region
-        const int ep = (ly + 4) * PX + (lx + 4);  // phi region
-        const int em = (ly + 3) * MX + (lx + 3);  // mu region
         // flow
         const T rc = sr[e], uc = su[e], vc = sv[e];
         const T rE = sr[e + 1], rW = sr[e - 1], rN = sr[e + RX], rS = sr[e - RX];
@@ -286,10 +326,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         const T sx = (srn[d + 1] - srn[d - 1]) - (rE - rW);
         const T sy = (srn[d + DX] - srn[d - DX]) - (rN - rS);
         const T rho_n = rho0 + rnC;
-        // surface tension -dt phi G_iso mu
-        const T pc = sp[ep];
-        const T fstx = -c.dt * pc * (gisox_num<T, MX>(smu, em) * c.gi);
-        const T fsty = -c.dt * pc * (gisoy_num<T, MX>(smu, em) * c.gi);
+        const T pc = pcq[k], fstx = fsx[k], fsty = fsy[k];
         T gx_ = c.gdt[0];
         if (c.fx) gx_ = fmaT(c.dt, c.fx[gy], gx_);
         const T dmx = fmaT(rho_n, gx_, fmaT(-c.ks, sx, fmaT(c.kv, lpx, fmaT(-c.cg, fxx, fstx))));
