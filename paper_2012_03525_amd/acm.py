@@ -356,7 +356,7 @@ class Batch:
     sliced into per-case views."""
 
     def __init__(self, cfgs, states, nsteps, tiles=None, chunk: int = 500, device: str = "cuda:0",
-                 umax_limit: float = 0.3, grab: int = 0, blocks: int = 0, mode: int = 0):
+                 umax_limit: float = 0.3, grab: int = 0, blocks: int = 0, mode: int = 0, forces=None):
         import torch
         self.torch = torch
         n = len(cfgs)
@@ -366,6 +366,7 @@ class Batch:
         self.offsets = np.concatenate([[0], np.cumsum([6 * z for z in sizes])]).astype(np.int64)
         self.arena = torch.empty(int(self.offsets[-1]), dtype=self.dtype, device=device)
         self.views = []
+        self.forces = []  # device copies of the per-row forces, kept alive with the batch
         arr = (BatchCase * n)()
         for i, (c, st) in enumerate(zip(cfgs, states)):
             o, z = int(self.offsets[i]), sizes[i]
@@ -378,6 +379,10 @@ class Batch:
             bc.a = Fields(v[0].data_ptr(), v[1].data_ptr(), v[2].data_ptr(), None, None)
             bc.b = Fields(v[3].data_ptr(), v[4].data_ptr(), v[5].data_ptr(), None, None)
             bc.force_x = None
+            if forces is not None and forces[i] is not None:
+                f = torch.from_numpy(np.ascontiguousarray(forces[i], dtype=np.float64)).to(device, self.dtype)
+                self.forces.append(f)
+                bc.force_x = f.data_ptr()
             bc.nsteps = int(nsteps[i])
             bc.tile = -1 if tiles is None else int(tiles[i])
         self._cases = arr

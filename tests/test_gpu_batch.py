@@ -88,6 +88,34 @@ def test_batch_bitwise_equals_single_runs(acm_mod, mode, grab, blocks, prec):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_batch_with_row_forces_bitwise(acm_mod, mode):
+    """Cases driven by a per-row body force (force_x, added to g[0] on row j)
+    next to an unforced case, both launch modes and every force path (tiles
+    with ragged edges, walls and a 128 x 4 tile whose staged region exceeds
+    the persistent kernel's register set): bitwise equal to single runs with
+    the same force."""
+    specs = [(64, 48, "channel", 5), (40, 33, "tgv", 1), (70, 45, "channel", 4), (32, 32, "tgv", 0)]
+    cfgs = [case_cfg(acm_mod, nx, ny, kind, 0.04) for nx, ny, kind, _ in specs]
+    states = [spec_state(nx, ny, 200 + i) for i, (nx, ny, _, _) in enumerate(specs)]
+    forces = []
+    for i, (nx, ny, kind, _) in enumerate(specs):
+        j = np.arange(ny) + 0.5
+        forces.append(None if i == 3 else (2e-6 if kind == "channel" else 1e-6) * np.sin(np.pi * j / ny + i))
+    b = acm_mod.Batch(cfgs, states, [40] * len(specs), tiles=[s[3] for s in specs], chunk=20, mode=mode,
+                      forces=forces)
+    assert b.run() == 0
+    for i in range(len(specs)):
+        s = acm_mod.Solver(cfgs[i], states[i], force_x=forces[i])
+        s.run(40)
+        ref = s.state()
+        s.close()
+        got = b.state(i)
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), (i, k)
+    b.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 def test_batch_divergence_is_isolated(acm_mod, mode):
     """A linearly unstable case (nu above the viscous bound, allowed
     explicitly) is retired as diverged; the others finish bitwise equal to
