@@ -102,9 +102,10 @@ typedef struct acm_config {
                                default); 0: the whole-row kernel with 4-row
                                bands where it applies (chunk chosen for the
                                CU count), else 13 with 64-plane chunks,
-                               or a smaller shape and chunk when that gives
-                               fewer than two workgroups per CU (FP64 accepts
-                               3, 4, else 32x8); bits 8+ = z chunk / 16 (0:
+                               or a smaller shape and chunk (down to 32x8
+                               with 4-plane chunks) when that gives fewer
+                               than two workgroups per CU (FP64 accepts 3,
+                               4, else 32x8); bits 8+ = z chunk / 16 (0:
                                64 planes).  Results do not depend on the
                                tile. */
     double wet_cos[6];      /* two-phase: cos(contact angle) of each wall face
