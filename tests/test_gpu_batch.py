@@ -171,6 +171,43 @@ def test_batch_sampled_sweep_cases_match_oracle(acm_mod, orc):
     b.close()
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sweep512_first_chunk_sampled_cases_bitwise(acm_mod, mode):
+    """The full 512-case sweep (seeded as in the benchmark, autotuned tiles
+    for its launch mode), one 500-step chunk: twelve cases spread over the
+    sizes and both kinds equal their single runs bit for bit (NaN where a
+    case has diverged), and the step accounting covers every node of every
+    case."""
+    cases = inputs.batch_cases(512, seed=4)
+    cfgs, states = [], []
+    for c in cases:
+        wu = [[0.0] * 3 for _ in range(6)]
+        bc = (0, 0, 0, 0, 0, 0)
+        if c.kind == "cavity":
+            bc = (1, 1, 1, 1, 0, 0)
+            wu[3] = [c.u_ref, 0.0, 0.0]
+        cfgs.append(acm_mod.make_config(2, c.n, c.n, nu=c.nu, precision="f32", bc=bc, wall_u=wu))
+        states.append(c.state)
+    b = acm_mod.Batch(cfgs, states, [c.nsteps for c in cases], chunk=500, mode=mode)
+    b.run(max_chunks=1)
+    ms, lups = b.timing()
+    assert lups == 500 * sum(c.n * c.n for c in cases)
+    order = sorted(range(len(cases)), key=lambda i: (cases[i].n, i))
+    pick = [order[k] for k in np.linspace(0, len(order) - 1, 12).astype(int)]
+    assert {cases[i].kind for i in pick} == {"tgv", "cavity"}
+    for i in pick:
+        assert b.status(i)["steps_done"] == 500
+        got = b.state(i)
+        s = acm_mod.Solver(cfgs[i], states[i])
+        s.run(500)
+        ref = s.state()
+        s.close()
+        for k in ref:
+            # cases that diverge within the chunk hold NaN at the same nodes in both
+            assert np.array_equal(got[k], ref[k], equal_nan=True), (i, cases[i].n, cases[i].kind, k)
+    b.close()
+
+
 def test_autotune_choice_is_valid_and_result_invariant(acm_mod):
     best, ms = acm_mod.autotune(64, 64, "f32", copies=64, steps=40)
     assert 0 <= best < 6 and all(m > 0 for m in ms)
