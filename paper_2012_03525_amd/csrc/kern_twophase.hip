@@ -208,6 +208,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
     __syncthreads();
 
     // ---- mu^n on tile+3
+#pragma unroll
     for (int q = tid; q < S::MXY; q += NT) {
         const int ly = q / MX, lx = q - ly * MX;
         int ex = lx + 1, ey = ly + 1;  // phi-region coordinates
@@ -220,6 +221,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
     __syncthreads();
 
     // ---- phi* on tile+2
+#pragma unroll
     for (int q = tid; q < S::RXY; q += NT) {
         const int ly = q / RX, lx = q - ly * RX;
         int ex = lx, ey = ly;  // flow-region coordinates of the evaluation node
@@ -259,6 +261,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
     __syncthreads();
 
     // ---- mu* on tile+1 (over phi^n) and drho' on tile+1 (over mu^n)
+#pragma unroll
     for (int q = tid; q < S::DXY; q += NT) {
         const int ly = q / DX, lx = q - ly * DX;
         int ex = lx + 1, ey = ly + 1;  // phi*-region coordinates
@@ -268,6 +271,7 @@ __global__ __launch_bounds__(NT) void twophase2d_kernel(Coef<T> c, State<T> in, 
         }
         sms[q] = chem_a<T, RX, AXI>(c, sps, ey * RX + ex, inv_radius<AXI, T>(y0 + ey - 2));
     }
+#pragma unroll
     for (int q = tid; q < S::DXY; q += NT) {
         const int ly = q / DX, lx = q - ly * DX;
         int ex = lx + 1, ey = ly + 1;  // flow-region coordinates
