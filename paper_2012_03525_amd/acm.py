@@ -353,7 +353,9 @@ class Batch:
     """Independent 2D single-phase cases advanced together by the batched
     kernel (mode 0: one workgroup per item; 1: persistent work queue).  All
     states live in one arena tensor (6 fields per case: set a then set b),
-    sliced into per-case views."""
+    sliced into per-case views.  `forces`, if given, holds per case None or
+    the ny values of a row force added to g[0] (kept on the device for the
+    life of the batch)."""
 
     def __init__(self, cfgs, states, nsteps, tiles=None, chunk: int = 500, device: str = "cuda:0",
                  umax_limit: float = 0.3, grab: int = 0, blocks: int = 0, mode: int = 0, forces=None):
