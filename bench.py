@@ -33,7 +33,7 @@ def parse():
                     choices=["tgv3d_256", "tgv2d_64", "drop_shear_1024", "drop_spreading_96", "batch512",
                              "pipe_axisym_4096x2048", "drop_axisym_2048x1024"])
     ap.add_argument("--no-closure", action="store_true",
-                    help="skip the closure step timing and evaluation in the default workload's line")
+                    help="skip the closure, drop-in-shear and batch-sweep objects of the default workload's line")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--batch-mode", type=int, default=0, choices=(0, 1),
                     help="batch512: 0 one workgroup per item, 1 persistent work queue")
@@ -173,7 +173,7 @@ def measured_traffic(name):
     return int(1024 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]))
 
 
-def run_batch(a, copy):
+def batch_sweep(mode: int):
     """The 512-case sweep, one batched launch per step (FP32, autotuned
     tiles, 500-step graph chunks): aggregate MLUPS over the whole job and the
     p50 / p99 case completion times."""
@@ -190,34 +190,65 @@ def run_batch(a, copy):
         cfgs.append(acm.make_config(2, c.n, c.n, nu=c.nu, precision="f32", bc=bc, wall_u=wu))
         states.append(c.state)
     print(f"[bench] batch: {len(cases)} cases, {sum(c.n * c.n for c in cases)} nodes", file=sys.stderr, flush=True)
-    b = acm.Batch(cfgs, states, [c.nsteps for c in cases], chunk=500, mode=a.batch_mode)
+    b = acm.Batch(cfgs, states, [c.nsteps for c in cases], chunk=500, mode=mode)
     b.run()
     ms, lups = b.timing()
     st = [b.status(i) for i in range(len(cases))]
     done = np.array([s["done_ms"] for s in st if s["state"] == acm.BATCH_FINISHED])
     diverged = sum(1 for s in st if s["state"] != acm.BATCH_FINISHED)
     b.close()
-    mlups = lups / (ms * 1e-3) / 1e6
-    gbs = 24 * lups / (ms * 1e-3) / 1e9
+    return {"cases": len(cases), "lattice_updates": int(lups), "wall_ms": round(ms, 2),
+            "mlups": round(lups / (ms * 1e-3) / 1e6, 1), "gbs": round(24 * lups / (ms * 1e-3) / 1e9, 1),
+            "steps": int(max(c.nsteps for c in cases)),
+            "p50_ms": round(float(np.percentile(done, 50)), 2), "p99_ms": round(float(np.percentile(done, 99)), 2),
+            "finished": int(done.size), "diverged": diverged}
+
+
+def run_batch(a, copy):
+    """The 512-case sweep as its own bench line."""
+    r = batch_sweep(a.batch_mode)
     out = {
         "metric": "MLUPS + HBM GB/s vs peak; learned-coarse vs plain-fine time at <=2% L2 err",
-        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": int(max(c.nsteps for c in cases)),
+        "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": r["steps"],
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched sweep: 512 2D cases n in {32..256}, half periodic TGV / half lid-driven "
                                "cavity, Re log-uniform [100, 5000], FP32, one launch per step, 500-step graph chunks",
                    "launch": ["one workgroup per item", "persistent work queue"][a.batch_mode],
-                   "cases": len(cases), "lattice_updates": int(lups), "parallelism": "single GPU"},
-        "wall_ms": round(ms, 2),
-        "case_completion_ms": {"p50": round(float(np.percentile(done, 50)), 2),
-                               "p99": round(float(np.percentile(done, 99)), 2),
-                               "finished": int(done.size), "diverged": diverged},
+                   "cases": r["cases"], "lattice_updates": r["lattice_updates"], "parallelism": "single GPU"},
+        "wall_ms": r["wall_ms"],
+        "case_completion_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"], "finished": r["finished"],
+                               "diverged": r["diverged"]},
         "roofline": {"bound": "hbm", "kernel": ["batch_grid_kernel", "batch_step_kernel"][a.batch_mode],
-                     "achieved": round(gbs, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "achieved": r["gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_lup": 24, "copy_kernel_gbs": copy["gbs"]},
     }
     print(json.dumps(out), flush=True)
+
+
+def drop_shear_timing(steps: int = 1000, warmup: int = 50):
+    """The 2D two-phase drop in shear (1024^2, FP32): time per step of the
+    fused two-phase launch, graph-launched, HIP events on the solver's stream."""
+    import torch
+    from paper_2012_03525_amd import acm
+    cfg, st, meta, bpl, kname = workload("drop_shear_1024", 0, 100)
+    s = acm.Solver(cfg, st)
+    s.run(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.run(steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    d = s.diagnostics()
+    s.close()
+    nodes = cfg.nx * cfg.ny
+    gbs = bpl * nodes / (ms * 1e-3) / 1e9
+    return {"workload": meta["workload"], "kernel": kname, "steps": steps, "us_per_step": round(ms * 1e3, 3),
+            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "gbs_algorithmic": round(gbs, 1),
+            "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4), "nonfinite": d["nonfinite"]}
 
 
 def closure_timing(steps: int = 2000):
@@ -374,6 +405,10 @@ def main():
         out["closure"] = closure_timing()
         print("[bench] closure train + evaluation (10 held-out seeds)...", file=sys.stderr, flush=True)
         out["closure"]["evaluation"] = closure_evaluation()
+        print("[bench] 2D two-phase drop in shear 1024^2...", file=sys.stderr, flush=True)
+        out["drop_shear"] = drop_shear_timing()
+        print("[bench] 512-case batch sweep (one workgroup per item)...", file=sys.stderr, flush=True)
+        out["batch"] = dict(batch_sweep(0), launch="one workgroup per item", bytes_per_lup=24)
     if not a.no_cpu:
         print("[bench] CPU oracle baseline...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.workload, cfg, st, a.cpu_seconds)
