@@ -116,6 +116,29 @@ def test_batch_with_row_forces_bitwise(acm_mod, mode):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_batch_tiny_grids_bitwise(acm_mod, mode):
+    """Grids smaller than every tile (down to the 4 x 4 minimum), periodic,
+    walled and with symmetry planes, one item per case: bitwise equal to
+    single runs; a second batch holding one case alone does the same."""
+    specs = [(4, 4, "tgv", 0), (5, 4, "cavity", 3), (7, 9, "sym", 4), (6, 5, "channel", 1)]
+    cfgs = [case_cfg(acm_mod, nx, ny, kind, 0.04) for nx, ny, kind, _ in specs]
+    states = [spec_state(nx, ny, 300 + i) for i, (nx, ny, _, _) in enumerate(specs)]
+    for sel in (range(len(specs)), [2]):
+        b = acm_mod.Batch([cfgs[i] for i in sel], [states[i] for i in sel], [40] * len(sel),
+                          tiles=[specs[i][3] for i in sel], chunk=20, mode=mode)
+        assert b.run() == 0
+        for k, i in enumerate(sel):
+            s = acm_mod.Solver(cfgs[i], states[i])
+            s.run(40)
+            ref = s.state()
+            s.close()
+            got = b.state(k)
+            for f in ref:
+                assert np.array_equal(got[f], ref[f]), (i, f)
+        b.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 def test_batch_divergence_is_isolated(acm_mod, mode):
     """A linearly unstable case (nu above the viscous bound, allowed
     explicitly) is retired as diverged; the others finish bitwise equal to
